@@ -1,0 +1,333 @@
+"""ctypes front end of the FP64 CPU oracle (test infrastructure only).
+
+Each function names the step of the hot path it computes; the arithmetic
+lives in ``sph_oracle.c``.  Arrays are numpy, float64 unless stated.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+from . import build as _build
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_build.LIB):
+            _build.build()
+        _lib = C.CDLL(_build.LIB)
+        _declare(_lib)
+    return _lib
+
+
+class OGrid(C.Structure):
+    _fields_ = [("o", C.c_double * 3), ("L", C.c_double), ("n", C.c_int32 * 3)]
+
+
+class OParams(C.Structure):
+    _fields_ = [("h", C.c_double), ("rho0", C.c_double), ("c0", C.c_double),
+                ("gamma", C.c_double), ("K", C.c_double), ("G", C.c_double),
+                ("Y0", C.c_double), ("H", C.c_double), ("beta", C.c_double),
+                ("cfl", C.c_double), ("g", C.c_double * 3), ("wlo", C.c_double * 3),
+                ("whi", C.c_double * 3), ("wall_mask", C.c_int32), ("material", C.c_int32)]
+
+
+_dp = C.POINTER(C.c_double)
+_up = C.POINTER(C.c_uint32)
+
+
+class OState(C.Structure):
+    _fields_ = [("n", C.c_int64), ("x", _dp), ("v", _dp), ("m", _dp), ("w", _dp),
+                ("rho", _dp), ("p", _dp), ("c", _dp), ("E", _dp), ("S", _dp), ("ep", _dp),
+                ("id", _up), ("hash", _up)]
+
+
+def _declare(L):
+    vp = C.c_void_p
+    L.or_hash.argtypes = [C.POINTER(OGrid), C.c_int64, vp, vp]
+    L.or_sort_perm.argtypes = [C.c_int64, vp, C.c_uint32, vp]
+    L.or_sort_perm.restype = C.c_int
+    L.or_cell_start.argtypes = [C.c_int64, vp, C.c_uint32, vp]
+    L.or_cell_start.restype = C.c_int
+    L.or_gather.argtypes = [C.POINTER(OState), C.POINTER(OState), vp]
+    L.or_mark.argtypes = [C.POINTER(OGrid), C.c_int64, vp, vp, vp, vp, vp]
+    L.or_kernel_W.argtypes = [C.c_double, C.c_double]
+    L.or_kernel_W.restype = C.c_double
+    L.or_kernel_F.argtypes = [C.c_double, C.c_double]
+    L.or_kernel_F.restype = C.c_double
+    L.or_eos.argtypes = [C.POINTER(OParams), C.c_double, _dp, _dp]
+    L.or_pair.argtypes = [C.POINTER(OParams), vp, vp, vp] + [C.c_double] * 10 + [vp, vp, vp]
+    L.or_pair_grad.argtypes = [C.POINTER(OParams), vp, vp, vp, C.c_double, vp]
+    L.or_interact.argtypes = [C.POINTER(OParams), C.POINTER(OGrid), C.c_int, C.POINTER(OState),
+                              vp, C.c_int64, C.POINTER(OState), vp, C.c_int, vp, vp]
+    L.or_neighbors.argtypes = [C.POINTER(OParams), C.POINTER(OGrid), C.POINTER(OState),
+                               C.POINTER(OState), vp, C.c_int, vp, vp, C.c_int64]
+    L.or_neighbors.restype = C.c_int64
+    L.or_integrate.argtypes = [C.POINTER(OParams), C.c_int, C.POINTER(OState), vp, vp,
+                               C.c_double, vp]
+    L.or_run.argtypes = [C.POINTER(OParams), C.POINTER(OGrid), C.POINTER(OState), C.c_int,
+                         C.c_double, vp, vp, vp]
+    L.or_run.restype = C.c_int
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def grid_struct(grid: dict) -> OGrid:
+    g = OGrid()
+    for d in range(3):
+        g.o[d] = grid["origin"][d]
+        g.n[d] = grid["dims"][d]
+    g.L = grid["cell"]
+    return g
+
+
+def params_struct(p: dict) -> OParams:
+    s = OParams()
+    for k in ("h", "rho0", "c0", "gamma", "K", "G", "Y0", "H", "beta", "cfl"):
+        setattr(s, k, float(p[k]))
+    for d in range(3):
+        s.g[d] = p["gravity"][d]
+        s.wlo[d] = p["wall_lo"][d]
+        s.whi[d] = p["wall_hi"][d]
+    s.wall_mask = int(p["wall_mask"])
+    s.material = int(p["material"])
+    return s
+
+
+def ncells(grid: dict) -> int:
+    d = grid["dims"]
+    return int(d[0]) * int(d[1]) * int(d[2])
+
+
+class State:
+    """Particle state in the oracle's layout (row-major (n,3) positions)."""
+
+    FIELDS = ("x", "v", "m", "w", "rho", "p", "c", "E", "S", "ep", "id", "hash")
+
+    def __init__(self, n: int, solid: bool = False):
+        self.n = n
+        self.x = np.zeros((n, 3))
+        self.v = np.zeros((n, 3))
+        self.m = np.zeros(n)
+        self.w = np.zeros(n)
+        self.rho = np.zeros(n)
+        self.p = np.zeros(n)
+        self.c = np.zeros(n)
+        self.E = np.zeros(n)
+        self.S = np.zeros((n, 6)) if solid else None
+        self.ep = np.zeros(n) if solid else None
+        self.id = np.zeros(n, dtype=np.uint32)
+        self.hash = np.zeros(n, dtype=np.uint32)
+
+    @classmethod
+    def from_workload(cls, wl) -> "State":
+        s = cls(wl.n, wl.S is not None)
+        s.x[:] = wl.x
+        s.v[:] = wl.v
+        s.m[:] = wl.m
+        s.w[:] = wl.omega
+        s.rho[:] = wl.rho
+        s.E[:] = wl.E
+        s.id[:] = wl.id
+        if wl.S is not None:
+            s.S[:] = wl.S
+            s.ep[:] = wl.eps_p
+        return s
+
+    def copy(self) -> "State":
+        o = State(self.n, self.S is not None)
+        for f in self.FIELDS:
+            a = getattr(self, f)
+            if a is not None:
+                getattr(o, f)[...] = a
+        return o
+
+    def struct(self) -> OState:
+        s = OState()
+        s.n = self.n
+        for f in self.FIELDS:
+            a = getattr(self, f)
+            if a is not None:
+                assert a.flags["C_CONTIGUOUS"]
+                setattr(s, f, a.ctypes.data_as(_up if a.dtype == np.uint32 else _dp))
+        return s
+
+    def by_id(self) -> "State":
+        """Copy reordered so that row k holds particle id k."""
+        order = np.argsort(self.id, kind="stable")
+        o = State(self.n, self.S is not None)
+        for f in self.FIELDS:
+            a = getattr(self, f)
+            if a is not None:
+                getattr(o, f)[...] = a[order]
+        return o
+
+
+# ----------------------------------------------------------- per-step calls
+
+def hash_cells(grid: dict, x: np.ndarray) -> np.ndarray:
+    """Bucket hash of every particle (Section I; Section II step a)."""
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    out = np.empty(x.shape[0], dtype=np.uint32)
+    g = grid_struct(grid)
+    lib().or_hash(C.byref(g), x.shape[0], _ptr(x), _ptr(out))
+    return out
+
+
+def sort_perm(key: np.ndarray, nkeys: int) -> np.ndarray:
+    """Stable ascending order of key (Section I radix sort)."""
+    key = np.ascontiguousarray(key, dtype=np.uint32)
+    perm = np.empty(key.shape[0], dtype=np.uint32)
+    if lib().or_sort_perm(key.shape[0], _ptr(key), nkeys, _ptr(perm)) != 0:
+        raise MemoryError
+    return perm
+
+
+def cell_start(sorted_key: np.ndarray, nc: int) -> np.ndarray:
+    sk = np.ascontiguousarray(sorted_key, dtype=np.uint32)
+    start = np.empty(nc + 1, dtype=np.uint32)
+    if lib().or_cell_start(sk.shape[0], _ptr(sk), nc, _ptr(start)) != 0:
+        raise MemoryError
+    return start
+
+
+def gather(s: State, perm: np.ndarray) -> State:
+    o = State(s.n, s.S is not None)
+    a, b = o.struct(), s.struct()
+    lib().or_gather(C.byref(a), C.byref(b), _ptr(np.ascontiguousarray(perm, dtype=np.uint32)))
+    return o
+
+
+def build_cells(grid: dict, s: State):
+    """Hash, stable sort, gather and cell table: returns (sorted state, perm, start)."""
+    h = hash_cells(grid, s.x)
+    s.hash[:] = h
+    perm = sort_perm(h, ncells(grid))
+    o = gather(s, perm)
+    start = cell_start(o.hash, ncells(grid))
+    return o, perm, start
+
+
+def mark_boundary(grid: dict, local_hash: np.ndarray, remote_start: np.ndarray):
+    """Communication hash and MGPU boundary list (Section II, step c)."""
+    n = local_hash.shape[0]
+    lh = np.ascontiguousarray(local_hash, dtype=np.uint32)
+    comm = np.empty(n, dtype=np.uint32)
+    bidx = np.empty(n, dtype=np.uint32)
+    nb = np.zeros(1, dtype=np.uint32)
+    g = grid_struct(grid)
+    lib().or_mark(C.byref(g), n, _ptr(lh), _ptr(np.ascontiguousarray(remote_start, dtype=np.uint32)),
+                  _ptr(comm), _ptr(bidx), _ptr(nb))
+    return comm, bidx[: int(nb[0])].copy()
+
+
+def kernel_W(r: float, h: float) -> float:
+    return lib().or_kernel_W(r, h)
+
+
+def kernel_F(r: float, h: float) -> float:
+    return lib().or_kernel_F(r, h)
+
+
+def eos(params: dict, rho: float):
+    p, c = C.c_double(), C.c_double()
+    P = params_struct(params)
+    lib().or_eos(C.byref(P), rho, C.byref(p), C.byref(c))
+    return p.value, c.value
+
+
+def pair(params: dict, d, vi, vj, wi, wj, rhoi, rhoj, pi, pj, ci, cj, ei, ej, Si=None, Sj=None):
+    """FORCE terms (mdot, mvdot[3], mEdot, wdot) of target i from source j."""
+    P = params_struct(params)
+    d = np.ascontiguousarray(d, dtype=np.float64)
+    vi = np.ascontiguousarray(vi, dtype=np.float64)
+    vj = np.ascontiguousarray(vj, dtype=np.float64)
+    Si = None if Si is None else np.ascontiguousarray(Si, dtype=np.float64)
+    Sj = None if Sj is None else np.ascontiguousarray(Sj, dtype=np.float64)
+    out = np.empty(6)
+    lib().or_pair(C.byref(P), _ptr(d), _ptr(vi), _ptr(vj), wi, wj, rhoi, rhoj, pi, pj, ci, cj,
+                  ei, ej, _ptr(Si), _ptr(Sj), _ptr(out))
+    return out
+
+
+def pair_grad(params: dict, d, vi, vj, wj):
+    P = params_struct(params)
+    out = np.empty(9)
+    lib().or_pair_grad(C.byref(P), _ptr(np.ascontiguousarray(d, dtype=np.float64)),
+                       _ptr(np.ascontiguousarray(vi, dtype=np.float64)),
+                       _ptr(np.ascontiguousarray(vj, dtype=np.float64)), wj, _ptr(out))
+    return out.reshape(3, 3)
+
+
+FORCE, GRADIENT = 0, 1
+MOTION, STRESS, EOS = 0, 1, 2
+
+
+def interact(params: dict, grid: dict, pass_: int, tgt: State, src: State, src_start,
+             self_pass: bool, rates=None, L=None, tidx=None):
+    """Accumulate pair sums into rates (n,6) or L (n,9) (Section II steps e, f)."""
+    P = params_struct(params)
+    g = grid_struct(grid)
+    if pass_ == FORCE and rates is None:
+        rates = np.zeros((tgt.n, 6))
+    if pass_ == GRADIENT and L is None:
+        L = np.zeros((tgt.n, 9))
+    ti = None if tidx is None else np.ascontiguousarray(tidx, dtype=np.uint32)
+    nt = tgt.n if ti is None else ti.shape[0]
+    a, b = tgt.struct(), src.struct()
+    lib().or_interact(C.byref(P), C.byref(g), pass_, C.byref(a), _ptr(ti), nt, C.byref(b),
+                      _ptr(np.ascontiguousarray(src_start, dtype=np.uint32)), int(self_pass),
+                      _ptr(rates), _ptr(L))
+    return rates if pass_ == FORCE else L
+
+
+def neighbors(params: dict, grid: dict, tgt: State, src: State, src_start, self_pass: bool):
+    """Ordered (i, j) pairs visited with r < 2h, in visiting order."""
+    P = params_struct(params)
+    g = grid_struct(grid)
+    a, b = tgt.struct(), src.struct()
+    st = np.ascontiguousarray(src_start, dtype=np.uint32)
+    cnt = lib().or_neighbors(C.byref(P), C.byref(g), C.byref(a), C.byref(b), _ptr(st),
+                             int(self_pass), None, None, 0)
+    pi = np.empty(cnt, dtype=np.uint32)
+    pj = np.empty(cnt, dtype=np.uint32)
+    lib().or_neighbors(C.byref(P), C.byref(g), C.byref(a), C.byref(b), _ptr(st),
+                       int(self_pass), _ptr(pi), _ptr(pj), cnt)
+    return pi, pj
+
+
+def integrate(params: dict, stage: int, s: State, rates=None, L=None, dt: float = 0.0):
+    """Update s in place (Section II step g); returns the 7 diagnostics."""
+    P = params_struct(params)
+    diag = np.zeros(7)
+    a = s.struct()
+    r = None if rates is None else np.ascontiguousarray(rates, dtype=np.float64)
+    l = None if L is None else np.ascontiguousarray(L, dtype=np.float64)
+    lib().or_integrate(C.byref(P), stage, C.byref(a), _ptr(r), _ptr(l), dt, _ptr(diag))
+    return diag
+
+
+def run(params: dict, grid: dict, s: State, nsteps: int, fixed_dt: float = 0.0, dts_in=None):
+    """Whole steps in C; s is updated in place.  Returns (dts used, last diag)."""
+    P = params_struct(params)
+    g = grid_struct(grid)
+    dts = np.zeros(max(nsteps, 1))
+    diag = np.zeros(7)
+    di = None if dts_in is None else np.ascontiguousarray(dts_in, dtype=np.float64)
+    a = s.struct()
+    if lib().or_run(C.byref(P), C.byref(g), C.byref(a), nsteps, fixed_dt, _ptr(di), _ptr(dts),
+                    _ptr(diag)) != 0:
+        raise MemoryError
+    return dts[:nsteps], diag
+
+
+def prime(params: dict, s: State):
+    """EOS stage on the initial state: rho = m / w, p, c; returns diagnostics."""
+    return integrate(params, EOS, s)
