@@ -1,0 +1,244 @@
+/*
+ * libsph: one GPU's share of the particle-decomposition SPH step on MI355X.
+ *
+ * The paper (Section I) finds SPH neighbours by hashing every particle into
+ * cubic buckets of side 2h and radix-sorting by that hash, so a particle's
+ * neighbours lie in its own bucket or the 26 surrounding ones.  Section II
+ * assigns particles to GPUs regardless of position and runs, per iteration:
+ * (a) hash, (b) exchange hashes, (c) communication hash marking the "MGPU
+ * boundary" particles that have another GPU's particles in their bucket or
+ * the surrounding buckets, (d) send those particles' data, (e) local
+ * interactions, (f) interactions of local particles with the received
+ * boundary particles, (g) integration.  This library is the per-GPU compute
+ * of (a), (c), the packing for (d), (e), (f) and (g), plus a hand-written
+ * adjoint of (e) and (g).
+ *
+ * Conventions shared by every call
+ *   - Every pointer inside the structs and every *_dev argument is DEVICE
+ *     memory owned by the caller; the structs themselves are host memory and
+ *     are read before the call returns.  The library allocates nothing; the
+ *     only temporary memory is the caller-provided workspace.
+ *   - Calls only enqueue work on `stream` (a hipStream_t; NULL = the default
+ *     stream).  They never synchronise and never read device memory on the
+ *     host, so device-resident counts (n_boundary, dt) stay on the device.
+ *   - Return SPH_OK or a negative sph_status.  Arguments are validated on the
+ *     host before anything is enqueued; on an error nothing is enqueued and
+ *     sph_last_error() describes it.  A failed kernel launch returns
+ *     SPH_ERR_HIP.  n == 0 is a valid no-op.
+ *   - Precision: SPH_FP64 keeps every real field in double.  SPH_FP32_SPLIT
+ *     keeps positions x and total energy E in double and every other real
+ *     field in float; its pair loops run in float on positions held as bucket
+ *     index plus a float offset from the bucket corner (so x_j - x_i keeps
+ *     its relative precision), and pair sums are compensated (hi, lo) pairs.
+ *     Fields typed `void*` below are double in SPH_FP64 and float in
+ *     SPH_FP32_SPLIT.
+ */
+#ifndef SPH_H
+#define SPH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum sph_status {
+    SPH_OK = 0,
+    SPH_ERR_ARG = -1,          /* invalid argument; nothing enqueued            */
+    SPH_ERR_WORKSPACE = -2,    /* workspace missing or smaller than required    */
+    SPH_ERR_HIP = -3,          /* a HIP launch or runtime call failed           */
+    SPH_ERR_UNSUPPORTED = -4   /* combination not provided (e.g. remote adjoint) */
+};
+
+enum sph_precision { SPH_FP64 = 0, SPH_FP32_SPLIT = 1 };
+enum sph_material { SPH_FLUID_TAIT = 0, SPH_SOLID_J2 = 1 };
+enum sph_pass { SPH_PASS_FORCE = 0, SPH_PASS_GRADIENT = 1 };
+enum sph_stage { SPH_STAGE_MOTION = 0, SPH_STAGE_STRESS = 1, SPH_STAGE_EOS = 2 };
+
+/* Bucket grid (Section I).  Buckets are cubes of side `cell` >= 2h; bucket
+ * (cx, cy, cz) covers origin + [c, c+1) * cell and has hash
+ * cx + dims[0] * (cy + dims[1] * cz).  Particles outside the grid are
+ * clamped into the edge buckets, which keeps the neighbour search complete.
+ * dims[0] * dims[1] * dims[2] must be below 2^32 - 1; its value G = ncells is
+ * the "garbage collector" communication hash (Section II). */
+typedef struct sph_grid {
+    double origin[3];
+    double cell;
+    int32_t dims[3];
+    int32_t reserved;
+} sph_grid;
+
+/* Physical constants.  Smoothing length h is one value for all particles
+ * (Section II: equal particle counts balance the work only when h is
+ * constant).  Tait fluid: p = rho0 c0^2 / gamma ((rho / rho0)^gamma - 1),
+ * c = c0 (rho / rho0)^((gamma - 1) / 2).  J2 solid: p = K (rho / rho0 - 1),
+ * c = sqrt((K + 4G/3) / rho0), yield Y0 + H eps_p.  beta scales the acoustic
+ * Riemann solver's dissipation (1 = the linearised Riemann solution).  Walls:
+ * bit 2d of wall_mask reflects at wall_lo[d], bit 2d+1 at wall_hi[d]. */
+typedef struct sph_params {
+    double h, rho0, c0, gamma, K, G, Y0, H, beta, cfl;
+    double gravity[3], wall_lo[3], wall_hi[3];
+    uint32_t wall_mask;
+    int32_t material;      /* sph_material  */
+    int32_t prec;          /* sph_precision */
+    int32_t reserved;
+} sph_params;
+
+/* One particle array in structure-of-arrays form, n entries per field.
+ * x: positions (double).  off: float offsets from the bucket corner, written
+ * by sph_build_cells in SPH_FP32_SPLIT (NULL in SPH_FP64).  hash: bucket
+ * hash, written by sph_build_cells.  id: caller's particle identity, carried
+ * through every reorder.  v, m, omega (volume), rho, p, c, e (specific
+ * internal energy): real fields.  E: specific total energy (double).  S[6]
+ * (xx yy zz xy xz yz) and eps_p: deviatoric stress and equivalent plastic
+ * strain, SPH_SOLID_J2 only (NULL for fluids). */
+typedef struct sph_particles {
+    uint32_t n;
+    int32_t prec;          /* sph_precision of the real fields */
+    double *x[3];
+    float *off[3];
+    uint32_t *hash;
+    uint32_t *id;
+    void *v[3];
+    void *m, *omega, *rho, *p, *c, *e;
+    double *E;
+    void *S[6];
+    void *eps_p;
+} sph_particles;
+
+/* Bucket table: start[c] = number of particles (in hash order) whose hash is
+ * below c, for c = 0..ncells, so bucket c holds [start[c], start[c+1]). */
+typedef struct sph_cells {
+    uint32_t *start;       /* ncells + 1 entries */
+    uint32_t ncells;
+    uint32_t reserved;
+} sph_cells;
+
+/* Pair-sum outputs, indexed like the target array.  hi[k]: rates of mass,
+ * momentum x, y, z, total energy and volume (FORCE pass); L: velocity
+ * gradient L_ab = dv_a / dx_b, row-major (GRADIENT pass).  lo / Llo hold the
+ * compensation terms in SPH_FP32_SPLIT (the rate is hi + lo) and are NULL in
+ * SPH_FP64. */
+typedef struct sph_rates {
+    void *hi[6];
+    void *lo[6];
+    void *Lhi[9];
+    void *Llo[9];
+} sph_rates;
+
+/* Adjoint (cotangent) of a particle state, same precision as the form:
+ * x, v, m, omega, E are the state variables of one step; rho, p, c, e are the
+ * cotangents of the derived fields that the pair terms read. */
+typedef struct sph_adjoint {
+    void *x[3];
+    void *v[3];
+    void *m, *omega, *E;
+    void *rho, *p, *c, *e;
+} sph_adjoint;
+
+/* Library version string (static storage). */
+const char *sph_version(void);
+
+/* Description of the last error on the calling thread (static per thread). */
+const char *sph_last_error(void);
+
+/* Bytes of workspace the calls below need for up to n_max particles on
+ * `grid`.  One workspace may be reused by consecutive calls on one stream. */
+size_t sph_workspace_size(const sph_grid *grid, uint32_t n_max);
+
+/* Steps (a) and the Section I bucket sort.  Hashes every particle of `in`
+ * into `grid`, stable-radix-sorts by hash (ties keep the order of `in`),
+ * writes every field present in `in` to `out` in sorted order (plus out->hash
+ * and, in SPH_FP32_SPLIT, out->off), perm_out[k] = index in `in` of the
+ * particle now at k, and the bucket table.  in and out must not overlap and
+ * must have the same n, prec and non-NULL fields.  cells.ncells must equal
+ * the grid's bucket count.  Errors: SPH_ERR_ARG (NULL field mismatch, grid
+ * too large, cell <= 0), SPH_ERR_WORKSPACE. */
+int sph_build_cells(const sph_grid *grid, const sph_particles *in, sph_particles *out,
+                    uint32_t *perm_out, sph_cells cells, void *ws, size_t ws_bytes, void *stream);
+
+/* Step (c).  For the hash-sorted `local` array and the bucket table of the
+ * separately stored remote particles (other GPUs' particles on the same grid),
+ * comm_hash_out[i] = local->hash[i] if a remote particle lies in i's bucket or
+ * a surrounding bucket, else G = ncells.  Because `local` is already in hash
+ * order, the stable sort by communication hash that isolates the boundary
+ * particles reduces to a stable compaction: boundary_idx_out receives the
+ * flagged indices in ascending order (at most boundary_cap of them) and
+ * *n_boundary_dev the true count, which may exceed boundary_cap (the caller
+ * checks after synchronising).  Errors: SPH_ERR_ARG, SPH_ERR_WORKSPACE. */
+int sph_mark_boundary(const sph_grid *grid, const sph_particles *local, sph_cells remote_cells,
+                      uint32_t *comm_hash_out, uint32_t *boundary_idx_out, uint32_t boundary_cap,
+                      uint32_t *n_boundary_dev, void *ws, size_t ws_bytes, void *stream);
+
+/* Packing for step (d): payload[k] = local[boundary_idx[k]] for
+ * k < min(*n_boundary_dev, payload->n), every field present in payload
+ * (payload->n is its capacity; its fields must be a subset of local's).
+ * Errors: SPH_ERR_ARG. */
+int sph_pack_boundary(const sph_particles *local, const uint32_t *boundary_idx,
+                      const uint32_t *n_boundary_dev, sph_particles *payload, void *stream);
+
+/* Steps (e) and (f).  For every target i (all of `targets` when target_idx is
+ * NULL, else target_idx[k] for k < *n_targets_dev, at most targets->n), sums
+ * the pair terms over sources j with |x_j - x_i| < 2h found through the
+ * sources' bucket table.  When sources and targets are the same array
+ * (local-local pass, step e) j == i is skipped.  pass = SPH_PASS_FORCE: rates
+ * of mass, momentum, energy and volume from the acoustic Riemann solver
+ * (solids: Cauchy stress -p I + S); SPH_PASS_GRADIENT: velocity gradient L.
+ * zero_first = 1 overwrites the rate entries of the targets, 0 adds to them
+ * (the local-remote pass, step f, continues the compensated sum of step e).
+ * Summation over j runs in ascending source index.  Both arrays must be
+ * hash-sorted on `grid`.  Errors: SPH_ERR_ARG (precision or material
+ * mismatch, missing field). */
+int sph_interact(const sph_params *params, const sph_grid *grid, int pass,
+                 const sph_particles *targets, const uint32_t *target_idx,
+                 const uint32_t *n_targets_dev, const sph_particles *sources, sph_cells source_cells,
+                 int zero_first, const sph_rates *rates, void *stream);
+
+/* Step (g).  stage = SPH_STAGE_MOTION: symplectic Euler update of mass,
+ * momentum, volume, energy and position with gravity and reflective walls,
+ * then the EOS (rho = m / omega, p, c, e).  SPH_STAGE_STRESS (solids): Jaumann
+ * rate of S from L, J2 radial return with linear hardening.  SPH_STAGE_EOS:
+ * the EOS alone (priming the initial state).  dt_dev: one double on the
+ * device.  diag_dev (7 doubles, may be NULL for SPH_STAGE_STRESS): [0] next dt
+ * = cfl h / max(c + |v|), [1] total mass, [2..4] total momentum, [5] total
+ * energy sum m E, [6] kinetic energy; sums are deterministic.  Errors:
+ * SPH_ERR_ARG, SPH_ERR_WORKSPACE. */
+int sph_integrate(const sph_params *params, int stage, sph_particles *p, const sph_rates *rates,
+                  const double *dt_dev, double *diag_dev, void *ws, size_t ws_bytes, void *stream);
+
+/* Adjoint of the local-local FORCE pass (step e) of a fluid.  With rates_bar
+ * the cotangents of the rates (hi only), accumulates into `bar` the
+ * cotangents of x, v, omega, rho, p, c and e of every particle of the
+ * hash-sorted array p.  Uses the pair terms' exact (anti)symmetry so each
+ * particle gathers from its neighbours without atomics.  Errors:
+ * SPH_ERR_ARG, SPH_ERR_UNSUPPORTED (solids). */
+int sph_interact_adjoint(const sph_params *params, const sph_grid *grid, const sph_particles *p,
+                         sph_cells cells, const sph_rates *rates_bar, const sph_adjoint *bar,
+                         void *stream);
+
+/* Adjoint of step (g) for a fluid.  stage = SPH_STAGE_MOTION: p is the state
+ * BEFORE the update (hash-sorted), rates its FORCE rates; on entry bar holds
+ * the cotangent of the state after the update (x, v, m, omega, E); on return
+ * bar holds the direct cotangent of the state before it and rates_bar (hi) the
+ * cotangents of the rates.  SPH_STAGE_EOS: folds the cotangents of rho, p, c
+ * and e into m, omega, v, E (rho = m / omega, p and c from the Tait EOS,
+ * e = E - |v|^2 / 2), clears them, and adds d/dc0 to param_bar_dev[0]
+ * (deterministic sum).  Errors: SPH_ERR_ARG, SPH_ERR_WORKSPACE,
+ * SPH_ERR_UNSUPPORTED (walls, gravity or solids). */
+int sph_integrate_adjoint(const sph_params *params, int stage, const sph_particles *p,
+                          const sph_rates *rates, const double *dt_dev, const sph_adjoint *bar,
+                          const sph_rates *rates_bar, double *param_bar_dev, void *ws,
+                          size_t ws_bytes, void *stream);
+
+/* Adjoint of the reorder in sph_build_cells: out[perm[k]] = in[k] for every
+ * non-NULL field of the state cotangent (x, v, m, omega, E), n entries.
+ * Errors: SPH_ERR_ARG. */
+int sph_permute_adjoint(int prec, uint32_t n, const uint32_t *perm, const sph_adjoint *in,
+                        const sph_adjoint *out, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SPH_H */

@@ -65,6 +65,7 @@ def _declare(L):
     L.or_pair_grad.argtypes = [C.POINTER(OParams), vp, vp, vp, C.c_double, vp]
     L.or_interact.argtypes = [C.POINTER(OParams), C.POINTER(OGrid), C.c_int, C.POINTER(OState),
                               vp, C.c_int64, C.POINTER(OState), vp, C.c_int, vp, vp]
+    L.or_interact_abs.argtypes = L.or_interact.argtypes
     L.or_neighbors.argtypes = [C.POINTER(OParams), C.POINTER(OGrid), C.POINTER(OState),
                                C.POINTER(OState), vp, C.c_int, vp, vp, C.c_int64]
     L.or_neighbors.restype = C.c_int64
@@ -286,6 +287,21 @@ def interact(params: dict, grid: dict, pass_: int, tgt: State, src: State, src_s
                       _ptr(np.ascontiguousarray(src_start, dtype=np.uint32)), int(self_pass),
                       _ptr(rates), _ptr(L))
     return rates if pass_ == FORCE else L
+
+
+def interact_abs(params: dict, grid: dict, pass_: int, tgt: State, src: State, src_start,
+                 self_pass: bool, tidx=None):
+    """Per-target sums of |pair term| (the round-off scale of each rate)."""
+    P = params_struct(params)
+    g = grid_struct(grid)
+    out = np.zeros((tgt.n, 6 if pass_ == FORCE else 9))
+    ti = None if tidx is None else np.ascontiguousarray(tidx, dtype=np.uint32)
+    nt = tgt.n if ti is None else ti.shape[0]
+    a, b = tgt.struct(), src.struct()
+    lib().or_interact_abs(C.byref(P), C.byref(g), pass_, C.byref(a), _ptr(ti), nt, C.byref(b),
+                          _ptr(np.ascontiguousarray(src_start, dtype=np.uint32)), int(self_pass),
+                          _ptr(out) if pass_ == FORCE else None, _ptr(out) if pass_ == GRADIENT else None)
+    return out
 
 
 def neighbors(params: dict, grid: dict, tgt: State, src: State, src_start, self_pass: bool):

@@ -303,9 +303,9 @@ void or_pair_grad(const op_t *P, const double d[3], const double vi[3], const do
  * cell table sstart.  self != 0: sources are the targets, j == i is skipped.
  * pass 0 = FORCE, 1 = GRADIENT.
  */
-void or_interact(const op_t *P, const og_t *g, int pass, const os_t *tg, const uint32_t *tidx,
-                 int64_t nt, const os_t *sr, const uint32_t *sstart, int self, double *rates,
-                 double *L)
+static void interact_impl(const op_t *P, const og_t *g, int pass, const os_t *tg,
+                          const uint32_t *tidx, int64_t nt, const os_t *sr, const uint32_t *sstart,
+                          int self, double *rates, double *L, int absval)
 {
     double R = 2.0 * P->h;
     double R2 = R * R;
@@ -342,11 +342,11 @@ void or_interact(const op_t *P, const og_t *g, int pass, const os_t *tg, const u
                             or_pair(P, d, vi, vj, tg->w[i], sr->w[j], tg->rho[i], sr->rho[j], tg->p[i],
                                     sr->p[j], tg->c[i], sr->c[j], ei, ej,
                                     solid ? tg->S + 6 * i : NULL, solid ? sr->S + 6 * (int64_t)j : NULL, o);
-                            for (int k = 0; k < 6; ++k) acc[k] += o[k];
+                            for (int k = 0; k < 6; ++k) acc[k] += absval ? fabs(o[k]) : o[k];
                         } else {
                             double o[9];
                             or_pair_grad(P, d, vi, vj, sr->w[j], o);
-                            for (int k = 0; k < 9; ++k) acc[k] += o[k];
+                            for (int k = 0; k < 9; ++k) acc[k] += absval ? fabs(o[k]) : o[k];
                         }
                     }
                 }
@@ -355,6 +355,22 @@ void or_interact(const op_t *P, const og_t *g, int pass, const os_t *tg, const u
         else
             for (int a = 0; a < 9; ++a) L[9 * i + a] = acc[a];
     }
+}
+
+void or_interact(const op_t *P, const og_t *g, int pass, const os_t *tg, const uint32_t *tidx,
+                 int64_t nt, const os_t *sr, const uint32_t *sstart, int self, double *rates,
+                 double *L)
+{
+    interact_impl(P, g, pass, tg, tidx, nt, sr, sstart, self, rates, L, 0);
+}
+
+/* Same sums of |term| per component: the scale against which round-off in a
+ * pair sum is judged. */
+void or_interact_abs(const op_t *P, const og_t *g, int pass, const os_t *tg, const uint32_t *tidx,
+                     int64_t nt, const os_t *sr, const uint32_t *sstart, int self, double *rates,
+                     double *L)
+{
+    interact_impl(P, g, pass, tg, tidx, nt, sr, sstart, self, rates, L, 1);
 }
 
 /* Every ordered pair (i, j) the FORCE pass visits with r < 2h; returns the

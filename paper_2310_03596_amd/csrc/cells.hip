@@ -1,0 +1,390 @@
+// Bucket hashing, stable radix sort, reorder, bucket table (Section I and
+// step a of Section II), communication hash and boundary compaction (step c)
+// and the boundary payload packing for step d.
+//
+// The sort is a least-significant-digit radix sort with 8-bit digits over a
+// (hash, index) pair.  Each pass: (1) per-tile digit histograms in LDS,
+// (2) one workgroup per digit scans that digit's counts over tiles,
+// (3) each tile ranks its keys stably with wavefront ballots (8 ballots give
+// every lane the mask of lanes holding the same digit; popcount of the lanes
+// below gives the rank inside the wavefront) and scatters.
+#include "common.hpp"
+
+namespace sph {
+
+namespace {
+
+__device__ inline int cell_coord(double x, double o, double L, int n)
+{
+    double t = floor((x - o) / L);
+    if (!(t >= 0.0)) return 0;
+    if (t > (double)(n - 1)) return n - 1;
+    return (int)t;
+}
+
+__global__ __launch_bounds__(kBlock) void k_hash(Grid g, uint32_t n, const double *__restrict__ x0,
+                                                 const double *__restrict__ x1,
+                                                 const double *__restrict__ x2, uint32_t *keys,
+                                                 uint32_t *vals)
+{
+    uint32_t i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    int cx = cell_coord(x0[i], g.o[0], g.L, g.nx);
+    int cy = cell_coord(x1[i], g.o[1], g.L, g.ny);
+    int cz = cell_coord(x2[i], g.o[2], g.L, g.nz);
+    keys[i] = (uint32_t)cx + (uint32_t)g.nx * ((uint32_t)cy + (uint32_t)g.ny * (uint32_t)cz);
+    vals[i] = i;
+}
+
+__device__ inline uint32_t wave_incl_scan(uint32_t v)
+{
+    int lane = threadIdx.x & (kWave - 1);
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+        uint32_t t = __shfl_up(v, off, kWave);
+        if (lane >= off) v += t;
+    }
+    return v;
+}
+
+// Exclusive scan over the 256 threads of a block; every thread gets `total`.
+__device__ inline uint32_t block_excl_scan(uint32_t v, uint32_t &total)
+{
+    __shared__ uint32_t wsum[kBlock / kWave];
+    int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    uint32_t inc = wave_incl_scan(v);
+    if (lane == kWave - 1) wsum[wave] = inc;
+    __syncthreads();
+    uint32_t before = 0, tot = 0;
+#pragma unroll
+    for (int w = 0; w < kBlock / kWave; ++w) {
+        uint32_t s = wsum[w];
+        before += (w < wave) ? s : 0u;
+        tot += s;
+    }
+    __syncthreads();
+    total = tot;
+    return before + inc - v;
+}
+
+__global__ __launch_bounds__(kBlock) void k_upsweep(const uint32_t *__restrict__ keys, uint32_t n, int shift,
+                                                    uint32_t *__restrict__ hist, uint32_t tiles)
+{
+    __shared__ uint32_t h[kRadixBins];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    uint32_t base = blockIdx.x * kSortTile;
+#pragma unroll
+    for (int it = 0; it < kSortItems; ++it) {
+        uint32_t e = base + it * kBlock + threadIdx.x;
+        if (e < n) atomicAdd(&h[(keys[e] >> shift) & (kRadixBins - 1)], 1u);
+    }
+    __syncthreads();
+    hist[(size_t)threadIdx.x * tiles + blockIdx.x] = h[threadIdx.x];
+}
+
+// One workgroup per digit: exclusive scan of that digit's tile counts.
+__global__ __launch_bounds__(kBlock) void k_scan_digit(uint32_t *__restrict__ hist, uint32_t tiles,
+                                                       uint32_t *__restrict__ totals)
+{
+    uint32_t *row = hist + (size_t)blockIdx.x * tiles;
+    uint32_t run = 0;
+    for (uint32_t b0 = 0; b0 < tiles; b0 += kBlock) {
+        uint32_t b = b0 + threadIdx.x;
+        uint32_t v = b < tiles ? row[b] : 0u;
+        uint32_t tot;
+        uint32_t ex = block_excl_scan(v, tot);
+        if (b < tiles) row[b] = run + ex;
+        run += tot;
+    }
+    if (threadIdx.x == 0) totals[blockIdx.x] = run;
+}
+
+__global__ __launch_bounds__(kBlock) void k_downsweep(const uint32_t *__restrict__ kin,
+                                                      const uint32_t *__restrict__ vin,
+                                                      uint32_t *__restrict__ kout,
+                                                      uint32_t *__restrict__ vout, uint32_t n, int shift,
+                                                      const uint32_t *__restrict__ hist, uint32_t tiles,
+                                                      const uint32_t *__restrict__ totals)
+{
+    constexpr int NW = kBlock / kWave;
+    __shared__ uint32_t dbase[kRadixBins];
+    __shared__ uint32_t run[kRadixBins];
+    __shared__ uint32_t cnt[NW][kRadixBins];
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+    uint32_t tot;
+    uint32_t ex = block_excl_scan(totals[tid], tot);
+    dbase[tid] = ex + hist[(size_t)tid * tiles + blockIdx.x];
+    run[tid] = 0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) cnt[w][tid] = 0;
+    __syncthreads();
+    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    const uint32_t base = blockIdx.x * kSortTile;
+    for (int it = 0; it < kSortItems; ++it) {
+        uint32_t e = base + it * kBlock + tid;
+        bool valid = e < n;
+        uint32_t key = valid ? kin[e] : 0u;
+        uint32_t val = valid ? vin[e] : 0u;
+        uint32_t d = (key >> shift) & (kRadixBins - 1);
+        uint64_t mask = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < kRadixBits; ++b) {
+            bool bit = (d >> b) & 1u;
+            uint64_t bm = __ballot(bit);
+            mask &= bit ? bm : ~bm;
+        }
+        uint32_t rank = (uint32_t)__popcll(mask & below);
+        bool leader = valid && ((mask >> lane) == 1ull);
+        if (leader) cnt[wave][d] = (uint32_t)__popcll(mask);
+        __syncthreads();
+        if (valid) {
+            uint32_t pre = run[d];
+            for (int w = 0; w < wave; ++w) pre += cnt[w][d];
+            uint32_t pos = dbase[d] + pre + rank;
+            kout[pos] = key;
+            vout[pos] = val;
+        }
+        __syncthreads();
+        uint32_t add = 0;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+            add += cnt[w][tid];
+            cnt[w][tid] = 0;
+        }
+        run[tid] += add;
+        __syncthreads();
+    }
+}
+
+template <typename real>
+__global__ __launch_bounds__(kBlock) void k_gather(Grid g, PV<real> in, PV<real> out,
+                                                   const uint32_t *__restrict__ keys,
+                                                   const uint32_t *__restrict__ vals,
+                                                   uint32_t *__restrict__ perm, int split)
+{
+    uint32_t k = blockIdx.x * kBlock + threadIdx.x;
+    if (k >= in.n) return;
+    uint32_t s = vals[k];
+    uint32_t h = keys[k];
+    perm[k] = s;
+    out.hash[k] = h;
+    out.id[k] = in.id[s];
+    double x[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        x[d] = in.x[d][s];
+        out.x[d][k] = x[d];
+        out.v[d][k] = in.v[d][s];
+    }
+    out.m[k] = in.m[s];
+    out.w[k] = in.w[s];
+    out.rho[k] = in.rho[s];
+    out.p[k] = in.p[s];
+    out.c[k] = in.c[s];
+    out.e[k] = in.e[s];
+    out.E[k] = in.E[s];
+    if (in.S[0]) {
+#pragma unroll
+        for (int q = 0; q < 6; ++q) out.S[q][k] = in.S[q][s];
+        out.ep[k] = in.ep[s];
+    }
+    if (split) {
+        uint32_t cx = h % (uint32_t)g.nx;
+        uint32_t cy = (h / (uint32_t)g.nx) % (uint32_t)g.ny;
+        uint32_t cz = h / ((uint32_t)g.nx * (uint32_t)g.ny);
+        out.off[0][k] = (float)((x[0] - g.o[0]) - (double)cx * g.L);
+        out.off[1][k] = (float)((x[1] - g.o[1]) - (double)cy * g.L);
+        out.off[2][k] = (float)((x[2] - g.o[2]) - (double)cz * g.L);
+    }
+}
+
+// start[c] = lower bound of c in the sorted keys, c = 0..ncells.
+__global__ __launch_bounds__(kBlock) void k_cell_start(const uint32_t *__restrict__ keys, uint32_t n,
+                                                       uint32_t ncells, uint32_t *__restrict__ start)
+{
+    uint32_t c = blockIdx.x * kBlock + threadIdx.x;
+    if (c > ncells) return;
+    uint32_t lo = 0, hi = n;
+    while (lo < hi) {
+        uint32_t mid = lo + ((hi - lo) >> 1);
+        if (keys[mid] < c)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    start[c] = lo;
+}
+
+// ------------------------------------------------------------ step c: mark
+
+__global__ __launch_bounds__(kBlock) void k_mark(Grid g, uint32_t n, const uint32_t *__restrict__ hash,
+                                                 const uint32_t *__restrict__ rstart,
+                                                 uint32_t *__restrict__ comm, uint32_t *__restrict__ counts)
+{
+    __shared__ uint32_t wc[kBlock / kWave];
+    uint32_t i = blockIdx.x * kBlock + threadIdx.x;
+    bool flag = false;
+    if (i < n) {
+        uint32_t h = hash[i];
+        int cx = (int)(h % (uint32_t)g.nx);
+        int cy = (int)((h / (uint32_t)g.nx) % (uint32_t)g.ny);
+        int cz = (int)(h / ((uint32_t)g.nx * (uint32_t)g.ny));
+        int x0 = cx > 0 ? cx - 1 : 0, x1 = cx + 1 < g.nx ? cx + 1 : g.nx - 1;
+        for (int dz = -1; dz <= 1 && !flag; ++dz) {
+            int z = cz + dz;
+            if (z < 0 || z >= g.nz) continue;
+            for (int dy = -1; dy <= 1; ++dy) {
+                int y = cy + dy;
+                if (y < 0 || y >= g.ny) continue;
+                uint32_t row = (uint32_t)g.nx * ((uint32_t)y + (uint32_t)g.ny * (uint32_t)z);
+                // a row of up to three adjacent buckets is occupied iff its range is non-empty
+                if (rstart[row + x1 + 1] > rstart[row + x0]) {
+                    flag = true;
+                    break;
+                }
+            }
+        }
+        comm[i] = flag ? h : g.ncells;
+    }
+    uint64_t m = __ballot(flag);
+    if ((threadIdx.x & (kWave - 1)) == 0) wc[threadIdx.x / kWave] = (uint32_t)__popcll(m);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t t = 0;
+        for (int w = 0; w < kBlock / kWave; ++w) t += wc[w];
+        counts[blockIdx.x] = t;
+    }
+}
+
+// Single workgroup: exclusive scan of block counts, total to *nb.
+__global__ __launch_bounds__(kBlock) void k_scan_counts(uint32_t *__restrict__ counts, uint32_t nblocks,
+                                                        uint32_t *__restrict__ nb)
+{
+    uint32_t run = 0;
+    for (uint32_t b0 = 0; b0 < nblocks; b0 += kBlock) {
+        uint32_t b = b0 + threadIdx.x;
+        uint32_t v = b < nblocks ? counts[b] : 0u;
+        uint32_t tot;
+        uint32_t ex = block_excl_scan(v, tot);
+        if (b < nblocks) counts[b] = run + ex;
+        run += tot;
+    }
+    if (threadIdx.x == 0) *nb = run;
+}
+
+__global__ __launch_bounds__(kBlock) void k_compact(uint32_t n, uint32_t G, const uint32_t *__restrict__ comm,
+                                                    const uint32_t *__restrict__ counts,
+                                                    uint32_t *__restrict__ bidx, uint32_t cap)
+{
+    __shared__ uint32_t wc[kBlock / kWave];
+    uint32_t i = blockIdx.x * kBlock + threadIdx.x;
+    int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    bool flag = i < n && comm[i] != G;
+    uint64_t m = __ballot(flag);
+    if (lane == 0) wc[wave] = (uint32_t)__popcll(m);
+    __syncthreads();
+    uint32_t pre = counts[blockIdx.x];
+    for (int w = 0; w < wave; ++w) pre += wc[w];
+    uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    uint32_t k = pre + (uint32_t)__popcll(m & below);
+    if (flag && k < cap) bidx[k] = i;
+}
+
+template <typename real>
+__global__ __launch_bounds__(kBlock) void k_pack(PV<real> in, const uint32_t *__restrict__ bidx,
+                                                 const uint32_t *__restrict__ nb, PV<real> out)
+{
+    uint32_t k = blockIdx.x * kBlock + threadIdx.x;
+    uint32_t cnt = *nb;
+    if (k >= out.n || k >= cnt) return;
+    uint32_t s = bidx[k];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        if (out.x[d]) out.x[d][k] = in.x[d][s];
+        if (out.off[d]) out.off[d][k] = in.off[d][s];
+        if (out.v[d]) out.v[d][k] = in.v[d][s];
+    }
+    if (out.hash) out.hash[k] = in.hash[s];
+    if (out.id) out.id[k] = in.id[s];
+    if (out.m) out.m[k] = in.m[s];
+    if (out.w) out.w[k] = in.w[s];
+    if (out.rho) out.rho[k] = in.rho[s];
+    if (out.p) out.p[k] = in.p[s];
+    if (out.c) out.c[k] = in.c[s];
+    if (out.e) out.e[k] = in.e[s];
+    if (out.E) out.E[k] = in.E[s];
+#pragma unroll
+    for (int q = 0; q < 6; ++q)
+        if (out.S[q]) out.S[q][k] = in.S[q][s];
+    if (out.ep) out.ep[k] = in.ep[s];
+}
+
+int key_bits(uint32_t ncells)
+{
+    int b = 0;
+    while (b < 32 && (uint64_t(1) << b) < ncells) ++b;
+    return b;
+}
+
+}  // namespace
+
+hipError_t launch_build_cells(const Grid &g, int prec, const sph_particles &in, const sph_particles &out,
+                              uint32_t *perm, uint32_t *start, const Workspace &ws, hipStream_t s)
+{
+    uint32_t n = in.n;
+    uint32_t blocks = div_up(n, kBlock);
+    if (n > 0) {
+        k_hash<<<blocks, kBlock, 0, s>>>(g, n, in.x[0], in.x[1], in.x[2], ws.keys[0], ws.vals[0]);
+        int bits = key_bits(g.ncells);
+        int passes = (bits + kRadixBits - 1) / kRadixBits;
+        if (passes < 1) passes = 1;
+        uint32_t tiles = div_up(n, kSortTile);
+        int cur = 0;
+        for (int ps = 0; ps < passes; ++ps) {
+            int shift = ps * kRadixBits;
+            k_upsweep<<<tiles, kBlock, 0, s>>>(ws.keys[cur], n, shift, ws.hist, tiles);
+            k_scan_digit<<<kRadixBins, kBlock, 0, s>>>(ws.hist, tiles, ws.totals);
+            k_downsweep<<<tiles, kBlock, 0, s>>>(ws.keys[cur], ws.vals[cur], ws.keys[cur ^ 1],
+                                                 ws.vals[cur ^ 1], n, shift, ws.hist, tiles, ws.totals);
+            cur ^= 1;
+        }
+        if (prec == SPH_FP64)
+            k_gather<double><<<blocks, kBlock, 0, s>>>(g, view<double>(in), view<double>(out), ws.keys[cur],
+                                                       ws.vals[cur], perm, 0);
+        else
+            k_gather<float><<<blocks, kBlock, 0, s>>>(g, view<float>(in), view<float>(out), ws.keys[cur],
+                                                      ws.vals[cur], perm, 1);
+        k_cell_start<<<div_up((uint64_t)g.ncells + 1, kBlock), kBlock, 0, s>>>(ws.keys[cur], n, g.ncells,
+                                                                                start);
+    } else {
+        k_cell_start<<<div_up((uint64_t)g.ncells + 1, kBlock), kBlock, 0, s>>>(ws.keys[0], 0, g.ncells, start);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_mark_boundary(const Grid &g, const sph_particles &local, const uint32_t *rstart,
+                                uint32_t *comm, uint32_t *bidx, uint32_t cap, uint32_t *nb,
+                                const Workspace &ws, hipStream_t s)
+{
+    uint32_t n = local.n;
+    uint32_t blocks = div_up(n > 0 ? n : 1, kBlock);
+    k_mark<<<blocks, kBlock, 0, s>>>(g, n, local.hash, rstart, comm, ws.counts);
+    k_scan_counts<<<1, kBlock, 0, s>>>(ws.counts, blocks, nb);
+    k_compact<<<blocks, kBlock, 0, s>>>(n, g.ncells, comm, ws.counts, bidx, cap);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack(int prec, const sph_particles &local, const uint32_t *bidx, const uint32_t *nb,
+                       const sph_particles &payload, hipStream_t s)
+{
+    uint32_t blocks = div_up(payload.n, kBlock);
+    if (blocks == 0) return hipSuccess;
+    if (prec == SPH_FP64)
+        k_pack<double><<<blocks, kBlock, 0, s>>>(view<double>(local), bidx, nb, view<double>(payload));
+    else
+        k_pack<float><<<blocks, kBlock, 0, s>>>(view<float>(local), bidx, nb, view<float>(payload));
+    return hipGetLastError();
+}
+
+}  // namespace sph

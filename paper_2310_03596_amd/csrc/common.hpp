@@ -1,0 +1,197 @@
+// Internal definitions shared by the HIP kernels and the C ABI of libsph.
+// gfx950 (CDNA4) only: 64-lane wavefronts, 256-thread workgroups.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "sph.h"
+
+namespace sph {
+
+constexpr int kBlock = 256;          // threads per workgroup for streaming kernels
+constexpr int kWave = 64;            // CDNA wavefront width
+constexpr int kSortItems = 8;        // keys per thread in a radix-sort tile
+constexpr int kSortTile = kBlock * kSortItems;
+constexpr int kRadixBits = 8;
+constexpr int kRadixBins = 1 << kRadixBits;
+constexpr int kDiag = 7;             // integrate diagnostics
+constexpr int kDiagPartial = 8;      // per-block partial record (doubles)
+
+// Device view of the grid: origin, bucket side and its float copy.
+struct Grid {
+    double o[3];
+    double L;
+    float Lf;
+    int nx, ny, nz;
+    uint32_t ncells;
+};
+
+// Constants the kernels read, precomputed on the host.
+struct Params {
+    double h, rho0, c0, gamma, K, G, Y0, H, beta, cfl;
+    double g[3], wlo[3], whi[3];
+    uint32_t wall_mask;
+    int material;
+    double R2;            // (2h)^2, the neighbour predicate bound
+    double hinv;          // 1 / h
+    double Fc;            // 1 / (pi h^4): F = Fc f(q)
+    double B;             // Tait stiffness rho0 c0^2 / gamma
+    double c_solid;       // solid sound speed
+};
+
+// Particle array with typed pointers.  real = float (FP32 split) or double.
+template <typename real>
+struct PV {
+    uint32_t n;
+    double *x[3];
+    float *off[3];
+    uint32_t *hash;
+    uint32_t *id;
+    real *v[3];
+    real *m, *w, *rho, *p, *c, *e;
+    double *E;
+    real *S[6];
+    real *ep;
+};
+
+template <typename real>
+inline PV<real> view(const sph_particles &s)
+{
+    PV<real> o;
+    o.n = s.n;
+    for (int d = 0; d < 3; ++d) {
+        o.x[d] = s.x[d];
+        o.off[d] = s.off[d];
+        o.v[d] = static_cast<real *>(s.v[d]);
+    }
+    o.hash = s.hash;
+    o.id = s.id;
+    o.m = static_cast<real *>(s.m);
+    o.w = static_cast<real *>(s.omega);
+    o.rho = static_cast<real *>(s.rho);
+    o.p = static_cast<real *>(s.p);
+    o.c = static_cast<real *>(s.c);
+    o.e = static_cast<real *>(s.e);
+    o.E = s.E;
+    for (int k = 0; k < 6; ++k) o.S[k] = static_cast<real *>(s.S[k]);
+    o.ep = static_cast<real *>(s.eps_p);
+    return o;
+}
+
+template <typename real>
+struct RV {
+    real *hi[6];
+    real *lo[6];
+    real *Lhi[9];
+    real *Llo[9];
+};
+
+template <typename real>
+inline RV<real> view(const sph_rates &r)
+{
+    RV<real> o;
+    for (int k = 0; k < 6; ++k) {
+        o.hi[k] = static_cast<real *>(r.hi[k]);
+        o.lo[k] = static_cast<real *>(r.lo[k]);
+    }
+    for (int k = 0; k < 9; ++k) {
+        o.Lhi[k] = static_cast<real *>(r.Lhi[k]);
+        o.Llo[k] = static_cast<real *>(r.Llo[k]);
+    }
+    return o;
+}
+
+template <typename real>
+struct AV {
+    real *x[3];
+    real *v[3];
+    real *m, *w, *E, *rho, *p, *c, *e;
+};
+
+template <typename real>
+inline AV<real> view(const sph_adjoint &a)
+{
+    AV<real> o;
+    for (int d = 0; d < 3; ++d) {
+        o.x[d] = static_cast<real *>(a.x[d]);
+        o.v[d] = static_cast<real *>(a.v[d]);
+    }
+    o.m = static_cast<real *>(a.m);
+    o.w = static_cast<real *>(a.omega);
+    o.E = static_cast<real *>(a.E);
+    o.rho = static_cast<real *>(a.rho);
+    o.p = static_cast<real *>(a.p);
+    o.c = static_cast<real *>(a.c);
+    o.e = static_cast<real *>(a.e);
+    return o;
+}
+
+// Workspace layout for n particles (256-byte aligned pieces).
+struct Workspace {
+    uint32_t *keys[2];
+    uint32_t *vals[2];
+    uint32_t *hist;        // kRadixBins * sort tiles
+    uint32_t *totals;      // kRadixBins
+    uint32_t *counts;      // compaction block counts (+1)
+    double *partials;      // kDiagPartial * reduction blocks
+    size_t bytes;
+};
+
+inline uint32_t div_up(uint64_t a, uint64_t b) { return (uint32_t)((a + b - 1) / b); }
+
+inline size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+inline Workspace carve(void *base, uint32_t n)
+{
+    Workspace w;
+    uint64_t nn = n > 0 ? n : 1;
+    uint32_t tiles = div_up(nn, kSortTile);
+    uint32_t blocks = div_up(nn, kBlock);
+    char *p = static_cast<char *>(base);
+    size_t off = 0;
+    auto take = [&](size_t b) {
+        char *r = p ? p + off : nullptr;
+        off += align256(b);
+        return r;
+    };
+    for (int k = 0; k < 2; ++k) {
+        w.keys[k] = reinterpret_cast<uint32_t *>(take(4 * nn));
+        w.vals[k] = reinterpret_cast<uint32_t *>(take(4 * nn));
+    }
+    w.hist = reinterpret_cast<uint32_t *>(take(4ull * kRadixBins * tiles));
+    w.totals = reinterpret_cast<uint32_t *>(take(4ull * kRadixBins));
+    w.counts = reinterpret_cast<uint32_t *>(take(4ull * (blocks + 1)));
+    w.partials = reinterpret_cast<double *>(take(8ull * kDiagPartial * blocks));
+    w.bytes = off;
+    return w;
+}
+
+// ---------------------------------------------------------------- launchers
+// Each returns hipSuccess or the launch error; arguments were validated.
+
+hipError_t launch_build_cells(const Grid &g, int prec, const sph_particles &in, const sph_particles &out,
+                              uint32_t *perm, uint32_t *start, const Workspace &ws, hipStream_t s);
+hipError_t launch_mark_boundary(const Grid &g, const sph_particles &local, const uint32_t *rstart,
+                                uint32_t *comm, uint32_t *bidx, uint32_t cap, uint32_t *nb,
+                                const Workspace &ws, hipStream_t s);
+hipError_t launch_pack(int prec, const sph_particles &local, const uint32_t *bidx, const uint32_t *nb,
+                       const sph_particles &payload, hipStream_t s);
+hipError_t launch_interact(const Params &P, const Grid &g, int prec, int pass, const sph_particles &tg,
+                           const uint32_t *tidx, const uint32_t *nt, const sph_particles &sr,
+                           const uint32_t *sstart, bool self, int zero_first, const sph_rates &r,
+                           hipStream_t s);
+hipError_t launch_integrate(const Params &P, int prec, int stage, const sph_particles &p,
+                            const sph_rates &r, const double *dt, double *diag, const Workspace &ws,
+                            hipStream_t s);
+hipError_t launch_interact_adjoint(const Params &P, const Grid &g, int prec, const sph_particles &p,
+                                   const uint32_t *start, const sph_rates &rbar, const sph_adjoint &bar,
+                                   hipStream_t s);
+hipError_t launch_integrate_adjoint(const Params &P, int prec, int stage, const sph_particles &p,
+                                    const sph_rates &r, const double *dt, const sph_adjoint &bar,
+                                    const sph_rates &rbar, double *pbar, const Workspace &ws,
+                                    hipStream_t s);
+hipError_t launch_permute_adjoint(int prec, uint32_t n, const uint32_t *perm, const sph_adjoint &in,
+                                  const sph_adjoint &out, hipStream_t s);
+
+}  // namespace sph

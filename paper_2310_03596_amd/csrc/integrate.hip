@@ -1,0 +1,241 @@
+// Step g of Section II: explicit update, equation of state, solid stress
+// stage, and deterministic FP64 diagnostics (next dt and conserved totals).
+//
+// Elementwise and HBM-bound: every stage reads and writes each particle once
+// in coalesced SoA order; arithmetic runs in FP64 in both forms (free next to
+// the memory traffic) and is stored back in the form's precision.  Totals
+// are reduced per workgroup in a fixed order into a partial record, then one
+// workgroup folds the records in a fixed order, so the result does not
+// depend on scheduling.
+#include "common.hpp"
+
+namespace sph {
+
+namespace {
+
+__device__ inline void eos(const Params &P, double rho, double &p, double &c)
+{
+    if (P.material == SPH_FLUID_TAIT) {
+        double s = rho / P.rho0;
+        p = P.B * (pow(s, P.gamma) - 1.0);
+        c = P.c0 * pow(s, 0.5 * (P.gamma - 1.0));
+    } else {
+        p = P.K * (rho / P.rho0 - 1.0);
+        c = P.c_solid;
+    }
+}
+
+// Fixed-order workgroup reduction of 7 values: slot 0 by max, the rest by sum.
+__device__ inline void block_reduce_record(double r[kDiag], double *out)
+{
+    __shared__ double sh[kDiag][kBlock / kWave];
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+#pragma unroll
+    for (int k = 0; k < kDiag; ++k) {
+        double v = r[k];
+#pragma unroll
+        for (int off = kWave / 2; off > 0; off >>= 1) {
+            double o = __shfl_down(v, off, kWave);
+            v = (k == 0) ? fmax(v, o) : v + o;
+        }
+        if (lane == 0) sh[k][wave] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < kDiag; ++k) {
+            double v = sh[k][0];
+            for (int w = 1; w < kBlock / kWave; ++w) v = (k == 0) ? fmax(v, sh[k][w]) : v + sh[k][w];
+            out[k] = v;
+        }
+        out[kDiag] = 0.0;
+    }
+}
+
+template <typename real>
+__device__ inline void finish(const Params &P, const PV<real> &s, uint32_t i, double m, double w, const double v[3],
+                              double E, double rec[kDiag])
+{
+    double rho = m / w;
+    double p, c;
+    eos(P, rho, p, c);
+    double v2 = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+    s.rho[i] = (real)rho;
+    s.p[i] = (real)p;
+    s.c[i] = (real)c;
+    s.e[i] = (real)(E - 0.5 * v2);
+    rec[0] = c + sqrt(v2);
+    rec[1] = m;
+    rec[2] = m * v[0];
+    rec[3] = m * v[1];
+    rec[4] = m * v[2];
+    rec[5] = m * E;
+    rec[6] = 0.5 * m * v2;
+}
+
+template <typename real, bool SPLIT>
+__global__ __launch_bounds__(kBlock) void k_motion(Params P, PV<real> s, RV<real> R, const double *__restrict__ dtp,
+                                                   double *__restrict__ partials)
+{
+    uint32_t i = blockIdx.x * kBlock + threadIdx.x;
+    double rec[kDiag] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    if (i < s.n) {
+        const double dt = *dtp;
+        double r[6];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) r[k] = (double)R.hi[k][i] + (SPLIT ? (double)R.lo[k][i] : 0.0);
+        double m = (double)s.m[i];
+        double v[3] = {(double)s.v[0][i], (double)s.v[1][i], (double)s.v[2][i]};
+        double mn = m + dt * r[0];
+        double gv = P.g[0] * v[0] + P.g[1] * v[1] + P.g[2] * v[2];
+        double vn[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) vn[a] = (m * v[a] + dt * (r[1 + a] + m * P.g[a])) / mn;
+        double En = (m * s.E[i] + dt * (r[4] + m * gv)) / mn;
+        double wn = (double)s.w[i] + dt * r[5];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            double xn = s.x[a][i] + dt * vn[a];
+            if ((P.wall_mask >> (2 * a)) & 1u)
+                if (xn < P.wlo[a]) {
+                    xn = 2.0 * P.wlo[a] - xn;
+                    vn[a] = -vn[a];
+                }
+            if ((P.wall_mask >> (2 * a + 1)) & 1u)
+                if (xn > P.whi[a]) {
+                    xn = 2.0 * P.whi[a] - xn;
+                    vn[a] = -vn[a];
+                }
+            s.x[a][i] = xn;
+            s.v[a][i] = (real)vn[a];
+        }
+        real mr = (real)mn, wr = (real)wn;
+        s.m[i] = mr;
+        s.w[i] = wr;
+        s.E[i] = En;
+        // the stored (possibly rounded) state defines the EOS and the totals
+        double vs[3] = {(double)(real)vn[0], (double)(real)vn[1], (double)(real)vn[2]};
+        finish<real>(P, s, i, (double)mr, (double)wr, vs, En, rec);
+    }
+    block_reduce_record(rec, partials + (size_t)blockIdx.x * kDiagPartial);
+}
+
+template <typename real>
+__global__ __launch_bounds__(kBlock) void k_eos(Params P, PV<real> s, double *__restrict__ partials)
+{
+    uint32_t i = blockIdx.x * kBlock + threadIdx.x;
+    double rec[kDiag] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    if (i < s.n) {
+        double v[3] = {(double)s.v[0][i], (double)s.v[1][i], (double)s.v[2][i]};
+        finish<real>(P, s, i, (double)s.m[i], (double)s.w[i], v, s.E[i], rec);
+    }
+    block_reduce_record(rec, partials + (size_t)blockIdx.x * kDiagPartial);
+}
+
+__global__ __launch_bounds__(kBlock) void k_diag_final(const double *__restrict__ partials, uint32_t nblocks,
+                                                       double cfl_h, double *__restrict__ diag)
+{
+    double rec[kDiag] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    for (uint32_t b = threadIdx.x; b < nblocks; b += kBlock) {
+        const double *q = partials + (size_t)b * kDiagPartial;
+        rec[0] = fmax(rec[0], q[0]);
+#pragma unroll
+        for (int k = 1; k < kDiag; ++k) rec[k] += q[k];
+    }
+    __shared__ double out[kDiagPartial];
+    block_reduce_record(rec, out);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        diag[0] = out[0] > 0.0 ? cfl_h / out[0] : __builtin_huge_val();
+#pragma unroll
+        for (int k = 1; k < kDiag; ++k) diag[k] = out[k];
+    }
+}
+
+// Jaumann rate of the deviatoric stress and J2 radial return with linear hardening.
+template <typename real, bool SPLIT>
+__global__ __launch_bounds__(kBlock) void k_stress(Params P, PV<real> s, RV<real> R, const double *__restrict__ dtp)
+{
+    uint32_t i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= s.n) return;
+    const double dt = *dtp;
+    double L[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) L[k] = (double)R.Lhi[k][i] + (SPLIT ? (double)R.Llo[k][i] : 0.0);
+    double D[3][3], W[3][3], S[3][3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            D[a][b] = 0.5 * (L[3 * a + b] + L[3 * b + a]);
+            W[a][b] = 0.5 * (L[3 * a + b] - L[3 * b + a]);
+        }
+    double s6[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) s6[k] = (double)s.S[k][i];
+    S[0][0] = s6[0]; S[1][1] = s6[1]; S[2][2] = s6[2];
+    S[0][1] = S[1][0] = s6[3];
+    S[0][2] = S[2][0] = s6[4];
+    S[1][2] = S[2][1] = s6[5];
+    const double tr = D[0][0] + D[1][1] + D[2][2];
+    double Sd[3][3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            double ws = 0.0, sw = 0.0;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                ws += W[a][k] * S[k][b];
+                sw += S[a][k] * W[k][b];
+            }
+            Sd[a][b] = 2.0 * P.G * (D[a][b] - (a == b ? tr / 3.0 : 0.0)) + ws - sw;
+        }
+    double St[6] = {S[0][0] + dt * Sd[0][0], S[1][1] + dt * Sd[1][1], S[2][2] + dt * Sd[2][2],
+                    S[0][1] + dt * Sd[0][1], S[0][2] + dt * Sd[0][2], S[1][2] + dt * Sd[1][2]};
+    double J = St[0] * St[0] + St[1] * St[1] + St[2] * St[2] + 2.0 * (St[3] * St[3] + St[4] * St[4] + St[5] * St[5]);
+    double q = sqrt(1.5 * J);
+    double ep = (double)s.ep[i];
+    double sy = P.Y0 + P.H * ep;
+    if (q > sy) {
+        double dep = (q - sy) / (3.0 * P.G + P.H);
+        double f = 1.0 - 3.0 * P.G * dep / q;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) St[k] *= f;
+        ep += dep;
+    }
+#pragma unroll
+    for (int k = 0; k < 6; ++k) s.S[k][i] = (real)St[k];
+    s.ep[i] = (real)ep;
+}
+
+template <typename real>
+hipError_t go(const Params &P, int stage, const sph_particles &p, const sph_rates &r, const double *dt,
+              double *diag, const Workspace &ws, hipStream_t s)
+{
+    constexpr bool SPLIT = sizeof(real) == 4;
+    uint32_t blocks = div_up(p.n, kBlock);
+    if (stage == SPH_STAGE_STRESS) {
+        if (blocks) k_stress<real, SPLIT><<<blocks, kBlock, 0, s>>>(P, view<real>(p), view<real>(r), dt);
+        return hipGetLastError();
+    }
+    if (blocks) {
+        if (stage == SPH_STAGE_MOTION)
+            k_motion<real, SPLIT><<<blocks, kBlock, 0, s>>>(P, view<real>(p), view<real>(r), dt, ws.partials);
+        else
+            k_eos<real><<<blocks, kBlock, 0, s>>>(P, view<real>(p), ws.partials);
+    }
+    if (diag) k_diag_final<<<1, kBlock, 0, s>>>(ws.partials, blocks, P.cfl * P.h, diag);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_integrate(const Params &P, int prec, int stage, const sph_particles &p, const sph_rates &r,
+                            const double *dt, double *diag, const Workspace &ws, hipStream_t s)
+{
+    if (prec == SPH_FP64) return go<double>(P, stage, p, r, dt, diag, ws, s);
+    return go<float>(P, stage, p, r, dt, diag, ws, s);
+}
+
+}  // namespace sph

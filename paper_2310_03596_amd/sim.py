@@ -1,0 +1,172 @@
+"""Step driver: sequences the libsph calls of one GPU's share of a step.
+
+Fluid step (Section II, steps a, e, g): build_cells -> FORCE pass -> MOTION.
+Solid step (two interaction loops per iteration, Section II note):
+build_cells -> GRADIENT pass -> STRESS stage -> FORCE pass -> MOTION.
+Share step (steps a, c, d packing, e, f): see ``SharePass``.
+All work is enqueued on the current stream; dt, boundary counts and
+diagnostics stay on the device.
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import _lib as L
+from .state import Particles, Rates, cells_struct, grid_struct, ncells, params_struct, stream_handle
+
+
+class Sim:
+    def __init__(self, wl, prec: int, device="cuda", fixed_dt: float | None = None):
+        self.wl = wl
+        self.prec = prec
+        self.solid = wl.S is not None
+        self.grid = grid_struct(wl.grid)
+        self.params = params_struct(wl.params, prec)
+        self.nc = ncells(wl.grid)
+        self.n = wl.n
+        self.A = Particles.upload(wl, prec, device)
+        self.B = Particles(self.n, prec, self.solid, device)
+        self.perm = torch.zeros(self.n, dtype=torch.int32, device=device)
+        self.start = torch.zeros(self.nc + 1, dtype=torch.int32, device=device)
+        self.ws_bytes = L.sph_workspace_size(self.grid, self.n)
+        self.ws = torch.zeros(self.ws_bytes, dtype=torch.uint8, device=device)
+        self.rates = Rates(self.n, prec, self.solid, device)
+        self.diag = torch.zeros((2, 8), dtype=torch.float64, device=device)
+        self.cur = 0
+        self.fixed = None
+        if fixed_dt is not None:
+            self.fixed = torch.full((1,), float(fixed_dt), dtype=torch.float64, device=device)
+        self.steps_done = 0
+        s = self.A.struct()
+        L.sph_integrate(self.params, L.SPH_STAGE_EOS, s, None, None, self.diag[0].data_ptr(),
+                        self.ws.data_ptr(), self.ws_bytes, stream_handle())
+
+    @property
+    def cells(self):
+        return cells_struct(self.start, self.nc)
+
+    def build(self):
+        """Step a + bucket sort: A (any order) -> B (hash order), then swap."""
+        a, b = self.A.struct(), self.B.struct()
+        L.sph_build_cells(self.grid, a, b, self.perm.data_ptr(), self.cells, self.ws.data_ptr(), self.ws_bytes,
+                          stream_handle())
+        self.A, self.B = self.B, self.A
+
+    def interact(self, pass_=L.SPH_PASS_FORCE):
+        a = self.A.struct()
+        r = self.rates.struct()
+        L.sph_interact(self.params, self.grid, pass_, a, None, None, a, self.cells, 1, r, stream_handle())
+
+    def dt_ptr(self, dt_ptr=None):
+        if dt_ptr is not None:
+            return dt_ptr
+        if self.fixed is not None:
+            return self.fixed.data_ptr()
+        return self.diag[self.cur].data_ptr()    # [0] = next dt of the previous update
+
+    def step(self, dt_ptr=None):
+        dtp = self.dt_ptr(dt_ptr)
+        self.build()
+        a = self.A.struct()
+        r = self.rates.struct()
+        st = stream_handle()
+        if self.solid:
+            L.sph_interact(self.params, self.grid, L.SPH_PASS_GRADIENT, a, None, None, a, self.cells, 1, r, st)
+            L.sph_integrate(self.params, L.SPH_STAGE_STRESS, a, r, dtp, None, None, 0, st)
+        L.sph_interact(self.params, self.grid, L.SPH_PASS_FORCE, a, None, None, a, self.cells, 1, r, st)
+        nxt = 1 - self.cur
+        L.sph_integrate(self.params, L.SPH_STAGE_MOTION, a, r, dtp, self.diag[nxt].data_ptr(), self.ws.data_ptr(),
+                        self.ws_bytes, st)
+        self.cur = nxt
+        self.steps_done += 1
+
+    def run(self, nsteps: int, dts: np.ndarray | None = None):
+        """nsteps steps; dts (optional) replays a given dt schedule."""
+        dts_dev = None
+        if dts is not None:
+            dts_dev = torch.as_tensor(np.asarray(dts, dtype=np.float64), device=self.A.x.device)
+        for k in range(nsteps):
+            self.step(None if dts_dev is None else dts_dev[k].data_ptr())
+        return dts_dev
+
+    def diagnostics(self) -> np.ndarray:
+        return self.diag[self.cur, :7].cpu().numpy()
+
+    def state_by_id(self) -> dict:
+        h = self.A.host()
+        order = np.argsort(h["id"], kind="stable")
+        return {k: v[order] for k, v in h.items()}
+
+
+class SharePass:
+    """One GPU's share of a particle-decomposition pass set (Section II a-f).
+
+    Local and remote particles are kept in separate arrays on the same grid.
+    ``run()`` enqueues: build_cells on both arrays (step a and the one-GPU
+    stand-in for receiving hashes, step b), communication hash and boundary
+    compaction (step c), packing of the boundary payload (step d), the
+    local-local FORCE pass (step e) and the local-remote FORCE pass over the
+    boundary list only (step f).
+    """
+
+    def __init__(self, local_wl, remote_wl, prec: int, device="cuda"):
+        self.prec = prec
+        self.grid = grid_struct(local_wl.grid)
+        self.params = params_struct(local_wl.params, prec)
+        self.nc = ncells(local_wl.grid)
+        self.nl, self.nr = local_wl.n, remote_wl.n
+        self.LA = Particles.upload(local_wl, prec, device)
+        self.LB = Particles(self.nl, prec, False, device)
+        self.RA = Particles.upload(remote_wl, prec, device)
+        self.RB = Particles(self.nr, prec, False, device)
+        self.lperm = torch.zeros(self.nl, dtype=torch.int32, device=device)
+        self.rperm = torch.zeros(self.nr, dtype=torch.int32, device=device)
+        self.lstart = torch.zeros(self.nc + 1, dtype=torch.int32, device=device)
+        self.rstart = torch.zeros(self.nc + 1, dtype=torch.int32, device=device)
+        nmax = max(self.nl, self.nr)
+        self.ws_bytes = L.sph_workspace_size(self.grid, nmax)
+        self.ws = torch.zeros(self.ws_bytes, dtype=torch.uint8, device=device)
+        self.comm = torch.zeros(self.nl, dtype=torch.int32, device=device)
+        self.bidx = torch.zeros(self.nl, dtype=torch.int32, device=device)
+        self.nb = torch.zeros(1, dtype=torch.int32, device=device)
+        self.payload = Particles(self.nl, prec, False, device)
+        self.rates = Rates(self.nl, prec, False, device)
+        self.diag = torch.zeros(8, dtype=torch.float64, device=device)
+        st = stream_handle()
+        for P in (self.LA, self.RA):
+            L.sph_integrate(self.params, L.SPH_STAGE_EOS, P.struct(), None, None, self.diag.data_ptr(),
+                            self.ws.data_ptr(), self.ws_bytes, st)
+
+    def build(self):
+        st = stream_handle()
+        L.sph_build_cells(self.grid, self.LA.struct(), self.LB.struct(), self.lperm.data_ptr(),
+                          cells_struct(self.lstart, self.nc), self.ws.data_ptr(), self.ws_bytes, st)
+        L.sph_build_cells(self.grid, self.RA.struct(), self.RB.struct(), self.rperm.data_ptr(),
+                          cells_struct(self.rstart, self.nc), self.ws.data_ptr(), self.ws_bytes, st)
+
+    def mark(self):
+        L.sph_mark_boundary(self.grid, self.LB.struct(), cells_struct(self.rstart, self.nc), self.comm.data_ptr(),
+                            self.bidx.data_ptr(), self.nl, self.nb.data_ptr(), self.ws.data_ptr(), self.ws_bytes,
+                            stream_handle())
+
+    def pack(self):
+        L.sph_pack_boundary(self.LB.struct(), self.bidx.data_ptr(), self.nb.data_ptr(), self.payload.struct(),
+                            stream_handle())
+
+    def interact_local(self):
+        a = self.LB.struct()
+        L.sph_interact(self.params, self.grid, L.SPH_PASS_FORCE, a, None, None, a,
+                       cells_struct(self.lstart, self.nc), 1, self.rates.struct(), stream_handle())
+
+    def interact_remote(self):
+        L.sph_interact(self.params, self.grid, L.SPH_PASS_FORCE, self.LB.struct(), self.bidx.data_ptr(),
+                       self.nb.data_ptr(), self.RB.struct(), cells_struct(self.rstart, self.nc), 0,
+                       self.rates.struct(), stream_handle())
+
+    def run(self):
+        self.build()
+        self.mark()
+        self.pack()
+        self.interact_local()
+        self.interact_remote()

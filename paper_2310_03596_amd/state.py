@@ -1,0 +1,170 @@
+"""Device particle arrays and ABI struct builders.
+
+PyTorch serves only as the device allocator and stream provider: every
+tensor here is raw device memory handed to libsph by pointer.
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+
+def real_dtype(prec: int):
+    return torch.float64 if prec == L.SPH_FP64 else torch.float32
+
+
+def grid_struct(grid: dict) -> L.SphGrid:
+    g = L.SphGrid()
+    for d in range(3):
+        g.origin[d] = float(grid["origin"][d])
+        g.dims[d] = int(grid["dims"][d])
+    g.cell = float(grid["cell"])
+    return g
+
+
+def ncells(grid: dict) -> int:
+    d = grid["dims"]
+    return int(d[0]) * int(d[1]) * int(d[2])
+
+
+def params_struct(p: dict, prec: int) -> L.SphParams:
+    s = L.SphParams()
+    for k in ("h", "rho0", "c0", "gamma", "K", "G", "Y0", "H", "beta", "cfl"):
+        setattr(s, k, float(p[k]))
+    for d in range(3):
+        s.gravity[d] = float(p["gravity"][d])
+        s.wall_lo[d] = float(p["wall_lo"][d])
+        s.wall_hi[d] = float(p["wall_hi"][d])
+    s.wall_mask = int(p["wall_mask"])
+    s.material = int(p["material"])
+    s.prec = int(prec)
+    return s
+
+
+def _ptr(t):
+    return None if t is None else t.data_ptr()
+
+
+class Particles:
+    """One particle array in SoA form on the device."""
+
+    REAL = ("m", "w", "rho", "p", "c", "e")
+
+    def __init__(self, n: int, prec: int, solid: bool, device="cuda"):
+        real = real_dtype(prec)
+        self.n, self.prec, self.solid, self.device = n, prec, solid, device
+
+        def z(shape, dt):
+            return torch.zeros(shape, dtype=dt, device=device)
+
+        self.x = z((3, n), torch.float64)
+        self.off = z((3, n), torch.float32) if prec == L.SPH_FP32_SPLIT else None
+        self.hash = z((n,), torch.int32)
+        self.id = z((n,), torch.int32)
+        self.v = z((3, n), real)
+        for f in self.REAL:
+            setattr(self, f, z((n,), real))
+        self.E = z((n,), torch.float64)
+        self.S = z((6, n), real) if solid else None
+        self.ep = z((n,), real) if solid else None
+
+    def struct(self) -> L.SphParticles:
+        s = L.SphParticles()
+        s.n = self.n
+        s.prec = self.prec
+        if self.n == 0:
+            return s
+        for d in range(3):
+            s.x[d] = self.x[d].data_ptr()
+            s.v[d] = self.v[d].data_ptr()
+            if self.off is not None:
+                s.off[d] = self.off[d].data_ptr()
+        s.hash = self.hash.data_ptr()
+        s.id = self.id.data_ptr()
+        s.m, s.omega, s.rho = self.m.data_ptr(), self.w.data_ptr(), self.rho.data_ptr()
+        s.p, s.c, s.e = self.p.data_ptr(), self.c.data_ptr(), self.e.data_ptr()
+        s.E = self.E.data_ptr()
+        if self.solid:
+            for k in range(6):
+                s.S[k] = self.S[k].data_ptr()
+            s.eps_p = self.ep.data_ptr()
+        return s
+
+    @classmethod
+    def upload(cls, wl, prec: int, device="cuda") -> "Particles":
+        p = cls(wl.n, prec, wl.S is not None, device)
+        real = real_dtype(prec)
+        p.x.copy_(torch.from_numpy(np.ascontiguousarray(wl.x.T)))
+        p.v.copy_(torch.from_numpy(np.ascontiguousarray(wl.v.T)).to(real))
+        p.m.copy_(torch.from_numpy(wl.m).to(real))
+        p.w.copy_(torch.from_numpy(wl.omega).to(real))
+        p.rho.copy_(torch.from_numpy(wl.rho).to(real))
+        p.E.copy_(torch.from_numpy(wl.E))
+        p.id.copy_(torch.from_numpy(wl.id.astype(np.int64)).to(torch.int32))
+        if wl.S is not None:
+            p.S.copy_(torch.from_numpy(np.ascontiguousarray(wl.S.T)).to(real))
+            p.ep.copy_(torch.from_numpy(wl.eps_p).to(real))
+        return p
+
+    def host(self) -> dict:
+        """Copy every field to host numpy arrays (array order, positions (n,3))."""
+        out = {"x": self.x.T.cpu().numpy().copy(), "v": self.v.T.double().cpu().numpy().copy(),
+               "hash": self.hash.cpu().numpy().view(np.uint32).copy(),
+               "id": self.id.cpu().numpy().view(np.uint32).copy(), "E": self.E.cpu().numpy().copy()}
+        for f in self.REAL:
+            out[f] = getattr(self, f).double().cpu().numpy().copy()
+        if self.off is not None:
+            out["off"] = self.off.T.double().cpu().numpy().copy()
+        if self.solid:
+            out["S"] = self.S.T.double().cpu().numpy().copy()
+            out["ep"] = self.ep.double().cpu().numpy().copy()
+        return out
+
+
+class Rates:
+    """Pair-sum outputs: FORCE rates and, for solids, the velocity gradient."""
+
+    def __init__(self, n: int, prec: int, gradient: bool, device="cuda"):
+        real = real_dtype(prec)
+        split = prec == L.SPH_FP32_SPLIT
+        self.hi = torch.zeros((6, n), dtype=real, device=device)
+        self.lo = torch.zeros((6, n), dtype=real, device=device) if split else None
+        self.Lhi = torch.zeros((9, n), dtype=real, device=device) if gradient else None
+        self.Llo = torch.zeros((9, n), dtype=real, device=device) if (gradient and split) else None
+
+    def struct(self) -> L.SphRates:
+        r = L.SphRates()
+        if self.hi.shape[1] == 0:
+            return r
+        for k in range(6):
+            r.hi[k] = self.hi[k].data_ptr()
+            if self.lo is not None:
+                r.lo[k] = self.lo[k].data_ptr()
+        if self.Lhi is not None:
+            for k in range(9):
+                r.Lhi[k] = self.Lhi[k].data_ptr()
+                if self.Llo is not None:
+                    r.Llo[k] = self.Llo[k].data_ptr()
+        return r
+
+    def force(self) -> torch.Tensor:
+        """(6, n) rate sums as float64 (hi + lo)."""
+        f = self.hi.double()
+        return f + self.lo.double() if self.lo is not None else f
+
+    def grad(self) -> torch.Tensor:
+        f = self.Lhi.double()
+        return f + self.Llo.double() if self.Llo is not None else f
+
+
+def cells_struct(start: torch.Tensor, nc: int) -> L.SphCells:
+    c = L.SphCells()
+    c.start = start.data_ptr()
+    c.ncells = nc
+    return c
+
+
+def stream_handle() -> int:
+    return torch.cuda.current_stream().cuda_stream

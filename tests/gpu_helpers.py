@@ -1,0 +1,70 @@
+"""Helpers for GPU parity tests: convert device state to the oracle's layout
+and compare with stated tolerances."""
+from __future__ import annotations
+
+import numpy as np
+
+import sph_synth as S
+from oracle import cpu
+
+
+def oracle_state(h: dict, solid: bool) -> cpu.State:
+    """Oracle state holding exactly the values the device holds (array order)."""
+    s = cpu.State(h["x"].shape[0], solid)
+    s.x[:] = h["x"]
+    s.v[:] = h["v"]
+    s.m[:] = h["m"]
+    s.w[:] = h["w"]
+    s.rho[:] = h["rho"]
+    s.p[:] = h["p"]
+    s.c[:] = h["c"]
+    s.E[:] = h["E"]
+    s.id[:] = h["id"]
+    s.hash[:] = h["hash"]
+    if solid:
+        s.S[:] = h["S"]
+        s.ep[:] = h["ep"]
+    return s
+
+
+def assert_close_scaled(got, ref, scale, rtol, what=""):
+    """|got - ref| <= rtol * scale elementwise (scale: per-entry round-off scale)."""
+    got = np.asarray(got, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    err = np.abs(got - ref)
+    bound = rtol * np.asarray(scale, dtype=np.float64) + 1e-300
+    bad = err > bound
+    if bad.any():
+        idx = np.argwhere(bad)[:5]
+        ratio = (err / np.maximum(scale, 1e-300)).max()
+        raise AssertionError(f"{what}: {bad.sum()} entries exceed {rtol} x scale (worst err/scale {ratio:.3e}); "
+                             f"first {idx.tolist()} got {got[tuple(idx[0])]} ref {ref[tuple(idx[0])]}")
+
+
+def pressure_scale(params: dict) -> float:
+    """Scale of the terms whose difference is p: gamma B for Tait (p = B (s^gamma - 1)
+    cancels near s = 1), K for the linear solid EOS."""
+    if params["material"] == S.FLUID_TAIT:
+        return params["gamma"] * params["rho0"] * params["c0"] ** 2 / params["gamma"]
+    return params["K"]
+
+
+def field_errors(gpu: dict, ref: cpu.State, fields=("x", "v", "m", "w", "rho", "p", "c", "E"),
+                 scales=None) -> dict:
+    """max |gpu - ref| / scale per field, rows matched by array position; the scale
+    is max |ref| unless ``scales`` gives one."""
+    out = {}
+    scales = scales or {}
+    for f in fields:
+        a = np.asarray(gpu[f], dtype=np.float64)
+        b = np.asarray(getattr(ref, f), dtype=np.float64)
+        den = scales.get(f, np.abs(b).max())
+        out[f] = float(np.abs(a - b).max() / den) if den > 0 else float(np.abs(a - b).max())
+    return out
+
+
+def dense_cell_cloud(n: int, seed: int) -> S.Workload:
+    """Many particles packed into a few buckets (long candidate rows)."""
+    w = S.random_cloud(n, seed=seed, h=0.05, box=1.0)
+    w.x = 0.45 + 0.1 * (w.x - 0.0)          # all inside [0.45, 0.55]^3 -> ~3^3 buckets of side 0.1
+    return w

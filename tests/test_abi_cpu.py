@@ -1,0 +1,185 @@
+"""CPU checks of the C ABI: the library loads, exports every symbol the
+header declares, and rejects invalid arguments on the host before anything
+is enqueued (no compute call runs here)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_2310_03596_amd import _lib as L
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "sph.h")
+
+FAKE = 0x1000   # never dereferenced: every call below fails validation first
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(sph_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_the_abi():
+    names = declared_functions()
+    for must in ("sph_build_cells", "sph_mark_boundary", "sph_interact", "sph_integrate",
+                 "sph_interact_adjoint"):
+        assert must in names
+    assert set(names) == set(L.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = L.load()
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+    assert "gfx950" in L.sph_version()
+
+
+def _grid(dims=(4, 4, 4), cell=1.0):
+    g = L.SphGrid()
+    for d in range(3):
+        g.origin[d] = 0.0
+        g.dims[d] = dims[d]
+    g.cell = cell
+    return g
+
+
+def _params(h=0.5, prec=L.SPH_FP64):
+    p = L.SphParams()
+    p.h, p.rho0, p.c0, p.gamma, p.cfl, p.beta = h, 1000.0, 50.0, 7.0, 0.3, 1.0
+    p.prec = prec
+    return p
+
+
+def _particles(n, prec=L.SPH_FP64, full=True):
+    s = L.SphParticles()
+    s.n, s.prec = n, prec
+    if full:
+        for d in range(3):
+            s.x[d] = s.v[d] = s.off[d] = FAKE
+        for f in ("hash", "id", "m", "omega", "rho", "p", "c", "e", "E"):
+            setattr(s, f, FAKE)
+    return s
+
+
+def _last():
+    return L.load().sph_last_error().decode()
+
+
+def test_workspace_size_grows_with_n():
+    g = _grid()
+    a, b = L.sph_workspace_size(g, 1000), L.sph_workspace_size(g, 100000)
+    assert 0 < a < b
+    assert L.sph_workspace_size(g, 0) > 0
+
+
+def test_build_cells_rejects_bad_arguments():
+    lib = L.load()
+    g = _grid()
+    cells = L.SphCells(FAKE, 64, 0)
+    a, b = _particles(10), _particles(10)
+    b.x[0] = 0x2000
+    ws = L.sph_workspace_size(g, 10)
+    # grid too large for 32-bit hashes
+    big = _grid(dims=(1 << 11, 1 << 11, 1 << 10))
+    assert lib.sph_build_cells(C.byref(big), C.byref(a), C.byref(b), FAKE, cells, FAKE, ws, None) == L.SPH_ERR_ARG
+    assert "2^32" in _last()
+    # bucket count mismatch
+    bad = L.SphCells(FAKE, 63, 0)
+    assert lib.sph_build_cells(C.byref(g), C.byref(a), C.byref(b), FAKE, bad, FAKE, ws, None) == L.SPH_ERR_ARG
+    # missing field
+    c = _particles(10)
+    c.rho = None
+    assert lib.sph_build_cells(C.byref(g), C.byref(c), C.byref(b), FAKE, cells, FAKE, ws, None) == L.SPH_ERR_ARG
+    assert "required field" in _last()
+    # in/out overlap
+    assert lib.sph_build_cells(C.byref(g), C.byref(a), C.byref(a), FAKE, cells, FAKE, ws, None) == L.SPH_ERR_ARG
+    # workspace too small
+    assert (lib.sph_build_cells(C.byref(g), C.byref(a), C.byref(b), FAKE, cells, FAKE, ws - 1, None)
+            == L.SPH_ERR_WORKSPACE)
+    # n mismatch
+    d = _particles(11)
+    assert lib.sph_build_cells(C.byref(g), C.byref(a), C.byref(d), FAKE, cells, FAKE, ws, None) == L.SPH_ERR_ARG
+    # zero-size bucket
+    z = _grid(cell=0.0)
+    assert lib.sph_build_cells(C.byref(z), C.byref(a), C.byref(b), FAKE, cells, FAKE, ws, None) == L.SPH_ERR_ARG
+
+
+def test_interact_rejects_bad_arguments():
+    lib = L.load()
+    g = _grid()
+    cells = L.SphCells(FAKE, 64, 0)
+    p = _particles(10)
+    r = L.SphRates()
+    for k in range(6):
+        r.hi[k] = FAKE
+    # bucket smaller than the support 2h
+    assert lib.sph_interact(C.byref(_params(h=0.6)), C.byref(g), 0, C.byref(p), None, None, C.byref(p), cells, 1,
+                            C.byref(r), None) == L.SPH_ERR_ARG
+    assert "smaller than the support" in _last()
+    # precision mismatch
+    assert lib.sph_interact(C.byref(_params(prec=L.SPH_FP32_SPLIT)), C.byref(g), 0, C.byref(p), None, None,
+                            C.byref(p), cells, 1, C.byref(r), None) == L.SPH_ERR_ARG
+    # FP32 split needs the compensation buffers and offsets
+    q = _particles(10, L.SPH_FP32_SPLIT)
+    assert lib.sph_interact(C.byref(_params(prec=L.SPH_FP32_SPLIT)), C.byref(g), 0, C.byref(q), None, None,
+                            C.byref(q), cells, 1, C.byref(r), None) == L.SPH_ERR_ARG
+    assert "lo" in _last()
+    # target list without a device count
+    assert lib.sph_interact(C.byref(_params()), C.byref(g), 0, C.byref(p), FAKE, None, C.byref(p), cells, 0,
+                            C.byref(r), None) == L.SPH_ERR_ARG
+    # unknown pass
+    assert lib.sph_interact(C.byref(_params()), C.byref(g), 7, C.byref(p), None, None, C.byref(p), cells, 1,
+                            C.byref(r), None) == L.SPH_ERR_ARG
+    # solid FORCE pass needs the stress fields
+    ps = _params()
+    ps.material, ps.K, ps.G = L.SPH_SOLID_J2, 1e9, 1e9
+    assert lib.sph_interact(C.byref(ps), C.byref(g), 0, C.byref(p), None, None, C.byref(p), cells, 1, C.byref(r),
+                            None) == L.SPH_ERR_ARG
+    assert "S[0]" in _last()
+
+
+def test_integrate_and_adjoint_reject_bad_arguments():
+    lib = L.load()
+    p = _particles(10)
+    ws = L.sph_workspace_size(_grid(), 10)
+    # stress stage on a fluid
+    assert lib.sph_integrate(C.byref(_params()), L.SPH_STAGE_STRESS, C.byref(p), None, FAKE, None, None, 0,
+                             None) == L.SPH_ERR_ARG
+    # motion without dt
+    r = L.SphRates()
+    for k in range(6):
+        r.hi[k] = FAKE
+    assert lib.sph_integrate(C.byref(_params()), L.SPH_STAGE_MOTION, C.byref(p), C.byref(r), None, FAKE, FAKE, ws,
+                             None) == L.SPH_ERR_ARG
+    # eos without diagnostics buffer
+    assert lib.sph_integrate(C.byref(_params()), L.SPH_STAGE_EOS, C.byref(p), None, None, None, FAKE, ws,
+                             None) == L.SPH_ERR_ARG
+    # adjoint: walls are not differentiated
+    pw = _params()
+    pw.wall_mask = 1
+    bar = L.SphAdjoint()
+    assert lib.sph_integrate_adjoint(C.byref(pw), L.SPH_STAGE_MOTION, C.byref(p), C.byref(r), FAKE, C.byref(bar),
+                                     C.byref(r), None, None, 0, None) == L.SPH_ERR_UNSUPPORTED
+    # adjoint of a solid
+    ps = _params()
+    ps.material, ps.K, ps.G = L.SPH_SOLID_J2, 1e9, 1e9
+    assert lib.sph_interact_adjoint(C.byref(ps), C.byref(_grid()), C.byref(p), L.SphCells(FAKE, 64, 0),
+                                    C.byref(r), C.byref(bar), None) == L.SPH_ERR_UNSUPPORTED
+
+
+def test_zero_particles_is_a_noop():
+    lib = L.load()
+    g = _grid()
+    cells = L.SphCells(FAKE, 64, 0)
+    p = _particles(0, full=False)
+    r = L.SphRates()
+    for k in range(6):
+        r.hi[k] = FAKE
+    assert lib.sph_interact(C.byref(_params()), C.byref(g), 0, C.byref(p), None, None, C.byref(p), cells, 1,
+                            C.byref(r), None) == L.SPH_OK
+    out = L.SphParticles()
+    out.n = 5
+    assert lib.sph_pack_boundary(C.byref(p), None, None, C.byref(L.SphParticles()), None) == L.SPH_OK
+    assert lib.sph_permute_adjoint(0, 0, None, None, None, None) == L.SPH_OK

@@ -1,0 +1,286 @@
+"""GPU parity of the HIP path (through the C ABI) against the FP64 CPU oracle.
+
+Tolerances
+  * Integer outputs (hash, permutation, bucket table, ids, communication
+    hash, boundary list and count): bit-exact.
+  * FP64 form, pair sums: |gpu - oracle| <= 1e-12 * S where S is the
+    per-target sum of |pair term| (sum of ~80 terms, each a chain of ~30
+    IEEE operations with FMA contraction on one side: a few hundred ulp of
+    S at most, far below 1e-12 S).
+  * FP32-split form, pair sums on the same (float-rounded) inputs:
+    |gpu - oracle| <= 2e-5 * S.  Each term is a chain of about 30 float
+    operations (unit round-off 6e-8 each, ~2e-6 of the term), the positions
+    enter through float offsets (relative error ~2e-7 of the bucket side),
+    and the compensated sum adds no more than one rounding of the result.
+  * One whole step: FP64 form within 1e-12 of the oracle per field (max
+    norm relative to the field's max); FP32-split form within 2e-5.
+"""
+import numpy as np
+import pytest
+import torch
+
+import sph_synth as S
+from oracle import cpu
+from tests import brute
+from tests.gpu_helpers import assert_close_scaled, dense_cell_cloud, field_errors, oracle_state, pressure_scale
+
+pytestmark = pytest.mark.gpu
+
+FP64, FP32 = 0, 1
+PRECS = [pytest.param(FP64, id="fp64"), pytest.param(FP32, id="fp32split")]
+TOL_RATE = {FP64: 1e-12, FP32: 2e-5}
+TOL_STEP = {FP64: 1e-12, FP32: 2e-5}
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2310_03596_amd import _lib
+    _lib.load()
+
+
+def _sim(wl, prec, **kw):
+    from paper_2310_03596_amd.sim import Sim
+    return Sim(wl, prec, **kw)
+
+
+def _clamped_cloud():
+    w = S.random_cloud(700, seed=51, h=0.05)
+    w.x[:40] -= 0.3            # outside the grid on the low side
+    w.x[40:80] += 0.3          # and on the high side
+    return w
+
+
+def _faces():
+    w = S.random_cloud(400, seed=52, h=0.05, box=0.5)
+    L = w.grid["cell"]
+    w.x[:, 0] = (np.arange(w.n) % 4) * L
+    w.x[1::3, 1] = np.nextafter(w.x[1::3, 0], np.inf)
+    w.x[2::3, 1] = np.nextafter(w.x[2::3, 0], -np.inf)
+    w.x = np.clip(w.x, 0.0, None)
+    return w
+
+
+CASES = {
+    "one": lambda: S.random_cloud(1, seed=50, h=0.05),
+    "cloud2049": lambda: S.random_cloud(2049, seed=53, h=0.04, rho_sigma=0.01),
+    "cube8000": lambda: S.c1_cube(),
+    "faces": _faces,
+    "clamped": _clamped_cloud,
+    "dense": lambda: dense_cell_cloud(1500, seed=54),
+    "lattice12": lambda: S.jittered_lattice(12, seed=55, rho_sigma=0.01),
+}
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("case", list(CASES))
+def test_build_cells_bit_exact(case, prec):
+    wl = CASES[case]()
+    print(f"[build_cells] case={case} prec={prec} n={wl.n}", flush=True)
+    sim = _sim(wl, prec)
+    sim.build()
+    torch.cuda.synchronize()
+    h = sim.A.host()
+    s = cpu.State.from_workload(wl)
+    o, operm, ostart = cpu.build_cells(wl.grid, s)
+    assert np.array_equal(sim.perm.cpu().numpy().view(np.uint32), operm)
+    assert np.array_equal(h["hash"], o.hash)
+    assert np.array_equal(h["id"], o.id)
+    assert np.array_equal(sim.start.cpu().numpy().view(np.uint32), ostart)
+    assert np.array_equal(h["x"], o.x)
+    assert np.array_equal(h["E"], o.E)
+    if prec == FP64:
+        assert np.array_equal(h["v"], o.v) and np.array_equal(h["m"], o.m)
+    else:
+        assert np.array_equal(h["v"], o.v.astype(np.float32).astype(np.float64))
+        # offsets from the bucket corner, rounded once to float
+        n = np.asarray(wl.grid["dims"])
+        c = np.stack([o.hash % n[0], (o.hash // n[0]) % n[1], o.hash // (n[0] * n[1])], axis=1)
+        ref = (o.x - np.asarray(wl.grid["origin"])) - c * wl.grid["cell"]
+        assert np.array_equal(h["off"], ref.astype(np.float32).astype(np.float64))
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("case", ["one", "cloud2049", "cube8000", "faces", "clamped", "dense", "lattice12"])
+def test_force_pass_matches_oracle(case, prec):
+    wl = CASES[case]()
+    print(f"[force] case={case} prec={prec} n={wl.n}", flush=True)
+    sim = _sim(wl, prec)
+    sim.build()
+    sim.interact()
+    torch.cuda.synchronize()
+    h = sim.A.host()
+    st = oracle_state(h, False)
+    start = cpu.cell_start(st.hash, cpu.ncells(wl.grid))
+    assert np.array_equal(sim.start.cpu().numpy().view(np.uint32), start)
+    ref = cpu.interact(wl.params, wl.grid, cpu.FORCE, st, st, start, True)
+    scale = cpu.interact_abs(wl.params, wl.grid, cpu.FORCE, st, st, start, True)
+    got = sim.rates.force().T.cpu().numpy()
+    assert_close_scaled(got, ref, scale, TOL_RATE[prec], f"{case} rates")
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_force_pass_conserves(prec):
+    wl = S.jittered_lattice(14, seed=56, jitter=0.3, rho_sigma=0.02, v_sigma=1.0)
+    sim = _sim(wl, prec)
+    sim.build()
+    sim.interact()
+    torch.cuda.synchronize()
+    got = sim.rates.force().T.cpu().numpy()
+    st = oracle_state(sim.A.host(), False)
+    start = cpu.cell_start(st.hash, cpu.ncells(wl.grid))
+    scale = cpu.interact_abs(wl.params, wl.grid, cpu.FORCE, st, st, start, True).sum(0)
+    tot = got.sum(0)
+    lim = 1e-12 if prec == FP64 else 2e-6
+    for k in range(5):
+        assert abs(tot[k]) <= lim * scale[k], (k, tot[k], scale[k])
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_gradient_pass_matches_oracle(prec):
+    wl = S.solid_block(8, seed=57, s_sigma=1e7)
+    sim = _sim(wl, prec)
+    sim.build()
+    sim.interact(pass_=1)
+    torch.cuda.synchronize()
+    st = oracle_state(sim.A.host(), True)
+    start = cpu.cell_start(st.hash, cpu.ncells(wl.grid))
+    ref = cpu.interact(wl.params, wl.grid, cpu.GRADIENT, st, st, start, True)
+    scale = cpu.interact_abs(wl.params, wl.grid, cpu.GRADIENT, st, st, start, True)
+    got = sim.rates.grad().T.cpu().numpy()
+    assert_close_scaled(got, ref, scale, TOL_RATE[prec], "velocity gradient")
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_solid_force_pass_matches_oracle(prec):
+    wl = S.solid_block(8, seed=58, s_sigma=1e8)
+    sim = _sim(wl, prec)
+    sim.build()
+    sim.interact()
+    torch.cuda.synchronize()
+    st = oracle_state(sim.A.host(), True)
+    start = cpu.cell_start(st.hash, cpu.ncells(wl.grid))
+    ref = cpu.interact(wl.params, wl.grid, cpu.FORCE, st, st, start, True)
+    scale = cpu.interact_abs(wl.params, wl.grid, cpu.FORCE, st, st, start, True)
+    got = sim.rates.force().T.cpu().numpy()
+    assert_close_scaled(got, ref, scale, TOL_RATE[prec], "solid rates")
+
+
+def _step_vs_oracle(wl, prec, nsteps, tol):
+    """Run nsteps on the GPU; before each, run the oracle one step from the
+    GPU's own state with the GPU's dt and compare in array order."""
+    sim = _sim(wl, prec)
+    solid = wl.S is not None
+    worst = {}
+    for k in range(nsteps):
+        torch.cuda.synchronize()
+        h0 = sim.A.host()
+        dt = float(sim.diag[sim.cur, 0].cpu()) if sim.fixed is None else float(sim.fixed.cpu())
+        st = oracle_state(h0, solid)
+        dts, odiag = cpu.run(wl.params, wl.grid, st, 1, dts_in=np.array([dt]))
+        sim.step()
+        torch.cuda.synchronize()
+        h1 = sim.A.host()
+        assert np.array_equal(h1["id"], st.id), f"step {k}: permutation differs"
+        fields = ("x", "v", "m", "w", "rho", "p", "c", "E") + (("S", "ep") if solid else ())
+        sc = {"p": np.abs(st.p).max() + pressure_scale(wl.params)}
+        if solid:
+            sc["S"] = np.abs(st.S).max() + wl.params["G"] * 1e-3
+            sc["ep"] = max(np.abs(st.ep).max(), 1e-6)
+        err = field_errors(h1, st, fields, sc)
+        for f, e in err.items():
+            worst[f] = max(worst.get(f, 0.0), e)
+            assert e <= tol, f"step {k} field {f}: rel err {e:.3e} > {tol}"
+        gd = sim.diagnostics()
+        assert gd[0] == pytest.approx(odiag[0], rel=tol * 10)
+    return worst
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_cube_steps_match_oracle_each_step(prec):
+    worst = _step_vs_oracle(S.c1_cube(), prec, 10, TOL_STEP[prec])
+    print("worst per-field error over 10 steps:", worst)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_solid_steps_match_oracle_each_step(prec):
+    wl = S.solid_block(8, seed=59)
+    worst = _step_vs_oracle(wl, prec, 3, TOL_STEP[prec])
+    print("solid worst per-field error:", worst)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_gravity_walls_step(prec):
+    wl = S.c2_column(nx=10, ny=8, nz=20, dx=5.4e-3, box=(0.1, 0.05, 0.12))
+    _step_vs_oracle(wl, prec, 4, TOL_STEP[prec])
+
+
+def test_steps_are_deterministic():
+    outs = []
+    for _ in range(2):
+        sim = _sim(S.c1_cube(), FP32)
+        for _k in range(5):
+            sim.step()
+        torch.cuda.synchronize()
+        outs.append(sim.A.host())
+    for f in outs[0]:
+        assert np.array_equal(outs[0][f], outs[1][f]), f
+
+
+@pytest.mark.parametrize("layout", ["slab", "mixed"])
+@pytest.mark.parametrize("prec", PRECS)
+def test_share_pass_matches_oracle(layout, prec):
+    from paper_2310_03596_amd.sim import SharePass
+    loc, rem = S.c4_share(layout, seed=60, nx=40, ny=18, nz=16, split_ix=30)
+    print(f"[share] layout={layout} prec={prec} local={loc.n} remote={rem.n}", flush=True)
+    sp = SharePass(loc, rem, prec)
+    sp.run()
+    torch.cuda.synchronize()
+    hl, hr = sp.LB.host(), sp.RB.host()
+    nb = int(sp.nb.cpu()[0])
+    sl, sr = oracle_state(hl, False), oracle_state(hr, False)
+    lstart = cpu.cell_start(sl.hash, cpu.ncells(loc.grid))
+    rstart = cpu.cell_start(sr.hash, cpu.ncells(loc.grid))
+    assert np.array_equal(sp.rstart.cpu().numpy().view(np.uint32), rstart)
+    comm, bidx = cpu.mark_boundary(loc.grid, sl.hash, rstart)
+    assert nb == bidx.size
+    assert np.array_equal(sp.comm.cpu().numpy().view(np.uint32), comm)
+    assert np.array_equal(sp.bidx.cpu().numpy().view(np.uint32)[:nb], bidx)
+    flags = brute.boundary_flags(loc.grid, sl.x, sr.x)
+    assert np.array_equal(np.flatnonzero(flags), bidx)
+    # packed payload = boundary particles, bit for bit
+    hp = sp.payload.host()
+    for f in ("x", "v", "m", "w", "rho", "p", "c", "E", "id", "hash"):
+        assert np.array_equal(hp[f][:nb], hl[f][bidx]), f
+    # LL then LR accumulate the same sums as the oracle's two passes
+    ref = cpu.interact(loc.params, loc.grid, cpu.FORCE, sl, sl, lstart, True)
+    ref = cpu.interact(loc.params, loc.grid, cpu.FORCE, sl, sr, rstart, False, rates=ref, tidx=bidx)
+    scale = cpu.interact_abs(loc.params, loc.grid, cpu.FORCE, sl, sl, lstart, True)
+    scale += cpu.interact_abs(loc.params, loc.grid, cpu.FORCE, sl, sr, rstart, False)
+    got = sp.rates.force().T.cpu().numpy()
+    assert_close_scaled(got, ref, scale, TOL_RATE[prec], f"share {layout}")
+    # particles with no remote bucket nearby have no remote neighbour
+    pi, pj = cpu.neighbors(loc.params, loc.grid, sl, sr, rstart, False)
+    assert set(np.unique(pi).tolist()) <= set(bidx.tolist())
+
+
+def test_boundary_capacity_overflow_reports_true_count():
+    from paper_2310_03596_amd import _lib as L
+    from paper_2310_03596_amd.sim import SharePass
+    from paper_2310_03596_amd.state import cells_struct, stream_handle
+    loc, rem = S.c4_share("mixed", seed=61, nx=30, ny=12, nz=12, split_ix=24)
+    sp = SharePass(loc, rem, FP32)
+    sp.build()
+    cap = 17
+    sentinel = torch.full((sp.nl,), -7, dtype=torch.int32, device="cuda")
+    L.sph_mark_boundary(sp.grid, sp.LB.struct(), cells_struct(sp.rstart, sp.nc), sp.comm.data_ptr(),
+                        sentinel.data_ptr(), cap, sp.nb.data_ptr(), sp.ws.data_ptr(), sp.ws_bytes,
+                        stream_handle())
+    torch.cuda.synchronize()
+    nb = int(sp.nb.cpu()[0])
+    assert nb > cap
+    got = sentinel.cpu().numpy()
+    assert np.all(got[cap:] == -7)
+    comm = sp.comm.cpu().numpy().view(np.uint32)
+    assert np.array_equal(got[:cap], np.flatnonzero(comm != cpu.ncells(loc.grid))[:cap])
