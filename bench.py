@@ -1,0 +1,187 @@
+#!/usr/bin/env python3
+"""Throughput of the particle-decomposition SPH hot path on one MI355X.
+
+Workload: 3D fluid column collapse, 810,448 particles (water lattice
+74 x 74 x 148 at dx = 5.4e-3 m in a 1.6 x 0.4 x 0.8 m reflective box),
+h = 1.3 dx, rho0 = 1000, c0 = 40, gravity -9.81 z, CFL 0.3, hydrostatic
+start.  One step = bucket hash + radix sort + reorder + bucket table
+(Section I), local FORCE pass (Section II step e) and the update (step g);
+inputs are resident in HBM before the timed region.
+
+Prints one JSON line: particle-updates/s of the FP32 split-precision form
+(value) and of the plain FP64 form, the roofline of the dominant kernel
+(the FORCE pass) from HIP events around its launches, and the FP64 CPU
+oracle timed on a bounded sample together with the per-field error of both
+GPU forms against it.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "particle-updates/s (FP32 vs FP64 form, stated error) + adjoint/forward ratio"
+# Algorithmic flops of the fluid FORCE pass, counted from the kernel source
+# (FMA = 2, add/mul/sqrt/rcp/rsq = 1): per candidate source (position
+# difference + squared distance) and per pair within 2h (pair terms +
+# compensated accumulation of 6 rates).
+FLOPS_CAND = {1: 12, 0: 8}
+FLOPS_PAIR = {1: 139, 0: 103}
+PEAK_TFLOPS = {1: 157.3, 0: 78.6}      # MI355X vector FP32 (published) / FP64
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--fp64-steps", type=int, default=None, help="timed steps of the FP64 form (default: --steps)")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the CPU oracle sample")
+    ap.add_argument("--only", choices=["fp32", "fp64", "both"], default="both")
+    return ap.parse_args()
+
+
+def time_form(wl, prec, steps, warmup):
+    import torch
+    from paper_2310_03596_amd.sim import Sim
+
+    sim = Sim(wl, prec)
+    for _ in range(warmup):
+        sim.step()
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    t0 = time.perf_counter()
+    for k in range(steps):
+        sim.step(force_events=evs[k])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    force_ms = sum(a.elapsed_time(b) for a, b in evs) / max(steps, 1)
+    cand, pairs = sim.count_pairs()
+    flops = cand * FLOPS_CAND[prec] + pairs * FLOPS_PAIR[prec]
+    return {
+        "value": wl.n * steps / wall,
+        "ms_per_step": 1e3 * wall / steps,
+        "force_ms": force_ms,
+        "candidates": cand,
+        "pairs": pairs,
+        "flops_per_launch": flops,
+        "force_tflops": flops / (force_ms * 1e-3) / 1e12,
+        "pair_evals_per_s": pairs / (force_ms * 1e-3),
+        "diag": sim.diagnostics().tolist(),
+    }
+
+
+def cpu_leg(wl, budget_s):
+    """FP64 oracle from the initial state for a bounded number of steps, then
+    both GPU forms on the same dt schedule; per-field error by particle id."""
+    import numpy as np
+    import torch
+    from oracle import cpu
+    from paper_2310_03596_amd.sim import Sim
+
+    st = cpu.State.from_workload(wl)
+    t0 = time.perf_counter()
+    dts1, _ = cpu.run(wl.params, wl.grid, st, 1)
+    t1 = time.perf_counter() - t0
+    more = max(0, min(49, int(budget_s / max(t1, 1e-3)) - 1))
+    t0 = time.perf_counter()
+    # continuing run: its first dt is the EOS-stage dt of the current state,
+    # which equals the previous step's next dt, so the schedule is unbroken
+    dts2, _ = cpu.run(wl.params, wl.grid, st, more) if more else (np.zeros(0), None)
+    tm = time.perf_counter() - t0
+    nsteps = 1 + more
+    dts_all = np.concatenate([dts1, dts2])
+    t_total = t1 + tm
+    ref = st.by_id()
+    errs = {}
+    for name, prec in (("fp32_split", 1), ("fp64", 0)):
+        sim = Sim(wl, prec)
+        sim.run(nsteps, dts=dts_all)
+        torch.cuda.synchronize()
+        g = sim.state_by_id()
+        e = {}
+        for f, gf in (("x", "x"), ("v", "v"), ("rho", "rho"), ("E", "E"), ("m", "m")):
+            a = np.asarray(g[gf], dtype=np.float64)
+            b = np.asarray(getattr(ref, f), dtype=np.float64)
+            e[f] = float(np.abs(a - b).max() / np.abs(b).max())
+        B = wl.params["rho0"] * wl.params["c0"] ** 2
+        e["p_over_rho0c0^2"] = float(np.abs(g["p"] - ref.p).max() / B)
+        errs[name] = e
+    return {
+        "value": wl.n * nsteps / t_total,
+        "unit": "particle-updates/s",
+        "cores": cpu.num_threads(),
+        "kind": "oracle",
+        "sample": f"first {nsteps} steps of the same 810448-particle column from its initial state "
+                  f"(FP64 C oracle, OpenMP over targets), {t_total:.1f} s",
+        "steps": nsteps,
+    }, {"steps": nsteps, "max_abs_err_over_max_abs_ref": errs}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
+              "the multi-GPU exchange is not built in this path", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import sph_synth as S
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    wl = S.c2_column()
+    out = {}
+    res = {}
+    if args.only in ("fp32", "both"):
+        res[1] = time_form(wl, 1, args.steps, args.warmup)
+    if args.only in ("fp64", "both"):
+        res[0] = time_form(wl, 0, args.fp64_steps or args.steps, args.warmup)
+    main_prec = 1 if 1 in res else 0
+    r = res[main_prec]
+    out.update({
+        "metric": METRIC,
+        "value": r["value"],
+        "unit": "particle-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if main_prec == 1 else "f64",
+        "data": "synthetic",
+        "config": {"workload": "fluid column collapse 3D: 74x74x148 water lattice, dx=5.4e-3 m, "
+                               "box 1.6x0.4x0.8 m, h=1.3dx, rho0=1000, c0=40, g=-9.81 z, CFL 0.3",
+                   "n_particles": wl.n, "grid": wl.grid["dims"],
+                   "form": "FP32 split (bucket index + float offset, compensated pair sums; x, E in FP64)"
+                   if main_prec == 1 else "plain FP64"},
+        "roofline": {"bound": "alu", "kernel": "FORCE pass (k_interact)",
+                     "achieved": r["force_tflops"], "peak": PEAK_TFLOPS[main_prec], "unit": "TFLOP/s",
+                     "frac": r["force_tflops"] / PEAK_TFLOPS[main_prec], "traffic": None,
+                     "avg_launch_ms": r["force_ms"], "flops_per_launch": r["flops_per_launch"],
+                     "units_per_launch": {"candidates": r["candidates"], "pairs_within_2h": r["pairs"]}},
+        "pair_evals_per_s": r["pair_evals_per_s"],
+    })
+    if 0 in res and 1 in res:
+        out["fp64_form"] = {"value": res[0]["value"], "ms_per_step": res[0]["ms_per_step"],
+                            "steps": args.fp64_steps or args.steps, "force_ms": res[0]["force_ms"],
+                            "force_tflops": res[0]["force_tflops"],
+                            "frac_of_fp64_peak": res[0]["force_tflops"] / PEAK_TFLOPS[0]}
+        out["fp32_over_fp64"] = res[1]["value"] / res[0]["value"]
+    if not args.no_cpu:
+        cb, err = cpu_leg(wl, args.cpu_seconds)
+        out["cpu_baseline"] = cb
+        out["error_vs_oracle"] = err
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -207,6 +207,17 @@ int sph_interact(const sph_params *params, const sph_grid *grid, int pass,
 int sph_integrate(const sph_params *params, int stage, sph_particles *p, const sph_rates *rates,
                   const double *dt_dev, double *diag_dev, void *ws, size_t ws_bytes, void *stream);
 
+/* Work count of one interaction pass (steps e and f), for throughput and
+ * roofline figures: adds to counts_dev[0] the number of candidate sources
+ * (particles in the 27 surrounding buckets, j != i in a local-local pass) and
+ * to counts_dev[1] the number of pairs with |x_j - x_i| < 2h, over the same
+ * targets and with the same predicate as sph_interact in params->prec.
+ * counts_dev: two uint64 on the device, not cleared.  Errors: SPH_ERR_ARG. */
+int sph_count_pairs(const sph_params *params, const sph_grid *grid, const sph_particles *targets,
+                    const uint32_t *target_idx, const uint32_t *n_targets_dev,
+                    const sph_particles *sources, sph_cells source_cells, uint64_t *counts_dev,
+                    void *stream);
+
 /* Adjoint of the local-local FORCE pass (step e) of a fluid.  With rates_bar
  * the cotangents of the rates (hi only), accumulates into `bar` the
  * cotangents of x, v, omega, rho, p, c and e of every particle of the

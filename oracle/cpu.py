@@ -66,6 +66,7 @@ def _declare(L):
     L.or_interact.argtypes = [C.POINTER(OParams), C.POINTER(OGrid), C.c_int, C.POINTER(OState),
                               vp, C.c_int64, C.POINTER(OState), vp, C.c_int, vp, vp]
     L.or_interact_abs.argtypes = L.or_interact.argtypes
+    L.or_interact_peak.argtypes = L.or_interact.argtypes
     L.or_neighbors.argtypes = [C.POINTER(OParams), C.POINTER(OGrid), C.POINTER(OState),
                                C.POINTER(OState), vp, C.c_int, vp, vp, C.c_int64]
     L.or_neighbors.restype = C.c_int64
@@ -74,6 +75,12 @@ def _declare(L):
     L.or_run.argtypes = [C.POINTER(OParams), C.POINTER(OGrid), C.POINTER(OState), C.c_int,
                          C.c_double, vp, vp, vp]
     L.or_run.restype = C.c_int
+    L.or_num_threads.restype = C.c_int
+
+
+def num_threads() -> int:
+    """OpenMP threads the oracle's parallel loops use."""
+    return int(lib().or_num_threads())
 
 
 def _ptr(a):
@@ -290,17 +297,19 @@ def interact(params: dict, grid: dict, pass_: int, tgt: State, src: State, src_s
 
 
 def interact_abs(params: dict, grid: dict, pass_: int, tgt: State, src: State, src_start,
-                 self_pass: bool, tidx=None):
-    """Per-target sums of |pair term| (the round-off scale of each rate)."""
+                 self_pass: bool, tidx=None, peak: bool = False):
+    """Per-target sums of |pair term| (the round-off scale of each rate); with
+    peak=True every term is rescaled to the kernel's peak strength F_max / F."""
     P = params_struct(params)
     g = grid_struct(grid)
     out = np.zeros((tgt.n, 6 if pass_ == FORCE else 9))
     ti = None if tidx is None else np.ascontiguousarray(tidx, dtype=np.uint32)
     nt = tgt.n if ti is None else ti.shape[0]
     a, b = tgt.struct(), src.struct()
-    lib().or_interact_abs(C.byref(P), C.byref(g), pass_, C.byref(a), _ptr(ti), nt, C.byref(b),
-                          _ptr(np.ascontiguousarray(src_start, dtype=np.uint32)), int(self_pass),
-                          _ptr(out) if pass_ == FORCE else None, _ptr(out) if pass_ == GRADIENT else None)
+    fn = lib().or_interact_peak if peak else lib().or_interact_abs
+    fn(C.byref(P), C.byref(g), pass_, C.byref(a), _ptr(ti), nt, C.byref(b),
+       _ptr(np.ascontiguousarray(src_start, dtype=np.uint32)), int(self_pass),
+       _ptr(out) if pass_ == FORCE else None, _ptr(out) if pass_ == GRADIENT else None)
     return out
 
 

@@ -36,9 +36,23 @@
 #include <stdlib.h>
 #include <string.h>
 
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
 #ifndef M_PI
 #define M_PI 3.14159265358979323846
 #endif
+
+/* Threads the OpenMP loops use (1 without OpenMP). */
+int or_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
 
 typedef struct {
     double o[3];
@@ -295,6 +309,62 @@ void or_pair_grad(const op_t *P, const double d[3], const double vi[3], const do
         for (int b = 0; b < 3; ++b) out[3 * a + b] = wj * (vj[a] - vi[a]) * g[b];
 }
 
+/* ------------------------------------------------- round-off magnitude bounds */
+
+/* Sum of |entries| of a symmetric stress (off-diagonals twice): bounds |S n|_k. */
+static double sym_abs(const double *s)
+{
+    return (fabs(s[0]) + fabs(s[1]) + fabs(s[2])) + 2.0 * (fabs(s[3]) + fabs(s[4]) + fabs(s[5]));
+}
+
+/* The FORCE terms evaluated on magnitudes: every input replaced by its
+ * absolute value, every difference by a sum, and every component of n by 1.
+ * Standard forward-error analysis bounds the rounding error of an evaluation
+ * of or_pair by (operation count) * (unit round-off) * this value, and a
+ * perturbation of the direction n or of the velocities by the same relative
+ * amount; it cannot vanish through cancellation the way the terms can. */
+static void pair_bound(const op_t *P, double r, const double vi[3], const double vj[3], double wi,
+                       double wj, double rhoi, double rhoj, double pi_, double pj, double ci,
+                       double cj, double ei, double ej, const double *Si, const double *Sj,
+                       double out[6])
+{
+    double F = or_kernel_F(r, P->h);
+    double ui = fabs(vi[0]) + fabs(vi[1]) + fabs(vi[2]);
+    double uj = fabs(vj[0]) + fabs(vj[1]) + fabs(vj[2]);
+    double rb = 0.5 * (rhoi + rhoj), cb = 0.5 * (ci + cj);
+    double Z = rb * cb;
+    double si = Si ? sym_abs(Si) : 0.0, sj = Sj ? sym_abs(Sj) : 0.0;
+    double du = fabs(P->beta) * ((fabs(pi_) + si) + (fabs(pj) + sj)) / (2.0 * Z);
+    double ps = 0.5 * (fabs(pi_) + fabs(pj)) + fabs(P->beta) * Z * (ui + uj) * 0.5;
+    double vs[3];
+    for (int a = 0; a < 3; ++a) vs[a] = 0.5 * (fabs(vi[a]) + fabs(vj[a])) + du;
+    double Es = 0.5 * (fabs(ei) + fabs(ej)) + 0.5 * ((vs[0] * vs[0] + vs[1] * vs[1]) + vs[2] * vs[2]);
+    double A = 2.0 * fabs(wi) * fabs(wj);
+    double Phi = rb * du * F;
+    double t = ps * F + F * 0.5 * (si + sj);
+    out[0] = A * Phi;
+    for (int a = 0; a < 3; ++a) out[1 + a] = A * (Phi * vs[a] + t);
+    out[4] = A * (Phi * Es + t * ((vs[0] + vs[1]) + vs[2]));
+    out[5] = fabs(wi) * fabs(wj) * F * ((fabs(vj[0]) + fabs(vi[0])) + (fabs(vj[1]) + fabs(vi[1])) +
+                                        (fabs(vj[2]) + fabs(vi[2])));
+}
+
+static void pair_grad_bound(const op_t *P, double r, const double vi[3], const double vj[3], double wj,
+                            double out[9])
+{
+    double F = or_kernel_F(r, P->h);
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) out[3 * a + b] = fabs(wj) * (fabs(vj[a]) + fabs(vi[a])) * F;
+}
+
+/* F_max / F(r): rescales a pair term to the kernel's peak strength
+ * (F peaks at q = 2/3 with F_max = 1 / (pi h^4)). */
+static double peak_factor(double h, double r2)
+{
+    double Fmax = 1.0 / (M_PI * h * h * h) / h;
+    return Fmax / or_kernel_F(sqrt(r2), h);
+}
+
 /* -------------------------------------------------------- interaction pass */
 
 /*
@@ -339,14 +409,24 @@ static void interact_impl(const op_t *P, const og_t *g, int pass, const os_t *tg
                         if (pass == 0) {
                             double ej = sr->E[j] - 0.5 * ((vj[0] * vj[0] + vj[1] * vj[1]) + vj[2] * vj[2]);
                             double o[6];
-                            or_pair(P, d, vi, vj, tg->w[i], sr->w[j], tg->rho[i], sr->rho[j], tg->p[i],
-                                    sr->p[j], tg->c[i], sr->c[j], ei, ej,
-                                    solid ? tg->S + 6 * i : NULL, solid ? sr->S + 6 * (int64_t)j : NULL, o);
-                            for (int k = 0; k < 6; ++k) acc[k] += absval ? fabs(o[k]) : o[k];
+                            const double *Si = solid ? tg->S + 6 * i : NULL;
+                            const double *Sj = solid ? sr->S + 6 * (int64_t)j : NULL;
+                            if (absval)
+                                pair_bound(P, sqrt(r2), vi, vj, tg->w[i], sr->w[j], tg->rho[i], sr->rho[j],
+                                           tg->p[i], sr->p[j], tg->c[i], sr->c[j], ei, ej, Si, Sj, o);
+                            else
+                                or_pair(P, d, vi, vj, tg->w[i], sr->w[j], tg->rho[i], sr->rho[j], tg->p[i],
+                                        sr->p[j], tg->c[i], sr->c[j], ei, ej, Si, Sj, o);
+                            double f = absval == 2 ? peak_factor(P->h, r2) : 1.0;
+                            for (int k = 0; k < 6; ++k) acc[k] += o[k] * f;
                         } else {
                             double o[9];
-                            or_pair_grad(P, d, vi, vj, sr->w[j], o);
-                            for (int k = 0; k < 9; ++k) acc[k] += absval ? fabs(o[k]) : o[k];
+                            if (absval)
+                                pair_grad_bound(P, sqrt(r2), vi, vj, sr->w[j], o);
+                            else
+                                or_pair_grad(P, d, vi, vj, sr->w[j], o);
+                            double f = absval == 2 ? peak_factor(P->h, r2) : 1.0;
+                            for (int k = 0; k < 9; ++k) acc[k] += o[k] * f;
                         }
                     }
                 }
@@ -364,13 +444,23 @@ void or_interact(const op_t *P, const og_t *g, int pass, const os_t *tg, const u
     interact_impl(P, g, pass, tg, tidx, nt, sr, sstart, self, rates, L, 0);
 }
 
-/* Same sums of |term| per component: the scale against which round-off in a
- * pair sum is judged. */
+/* Per-target sums of the magnitude bounds (pair_bound): the scale against
+ * which round-off in a pair sum is judged. */
 void or_interact_abs(const op_t *P, const og_t *g, int pass, const os_t *tg, const uint32_t *tidx,
                      int64_t nt, const os_t *sr, const uint32_t *sstart, int self, double *rates,
                      double *L)
 {
     interact_impl(P, g, pass, tg, tidx, nt, sr, sstart, self, rates, L, 1);
+}
+
+/* The same bounds with every pair at the kernel's peak strength (F_max / F).
+ * Near the support edge F ~ (2 - q)^2 amplifies any rounding of q or r
+ * relative to the (vanishing) term itself; this scale bounds that. */
+void or_interact_peak(const op_t *P, const og_t *g, int pass, const os_t *tg, const uint32_t *tidx,
+                      int64_t nt, const os_t *sr, const uint32_t *sstart, int self, double *rates,
+                      double *L)
+{
+    interact_impl(P, g, pass, tg, tidx, nt, sr, sstart, self, rates, L, 2);
 }
 
 /* Every ordered pair (i, j) the FORCE pass visits with r < 2h; returns the

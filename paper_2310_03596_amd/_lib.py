@@ -54,7 +54,7 @@ class SphAdjoint(C.Structure):
 
 
 EXPORTS = ("sph_version", "sph_last_error", "sph_workspace_size", "sph_build_cells", "sph_mark_boundary",
-           "sph_pack_boundary", "sph_interact", "sph_integrate", "sph_interact_adjoint",
+           "sph_pack_boundary", "sph_interact", "sph_count_pairs", "sph_integrate", "sph_interact_adjoint",
            "sph_integrate_adjoint", "sph_permute_adjoint")
 
 _lib = None
@@ -87,6 +87,8 @@ def load():
     L.sph_pack_boundary.argtypes = [P(SphParticles), _vp, _vp, P(SphParticles), _vp]
     L.sph_interact.argtypes = [P(SphParams), P(SphGrid), C.c_int, P(SphParticles), _vp, _vp,
                                P(SphParticles), SphCells, C.c_int, P(SphRates), _vp]
+    L.sph_count_pairs.argtypes = [P(SphParams), P(SphGrid), P(SphParticles), _vp, _vp, P(SphParticles),
+                                  SphCells, _vp, _vp]
     L.sph_integrate.argtypes = [P(SphParams), C.c_int, P(SphParticles), P(SphRates), _vp, _vp, _vp,
                                 C.c_size_t, _vp]
     L.sph_interact_adjoint.argtypes = [P(SphParams), P(SphGrid), P(SphParticles), SphCells, P(SphRates),
@@ -142,6 +144,12 @@ def sph_interact(params, grid, pass_, targets, tidx_ptr, nt_ptr, sources, source
     return check("sph_interact", load().sph_interact(C.byref(params), C.byref(grid), pass_, C.byref(targets),
                                                      tidx_ptr, nt_ptr, C.byref(sources), source_cells,
                                                      zero_first, C.byref(rates), stream))
+
+
+def sph_count_pairs(params, grid, targets, tidx_ptr, nt_ptr, sources, source_cells, counts_ptr, stream):
+    return check("sph_count_pairs", load().sph_count_pairs(C.byref(params), C.byref(grid), C.byref(targets),
+                                                           tidx_ptr, nt_ptr, C.byref(sources), source_cells,
+                                                           counts_ptr, stream))
 
 
 def sph_integrate(params, stage, p, rates, dt_ptr, diag_ptr, ws_ptr, ws_bytes, stream):

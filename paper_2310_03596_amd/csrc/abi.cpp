@@ -249,6 +249,29 @@ int sph_interact(const sph_params *params, const sph_grid *grid, int pass, const
                       "sph_interact");
 }
 
+int sph_count_pairs(const sph_params *params, const sph_grid *grid, const sph_particles *targets,
+                    const uint32_t *target_idx, const uint32_t *n_targets_dev, const sph_particles *sources,
+                    sph_cells source_cells, uint64_t *counts_dev, void *stream)
+{
+    Grid g;
+    Params P;
+    if (!make_grid(grid, g) || !make_params(params, grid, P)) return SPH_ERR_ARG;
+    if (!targets || !sources) return fail(SPH_ERR_ARG, "targets/sources is NULL");
+    if (targets->prec != params->prec || sources->prec != params->prec)
+        return fail(SPH_ERR_ARG, "particle precision does not match params.prec");
+    if (!check_particles(targets, "targets", true, false) || !check_particles(sources, "sources", true, false))
+        return SPH_ERR_ARG;
+    if (target_idx && !n_targets_dev) return fail(SPH_ERR_ARG, "target_idx given without n_targets_dev");
+    if (!source_cells.start || source_cells.ncells != g.ncells)
+        return fail(SPH_ERR_ARG, "source bucket table missing or not on this grid");
+    if (!counts_dev) return fail(SPH_ERR_ARG, "counts_dev is NULL");
+    if (targets->n == 0) return SPH_OK;
+    bool self = targets->hash == sources->hash;
+    return hip_status(launch_count_pairs(P, g, params->prec, *targets, target_idx, n_targets_dev, *sources,
+                                         source_cells.start, self, counts_dev, (hipStream_t)stream),
+                      "sph_count_pairs");
+}
+
 int sph_integrate(const sph_params *params, int stage, sph_particles *p, const sph_rates *rates,
                   const double *dt_dev, double *diag_dev, void *ws, size_t ws_bytes, void *stream)
 {

@@ -157,6 +157,14 @@ __global__ __launch_bounds__(kBlock) void k_downsweep(const uint32_t *__restrict
     }
 }
 
+// Float offset from the bucket corner, ((x - o) - c L) evaluated in IEEE
+// double without contraction, rounded once to float.
+__device__ inline float corner_offset(double x, double o, uint32_t c, double L)
+{
+#pragma clang fp contract(off)
+    return (float)((x - o) - (double)c * L);
+}
+
 template <typename real>
 __global__ __launch_bounds__(kBlock) void k_gather(Grid g, PV<real> in, PV<real> out,
                                                    const uint32_t *__restrict__ keys,
@@ -193,9 +201,9 @@ __global__ __launch_bounds__(kBlock) void k_gather(Grid g, PV<real> in, PV<real>
         uint32_t cx = h % (uint32_t)g.nx;
         uint32_t cy = (h / (uint32_t)g.nx) % (uint32_t)g.ny;
         uint32_t cz = h / ((uint32_t)g.nx * (uint32_t)g.ny);
-        out.off[0][k] = (float)((x[0] - g.o[0]) - (double)cx * g.L);
-        out.off[1][k] = (float)((x[1] - g.o[1]) - (double)cy * g.L);
-        out.off[2][k] = (float)((x[2] - g.o[2]) - (double)cz * g.L);
+        out.off[0][k] = corner_offset(x[0], g.o[0], cx, g.L);
+        out.off[1][k] = corner_offset(x[1], g.o[1], cy, g.L);
+        out.off[2][k] = corner_offset(x[2], g.o[2], cz, g.L);
     }
 }
 

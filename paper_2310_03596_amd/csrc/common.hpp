@@ -181,6 +181,9 @@ hipError_t launch_interact(const Params &P, const Grid &g, int prec, int pass, c
                            const uint32_t *tidx, const uint32_t *nt, const sph_particles &sr,
                            const uint32_t *sstart, bool self, int zero_first, const sph_rates &r,
                            hipStream_t s);
+hipError_t launch_count_pairs(const Params &P, const Grid &g, int prec, const sph_particles &tg,
+                              const uint32_t *tidx, const uint32_t *nt, const sph_particles &sr,
+                              const uint32_t *sstart, bool self, uint64_t *counts, hipStream_t s);
 hipError_t launch_integrate(const Params &P, int prec, int stage, const sph_particles &p,
                             const sph_rates &r, const double *dt, double *diag, const Workspace &ws,
                             hipStream_t s);

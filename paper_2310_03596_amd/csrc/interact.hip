@@ -151,6 +151,81 @@ __global__ __launch_bounds__(kBlock) void k_interact(Params P, Grid g, PV<real> 
     }
 }
 
+// Candidates and hits of one pass, same traversal and predicate as k_interact.
+template <typename real, bool SELF>
+__global__ __launch_bounds__(kBlock) void k_count(Params P, Grid g, PV<real> tg, const uint32_t *__restrict__ tidx,
+                                                  const uint32_t *__restrict__ ntdev, PV<real> sr,
+                                                  const uint32_t *__restrict__ sstart,
+                                                  unsigned long long *__restrict__ counts)
+{
+    constexpr bool SPLIT = sizeof(real) == 4;
+    uint32_t t = blockIdx.x * kBlock + threadIdx.x;
+    uint32_t nt = tg.n;
+    if (tidx) {
+        uint32_t c = *ntdev;
+        nt = c < nt ? c : nt;
+    }
+    unsigned long long cand = 0, hits = 0;
+    if (t < nt) {
+        const uint32_t i = tidx ? tidx[t] : t;
+        const real R2 = (real)P.R2;
+        const real Lf = SPLIT ? (real)g.Lf : real(0);
+        const uint32_t h = tg.hash[i];
+        const int cx = (int)(h % (uint32_t)g.nx);
+        const int cy = (int)((h / (uint32_t)g.nx) % (uint32_t)g.ny);
+        const int cz = (int)(h / ((uint32_t)g.nx * (uint32_t)g.ny));
+        const int x0 = cx > 0 ? cx - 1 : 0;
+        const int x1 = cx + 1 < g.nx ? cx + 1 : g.nx - 1;
+        double xi[3];
+        real oi[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            if constexpr (SPLIT)
+                oi[d] = tg.off[d][i];
+            else
+                xi[d] = tg.x[d][i];
+        }
+        for (int dz = -1; dz <= 1; ++dz) {
+            const int z = cz + dz;
+            if (z < 0 || z >= g.nz) continue;
+            for (int dy = -1; dy <= 1; ++dy) {
+                const int y = cy + dy;
+                if (y < 0 || y >= g.ny) continue;
+                const uint32_t row = (uint32_t)g.nx * ((uint32_t)y + (uint32_t)g.ny * (uint32_t)z);
+                const uint32_t jb = sstart[row + x0], je = sstart[row + x1 + 1];
+                const uint32_t sA = sstart[row + cx], sB = sstart[row + cx + 1];
+                const real ddy = (real)dy * Lf, ddz = (real)dz * Lf;
+                for (uint32_t j = jb; j < je; ++j) {
+                    if (SELF && j == i) continue;
+                    real d[3];
+                    if constexpr (SPLIT) {
+                        const int dcx = (int)(j >= sB) - (int)(j < sA);
+                        d[0] = (real)dcx * Lf + (sr.off[0][j] - oi[0]);
+                        d[1] = ddy + (sr.off[1][j] - oi[1]);
+                        d[2] = ddz + (sr.off[2][j] - oi[2]);
+                    } else {
+                        d[0] = sr.x[0][j] - xi[0];
+                        d[1] = sr.x[1][j] - xi[1];
+                        d[2] = sr.x[2][j] - xi[2];
+                    }
+                    ++cand;
+                    hits += (r2_of<real>(d) < R2) ? 1u : 0u;
+                }
+            }
+        }
+    }
+    // wavefront sums, one atomic per wavefront (integer: order-independent)
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) {
+        cand += __shfl_down(cand, off, kWave);
+        hits += __shfl_down(hits, off, kWave);
+    }
+    if ((threadIdx.x & (kWave - 1)) == 0) {
+        atomicAdd(&counts[0], cand);
+        atomicAdd(&counts[1], hits);
+    }
+}
+
 template <typename real, int PASS, bool SOLID>
 hipError_t go(const Params &P, const Grid &g, const sph_particles &tg, const uint32_t *tidx,
               const uint32_t *nt, const sph_particles &sr, const uint32_t *sstart, bool self, int zero_first,
@@ -182,6 +257,31 @@ hipError_t go_prec(const Params &P, const Grid &g, int pass, const sph_particles
 }
 
 }  // namespace
+
+hipError_t launch_count_pairs(const Params &P, const Grid &g, int prec, const sph_particles &tg,
+                              const uint32_t *tidx, const uint32_t *nt, const sph_particles &sr,
+                              const uint32_t *sstart, bool self, uint64_t *counts, hipStream_t s)
+{
+    uint32_t blocks = div_up(tg.n, kBlock);
+    if (blocks == 0) return hipSuccess;
+    auto *c = reinterpret_cast<unsigned long long *>(counts);
+    if (prec == SPH_FP64) {
+        if (self)
+            k_count<double, true><<<blocks, kBlock, 0, s>>>(P, g, view<double>(tg), tidx, nt, view<double>(sr),
+                                                            sstart, c);
+        else
+            k_count<double, false><<<blocks, kBlock, 0, s>>>(P, g, view<double>(tg), tidx, nt, view<double>(sr),
+                                                             sstart, c);
+    } else {
+        if (self)
+            k_count<float, true><<<blocks, kBlock, 0, s>>>(P, g, view<float>(tg), tidx, nt, view<float>(sr),
+                                                           sstart, c);
+        else
+            k_count<float, false><<<blocks, kBlock, 0, s>>>(P, g, view<float>(tg), tidx, nt, view<float>(sr),
+                                                            sstart, c);
+    }
+    return hipGetLastError();
+}
 
 hipError_t launch_interact(const Params &P, const Grid &g, int prec, int pass, const sph_particles &tg,
                            const uint32_t *tidx, const uint32_t *nt, const sph_particles &sr,

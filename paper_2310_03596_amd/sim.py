@@ -65,7 +65,9 @@ class Sim:
             return self.fixed.data_ptr()
         return self.diag[self.cur].data_ptr()    # [0] = next dt of the previous update
 
-    def step(self, dt_ptr=None):
+    def step(self, dt_ptr=None, force_events=None):
+        """One whole step.  force_events: optional (start, end) stream events
+        recorded around the FORCE pass (per-kernel timing)."""
         dtp = self.dt_ptr(dt_ptr)
         self.build()
         a = self.A.struct()
@@ -74,7 +76,11 @@ class Sim:
         if self.solid:
             L.sph_interact(self.params, self.grid, L.SPH_PASS_GRADIENT, a, None, None, a, self.cells, 1, r, st)
             L.sph_integrate(self.params, L.SPH_STAGE_STRESS, a, r, dtp, None, None, 0, st)
+        if force_events is not None:
+            force_events[0].record()
         L.sph_interact(self.params, self.grid, L.SPH_PASS_FORCE, a, None, None, a, self.cells, 1, r, st)
+        if force_events is not None:
+            force_events[1].record()
         nxt = 1 - self.cur
         L.sph_integrate(self.params, L.SPH_STAGE_MOTION, a, r, dtp, self.diag[nxt].data_ptr(), self.ws.data_ptr(),
                         self.ws_bytes, st)
@@ -89,6 +95,15 @@ class Sim:
         for k in range(nsteps):
             self.step(None if dts_dev is None else dts_dev[k].data_ptr())
         return dts_dev
+
+    def count_pairs(self) -> tuple[int, int]:
+        """(candidates, pairs within 2h) of the FORCE pass on the current state."""
+        c = torch.zeros(2, dtype=torch.int64, device=self.A.x.device)
+        a = self.A.struct()
+        L.sph_count_pairs(self.params, self.grid, a, None, None, a, self.cells, c.data_ptr(), stream_handle())
+        torch.cuda.synchronize()
+        v = c.cpu().numpy()
+        return int(v[0]), int(v[1])
 
     def diagnostics(self) -> np.ndarray:
         return self.diag[self.cur, :7].cpu().numpy()

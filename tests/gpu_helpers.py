@@ -41,6 +41,36 @@ def assert_close_scaled(got, ref, scale, rtol, what=""):
                              f"first {idx.tolist()} got {got[tuple(idx[0])]} ref {ref[tuple(idx[0])]}")
 
 
+# Round-off bound of a pair sum: rtol of B plus rtol_edge of B_peak.  B sums
+# the oracle's magnitude bound of every term (inputs in absolute value,
+# differences as sums, |n_k| -> 1), which bounds both the rounding of the
+# term's ~30 operations and a relative perturbation of positions or
+# velocities; B_peak is the same with every pair at the kernel's peak
+# strength, covering the support edge where F ~ (2 - q)^2 turns a one-ulp
+# change of q (FP64) or a float-offset rounding of r (FP32) into a large
+# relative change of a vanishing term, and a pair within round-off of r = 2h.
+RATE_TOL = {0: (1e-13, 1e-14), 1: (2e-5, 2e-6)}
+
+
+def rate_bound(params, grid, pass_, tg, src, start, self_pass, prec, tidx=None):
+    rtol, rtol_edge = RATE_TOL[prec]
+    a = cpu.interact_abs(params, grid, pass_, tg, src, start, self_pass, tidx=tidx)
+    b = cpu.interact_abs(params, grid, pass_, tg, src, start, self_pass, tidx=tidx, peak=True)
+    return rtol * a + rtol_edge * b
+
+
+def assert_within(got, ref, bound, what=""):
+    got = np.asarray(got, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    err = np.abs(got - ref)
+    bad = err > bound + 1e-300
+    if bad.any():
+        idx = np.argwhere(bad)[:5]
+        ratio = (err / np.maximum(bound, 1e-300)).max()
+        raise AssertionError(f"{what}: {bad.sum()} entries exceed the bound (worst err/bound {ratio:.3e}); "
+                             f"first {idx.tolist()} got {got[tuple(idx[0])]} ref {ref[tuple(idx[0])]}")
+
+
 def pressure_scale(params: dict) -> float:
     """Scale of the terms whose difference is p: gamma B for Tait (p = B (s^gamma - 1)
     cancels near s = 1), K for the linear solid EOS."""
