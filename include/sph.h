@@ -143,9 +143,11 @@ const char *sph_version(void);
 /* Description of the last error on the calling thread (static per thread). */
 const char *sph_last_error(void);
 
-/* Bytes of workspace the calls below need for up to n_max particles on
- * `grid`.  One workspace may be reused by consecutive calls on one stream. */
-size_t sph_workspace_size(const sph_grid *grid, uint32_t n_max);
+/* Bytes of workspace the calls below need for arrays of up to n_max
+ * particles of precision `prec` (sph_precision) and material `material`
+ * (sph_material).  One workspace may be reused by consecutive calls on one
+ * stream; calls that overlap on different streams need their own. */
+size_t sph_workspace_size(const sph_grid *grid, uint32_t n_max, int prec, int material);
 
 /* Steps (a) and the Section I bucket sort.  Hashes every particle of `in`
  * into `grid`, stable-radix-sorts by hash (ties keep the order of `in`),
@@ -188,12 +190,14 @@ int sph_pack_boundary(const sph_particles *local, const uint32_t *boundary_idx,
  * zero_first = 1 overwrites the rate entries of the targets, 0 adds to them
  * (the local-remote pass, step f, continues the compensated sum of step e).
  * Summation over j runs in ascending source index.  Both arrays must be
- * hash-sorted on `grid`.  Errors: SPH_ERR_ARG (precision or material
- * mismatch, missing field). */
+ * hash-sorted on `grid`.  The workspace receives a packed copy of the
+ * sources' pair inputs (sized by sph_workspace_size for sources->n).
+ * Errors: SPH_ERR_ARG (precision or material mismatch, missing field),
+ * SPH_ERR_WORKSPACE. */
 int sph_interact(const sph_params *params, const sph_grid *grid, int pass,
                  const sph_particles *targets, const uint32_t *target_idx,
                  const uint32_t *n_targets_dev, const sph_particles *sources, sph_cells source_cells,
-                 int zero_first, const sph_rates *rates, void *stream);
+                 int zero_first, const sph_rates *rates, void *ws, size_t ws_bytes, void *stream);
 
 /* Step (g).  stage = SPH_STAGE_MOTION: symplectic Euler update of mass,
  * momentum, volume, energy and position with gravity and reflective walls,

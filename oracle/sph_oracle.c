@@ -18,8 +18,9 @@
  *   mark        flag_i = some remote particle lies in the bucket of i or in one
  *               of the surrounding buckets; comm_i = flag ? hash_i : G, G = ncells;
  *               B = flagged particles in sorted order                 (Section II, step c)
- *   interact    per target i, sum over j != i with |x_i - x_j|^2 < (2h)^2 of the
- *               pair terms (Section II, steps e and f)
+ *   interact    per target i, sum over j with 0 < |x_i - x_j|^2 < (2h)^2 of the
+ *               pair terms (Section II, steps e and f); a coincident pair has
+ *               no direction and every term carries F(0) = 0, so it adds 0
  *   integrate   symplectic Euler, reflective walls, EOS              (Section II, step g)
  *
  * Every floating-point operation is IEEE binary64, built without FMA
@@ -404,7 +405,7 @@ static void interact_impl(const op_t *P, const og_t *g, int pass, const os_t *tg
                         const double *xj = sr->x + 3 * (int64_t)j;
                         double d[3] = {xj[0] - xi[0], xj[1] - xi[1], xj[2] - xi[2]};
                         double r2 = (d[0] * d[0] + d[1] * d[1]) + d[2] * d[2];
-                        if (!(r2 < R2)) continue;
+                        if (!(r2 < R2) || r2 == 0.0) continue;   /* coincident: no direction, F(0) = 0 */
                         const double *vj = sr->v + 3 * (int64_t)j;
                         if (pass == 0) {
                             double ej = sr->E[j] - 0.5 * ((vj[0] * vj[0] + vj[1] * vj[1]) + vj[2] * vj[2]);
@@ -488,7 +489,7 @@ int64_t or_neighbors(const op_t *P, const og_t *g, const os_t *tg, const os_t *s
                         const double *xj = sr->x + 3 * (int64_t)j;
                         double d[3] = {xj[0] - xi[0], xj[1] - xi[1], xj[2] - xi[2]};
                         double r2 = (d[0] * d[0] + d[1] * d[1]) + d[2] * d[2];
-                        if (!(r2 < R2)) continue;
+                        if (!(r2 < R2) || r2 == 0.0) continue;   /* coincident: no direction, F(0) = 0 */
                         if (k < cap) {
                             pi_out[k] = (uint32_t)i;
                             pj_out[k] = j;

@@ -78,7 +78,7 @@ def load():
     P = C.POINTER
     L.sph_version.restype = C.c_char_p
     L.sph_last_error.restype = C.c_char_p
-    L.sph_workspace_size.argtypes = [P(SphGrid), C.c_uint32]
+    L.sph_workspace_size.argtypes = [P(SphGrid), C.c_uint32, C.c_int, C.c_int]
     L.sph_workspace_size.restype = C.c_size_t
     L.sph_build_cells.argtypes = [P(SphGrid), P(SphParticles), P(SphParticles), _vp, SphCells, _vp,
                                   C.c_size_t, _vp]
@@ -86,7 +86,7 @@ def load():
                                     C.c_size_t, _vp]
     L.sph_pack_boundary.argtypes = [P(SphParticles), _vp, _vp, P(SphParticles), _vp]
     L.sph_interact.argtypes = [P(SphParams), P(SphGrid), C.c_int, P(SphParticles), _vp, _vp,
-                               P(SphParticles), SphCells, C.c_int, P(SphRates), _vp]
+                               P(SphParticles), SphCells, C.c_int, P(SphRates), _vp, C.c_size_t, _vp]
     L.sph_count_pairs.argtypes = [P(SphParams), P(SphGrid), P(SphParticles), _vp, _vp, P(SphParticles),
                                   SphCells, _vp, _vp]
     L.sph_integrate.argtypes = [P(SphParams), C.c_int, P(SphParticles), P(SphRates), _vp, _vp, _vp,
@@ -119,8 +119,8 @@ def sph_version() -> str:
     return load().sph_version().decode()
 
 
-def sph_workspace_size(grid: SphGrid, n_max: int) -> int:
-    return load().sph_workspace_size(C.byref(grid), n_max)
+def sph_workspace_size(grid: SphGrid, n_max: int, prec: int, material: int) -> int:
+    return load().sph_workspace_size(C.byref(grid), n_max, prec, material)
 
 
 def sph_build_cells(grid, inp, out, perm_ptr, cells, ws_ptr, ws_bytes, stream):
@@ -140,10 +140,10 @@ def sph_pack_boundary(local, bidx_ptr, nb_ptr, payload, stream):
 
 
 def sph_interact(params, grid, pass_, targets, tidx_ptr, nt_ptr, sources, source_cells, zero_first, rates,
-                 stream):
+                 ws_ptr, ws_bytes, stream):
     return check("sph_interact", load().sph_interact(C.byref(params), C.byref(grid), pass_, C.byref(targets),
                                                      tidx_ptr, nt_ptr, C.byref(sources), source_cells,
-                                                     zero_first, C.byref(rates), stream))
+                                                     zero_first, C.byref(rates), ws_ptr, ws_bytes, stream))
 
 
 def sph_count_pairs(params, grid, targets, tidx_ptr, nt_ptr, sources, source_cells, counts_ptr, stream):

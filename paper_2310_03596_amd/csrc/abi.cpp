@@ -117,13 +117,13 @@ bool check_particles(const sph_particles *p, const char *name, bool need_off, bo
     return true;
 }
 
-bool check_ws(void *ws, size_t bytes, uint32_t n, Workspace &w)
+bool check_ws(void *ws, size_t bytes, uint32_t n, Workspace &w, size_t stage = 0)
 {
-    size_t need = carve(nullptr, n).bytes;
+    size_t need = carve(nullptr, n, stage).bytes;
     if (!ws || bytes < need)
         return fail(SPH_ERR_WORKSPACE, "workspace of %zu bytes, need %zu for n = %u", ws ? bytes : 0, need, n),
                false;
-    w = carve(ws, n);
+    w = carve(ws, n, stage);
     return true;
 }
 
@@ -152,10 +152,10 @@ const char *sph_version(void) { return "libsph 0.1 (gfx950, wave64)"; }
 
 const char *sph_last_error(void) { return g_err.c_str(); }
 
-size_t sph_workspace_size(const sph_grid *grid, uint32_t n_max)
+size_t sph_workspace_size(const sph_grid *grid, uint32_t n_max, int prec, int material)
 {
     (void)grid;
-    return carve(nullptr, n_max).bytes;
+    return carve(nullptr, n_max, stage_bytes(prec, material)).bytes;
 }
 
 int sph_build_cells(const sph_grid *grid, const sph_particles *in, sph_particles *out, uint32_t *perm_out,
@@ -225,7 +225,8 @@ int sph_pack_boundary(const sph_particles *local, const uint32_t *boundary_idx, 
 
 int sph_interact(const sph_params *params, const sph_grid *grid, int pass, const sph_particles *targets,
                  const uint32_t *target_idx, const uint32_t *n_targets_dev, const sph_particles *sources,
-                 sph_cells source_cells, int zero_first, const sph_rates *rates, void *stream)
+                 sph_cells source_cells, int zero_first, const sph_rates *rates, void *ws, size_t ws_bytes,
+                 void *stream)
 {
     Grid g;
     Params P;
@@ -243,9 +244,13 @@ int sph_interact(const sph_params *params, const sph_grid *grid, int pass, const
         return fail(SPH_ERR_ARG, "source bucket table missing or not on this grid");
     if (!check_rates(rates, pass, params->prec)) return SPH_ERR_ARG;
     if (targets->n == 0) return SPH_OK;
+    if (sources->n >= (1u << 28)) return fail(SPH_ERR_ARG, "sources.n = %u must be below 2^28", sources->n);
+    Workspace w;
+    int staged_material = pass == SPH_PASS_FORCE ? params->material : SPH_FLUID_TAIT;
+    if (!check_ws(ws, ws_bytes, sources->n, w, stage_bytes(params->prec, staged_material))) return SPH_ERR_WORKSPACE;
     bool self = targets->hash == sources->hash;
     return hip_status(launch_interact(P, g, params->prec, pass, *targets, target_idx, n_targets_dev, *sources,
-                                      source_cells.start, self, zero_first, *rates, (hipStream_t)stream),
+                                      source_cells.start, self, zero_first, *rates, w, (hipStream_t)stream),
                       "sph_interact");
 }
 

@@ -127,7 +127,36 @@ inline AV<real> view(const sph_adjoint &a)
     return o;
 }
 
-// Workspace layout for n particles (256-byte aligned pieces).
+// Packed pair inputs of the source particles, one record per particle so a
+// candidate costs one 16-byte load (FP32) and a pair two more:
+//   pos = (position or bucket offset x, y, z, bucket x index), va = (v, omega),
+//   vb = (rho, p, c, e), solids s0 = (S xx yy zz xy), s1 = (S xz yz, 0, 0).
+template <typename real>
+struct Vec4;
+template <>
+struct Vec4<float> {
+    using type = float4;
+};
+template <>
+struct Vec4<double> {
+    using type = double4;
+};
+
+template <typename real>
+struct Stage {
+    using v4 = typename Vec4<real>::type;
+    v4 *pos, *va, *vb, *s0, *s1;
+};
+
+// Bytes per source particle of the packed records.
+inline size_t stage_bytes(int prec, int material)
+{
+    size_t rec = prec == SPH_FP64 ? 32 : 16;
+    return rec * (material == SPH_SOLID_J2 ? 5 : 3);
+}
+
+// Workspace layout for n particles (256-byte aligned pieces).  The packed
+// source records come last; calls other than sph_interact never touch them.
 struct Workspace {
     uint32_t *keys[2];
     uint32_t *vals[2];
@@ -135,6 +164,7 @@ struct Workspace {
     uint32_t *totals;      // kRadixBins
     uint32_t *counts;      // compaction block counts (+1)
     double *partials;      // kDiagPartial * reduction blocks
+    char *stage;           // n * stage bytes
     size_t bytes;
 };
 
@@ -142,7 +172,7 @@ inline uint32_t div_up(uint64_t a, uint64_t b) { return (uint32_t)((a + b - 1) /
 
 inline size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
-inline Workspace carve(void *base, uint32_t n)
+inline Workspace carve(void *base, uint32_t n, size_t stage_per_particle)
 {
     Workspace w;
     uint64_t nn = n > 0 ? n : 1;
@@ -163,8 +193,24 @@ inline Workspace carve(void *base, uint32_t n)
     w.totals = reinterpret_cast<uint32_t *>(take(4ull * kRadixBins));
     w.counts = reinterpret_cast<uint32_t *>(take(4ull * (blocks + 1)));
     w.partials = reinterpret_cast<double *>(take(8ull * kDiagPartial * blocks));
+    w.stage = take(stage_per_particle * nn);
     w.bytes = off;
     return w;
+}
+
+template <typename real>
+inline Stage<real> stage_view(const Workspace &w, uint32_t n, bool solid)
+{
+    using v4 = typename Vec4<real>::type;
+    Stage<real> s;
+    v4 *b = reinterpret_cast<v4 *>(w.stage);
+    size_t nn = n > 0 ? n : 1;
+    s.pos = b;
+    s.va = b + nn;
+    s.vb = b + 2 * nn;
+    s.s0 = solid ? b + 3 * nn : nullptr;
+    s.s1 = solid ? b + 4 * nn : nullptr;
+    return s;
 }
 
 // ---------------------------------------------------------------- launchers
@@ -180,7 +226,7 @@ hipError_t launch_pack(int prec, const sph_particles &local, const uint32_t *bid
 hipError_t launch_interact(const Params &P, const Grid &g, int prec, int pass, const sph_particles &tg,
                            const uint32_t *tidx, const uint32_t *nt, const sph_particles &sr,
                            const uint32_t *sstart, bool self, int zero_first, const sph_rates &r,
-                           hipStream_t s);
+                           const Workspace &ws, hipStream_t s);
 hipError_t launch_count_pairs(const Params &P, const Grid &g, int prec, const sph_particles &tg,
                               const uint32_t *tidx, const uint32_t *nt, const sph_particles &sr,
                               const uint32_t *sstart, bool self, uint64_t *counts, hipStream_t s);

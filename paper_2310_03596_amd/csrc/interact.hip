@@ -1,19 +1,56 @@
 // Interaction loops: steps e (local-local) and f (local x received boundary
 // particles) of Section II, FORCE and GRADIENT passes, FP64 and FP32-split.
 //
-// One lane per target particle.  The 27 surrounding buckets of a target are
-// 9 rows of up to 3 buckets that are contiguous in hash order (the hash runs
-// x-fastest), so each row is one contiguous source range [b, e) of the
-// sorted arrays; rows are visited in ascending hash order, so every target
-// sums its sources in ascending index.  In the FP32-split form the position
-// difference is rebuilt from bucket indices and float offsets,
-// d = (c_j - c_i) L + (off_j - off_i), which is exactly odd under i <-> j
-// and never cancels the way a difference of large float positions would.
+// Neighbour search (Section I): the 27 buckets around a target are 9 rows of
+// up to 3 buckets that are contiguous in hash order (the hash runs
+// x-fastest), so each row is one contiguous range of the sorted sources.
+//
+// Work mapping (one lane per target, sources sorted by hash):
+//   * the lanes of a wavefront are split into groups that share a bucket row
+//     (cy, cz); consecutive sorted targets almost always do;
+//   * for each of the 9 neighbour rows the group's candidates form one
+//     contiguous source range (the union of the lanes' 3-bucket ranges); the
+//     wavefront streams it through LDS in coalesced 64-record chunks and every
+//     lane tests every staged record against its own target (LDS broadcast
+//     reads, no divergence, no per-lane gathers whose latency would serialise
+//     the test);
+//   * hits go to a per-lane list in LDS; when any lane's list is nearly full
+//     (and at the end of the group) every lane evaluates the pair terms of its
+//     listed hits.  Only ~1 candidate in 6 is a neighbour, so separating the
+//     cheap test from the ~140-flop pair body keeps the body dense.
+// A candidate outside a lane's own 3-bucket range is farther than one bucket
+// side >= 2h on some axis and fails the distance test, so testing the union
+// changes no neighbour set.  Hits are listed, and summed, in ascending source
+// index.  A pair with r = 0 (the target itself, or a coincident particle)
+// adds nothing: its terms all carry F(0) = 0.
+//
+// In the FP32-split form the position difference is rebuilt from bucket
+// indices and float offsets, d = (c_j - c_i) L + (off_j - off_i), which is
+// exactly odd under i <-> j and never cancels the way a difference of large
+// float positions would; its pair sums accumulate in FP64 (full rate on
+// gfx950: a convert and an add per term) and are stored as a float (hi, lo)
+// pair.
 #include "pair.hpp"
 
 namespace sph {
 
 namespace {
+
+constexpr int kPairBlock = 256;            // targets per workgroup
+constexpr int kWaves = kPairBlock / kWave;
+constexpr int kChunk = 64;                 // source records staged per wavefront load
+#ifndef SPH_PAIR_SUB
+#define SPH_PAIR_SUB 4   // measured best of 4, 8, 16 on the 810k column (fewer live VGPRs)
+#endif
+constexpr int kSub = SPH_PAIR_SUB;         // candidates tested between list-fill checks
+constexpr int kHitCap = 48;                // listed hits per lane (u16 entries)
+constexpr int kWinBits = 12;               // hit entry: window slot (4 bits) | offset (12 bits)
+constexpr uint32_t kWinLen = 1u << kWinBits;
+constexpr int kMaxWin = 16;
+#ifndef SPH_PAIR_WAVES_PER_EU
+#define SPH_PAIR_WAVES_PER_EU 4
+#endif
+constexpr int kPairWavesPerEU = SPH_PAIR_WAVES_PER_EU;   // occupancy target: caps VGPRs at 512 / 4
 
 // (2h)^2 predicate on FP64 differences without FMA contraction, identical
 // to a left-to-right IEEE evaluation of ((dx dx + dy dy) + dz dz).
@@ -36,23 +73,134 @@ __device__ inline float r2_of<float>(const float d[3])
     return d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
 }
 
-template <typename real, int PASS, bool SOLID, bool SELF>
-__global__ __launch_bounds__(kBlock) void k_interact(Params P, Grid g, PV<real> tg,
-                                                     const uint32_t *__restrict__ tidx,
-                                                     const uint32_t *__restrict__ ntdev, PV<real> sr,
-                                                     const uint32_t *__restrict__ sstart, int zero_first,
-                                                     RV<real> R)
+// Orders this wavefront's LDS writes before its following LDS reads.
+__device__ inline void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ inline int wave_min(int v)
+{
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) v = min(v, __shfl_xor(v, off, kWave));
+    return v;
+}
+
+__device__ inline int wave_max(int v)
+{
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) v = max(v, __shfl_xor(v, off, kWave));
+    return v;
+}
+
+// Packs the pair inputs of every source particle (see Stage).
+template <typename real, bool SOLID>
+__global__ __launch_bounds__(kBlock) void k_stage(Grid g, PV<real> s, Stage<real> st)
 {
     constexpr bool SPLIT = sizeof(real) == 4;
+    uint32_t j = blockIdx.x * kBlock + threadIdx.x;
+    if (j >= s.n) return;
+    using v4 = typename Vec4<real>::type;
+    v4 pos;
+    const uint32_t cx = s.hash[j] % (uint32_t)g.nx;
+    if constexpr (SPLIT) {
+        pos.x = s.off[0][j];
+        pos.y = s.off[1][j];
+        pos.z = s.off[2][j];
+    } else {
+        pos.x = s.x[0][j];
+        pos.y = s.x[1][j];
+        pos.z = s.x[2][j];
+    }
+    pos.w = (real)cx;
+    st.pos[j] = pos;
+    v4 a, b;
+    a.x = s.v[0][j];
+    a.y = s.v[1][j];
+    a.z = s.v[2][j];
+    a.w = s.w[j];
+    b.x = s.rho[j];
+    b.y = s.p[j];
+    b.z = s.c[j];
+    b.w = s.e[j];
+    st.va[j] = a;
+    st.vb[j] = b;
+    if constexpr (SOLID) {
+        v4 c0, c1;
+        c0.x = s.S[0][j];
+        c0.y = s.S[1][j];
+        c0.z = s.S[2][j];
+        c0.w = s.S[3][j];
+        c1.x = s.S[4][j];
+        c1.y = s.S[5][j];
+        c1.z = 0;
+        c1.w = 0;
+        st.s0[j] = c0;
+        st.s1[j] = c1;
+    }
+}
+
+// Target position: bucket offsets and bucket x index (split), or x (FP64).
+template <typename real>
+struct TargetPos {
+    real o[3];
+    double x[3];
+    real cxf;
+    real Lf;
+};
+
+// d = x_j - x_i for a staged source record p in neighbour row (ddy, ddz).
+template <typename real>
+__device__ inline void diff(const TargetPos<real> &T, const typename Vec4<real>::type &p, real ddy, real ddz,
+                            real d[3])
+{
+    if constexpr (sizeof(real) == 4) {
+        d[0] = (p.w - T.cxf) * T.Lf + (p.x - T.o[0]);
+        d[1] = ddy + (p.y - T.o[1]);
+        d[2] = ddz + (p.z - T.o[2]);
+    } else {
+        d[0] = p.x - T.x[0];
+        d[1] = p.y - T.x[1];
+        d[2] = p.z - T.x[2];
+    }
+}
+
+// Pair-sum accumulator: FP64 in both forms.
+struct Acc {
+    double s;
+    __device__ inline void add(float x) { s += (double)x; }
+    __device__ inline void add(double x) { s += x; }
+};
+
+template <typename real, int PASS, bool SOLID, bool SELF>
+__global__ __launch_bounds__(kPairBlock) __attribute__((amdgpu_waves_per_eu(kPairWavesPerEU)))
+void k_pairs(Params P, Grid g, PV<real> tg,
+                                                      const uint32_t *__restrict__ tidx,
+                                                      const uint32_t *__restrict__ ntdev, Stage<real> src,
+                                                      const uint32_t *__restrict__ sstart, int zero_first,
+                                                      RV<real> R)
+{
+    using v4 = typename Vec4<real>::type;
+    constexpr bool SPLIT = sizeof(real) == 4;
     constexpr int NOUT = PASS == SPH_PASS_FORCE ? 6 : 9;
-    uint32_t t = blockIdx.x * kBlock + threadIdx.x;
+    __shared__ uint16_t hits[kHitCap][kPairBlock];
+    __shared__ v4 stage[kWaves][kChunk];
+    __shared__ uint32_t wbase[kWaves][kMaxWin];
+    __shared__ uint32_t wrow[kWaves][kMaxWin];
+
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+    const uint32_t t = blockIdx.x * kPairBlock + tid;
     uint32_t nt = tg.n;
     if (tidx) {
         uint32_t c = *ntdev;
         nt = c < nt ? c : nt;
     }
-    if (t >= nt) return;
-    const uint32_t i = tidx ? tidx[t] : t;
+    // whole wavefronts beyond the targets leave; partial ones keep idle lanes
+    if (blockIdx.x * kPairBlock + wave * kWave >= nt) return;
+    const bool valid = t < nt;
+    const uint32_t i = valid ? (tidx ? tidx[t] : t) : 0u;
 
     PairK<real> K;
     K.hinv = (real)P.hinv;
@@ -60,98 +208,176 @@ __global__ __launch_bounds__(kBlock) void k_interact(Params P, Grid g, PV<real> 
     K.beta = (real)P.beta;
     K.half_beta = (real)(0.5 * P.beta);
     const real R2 = (real)P.R2;
-    const real Lf = SPLIT ? (real)g.Lf : real(0);
 
-    const uint32_t h = tg.hash[i];
+    const uint32_t h = valid ? tg.hash[i] : 0u;
     const int cx = (int)(h % (uint32_t)g.nx);
-    const int cy = (int)((h / (uint32_t)g.nx) % (uint32_t)g.ny);
-    const int cz = (int)(h / ((uint32_t)g.nx * (uint32_t)g.ny));
+    const uint32_t rowkey = valid ? h / (uint32_t)g.nx : 0xFFFFFFFFu;   // cy + ny cz
     const int x0 = cx > 0 ? cx - 1 : 0;
     const int x1 = cx + 1 < g.nx ? cx + 1 : g.nx - 1;
 
-    double xi[3];
-    real oi[3];
+    TargetPos<real> T;
+    T.cxf = (real)cx;
+    T.Lf = SPLIT ? (real)g.Lf : real(0);
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-        if constexpr (SPLIT)
-            oi[d] = tg.off[d][i];
-        else
-            xi[d] = tg.x[d][i];
+        if constexpr (SPLIT) {
+            T.o[d] = valid ? tg.off[d][i] : real(0);
+            T.x[d] = 0.0;
+        } else {
+            T.x[d] = valid ? tg.x[d][i] : 0.0;
+            T.o[d] = real(0);
+        }
     }
     Part<real, SOLID> I;
-    real vi[3];
-    real wj_dummy = 0;
-    (void)wj_dummy;
     if constexpr (PASS == SPH_PASS_FORCE) {
         load_part<real, SOLID>(tg, i, I);
     } else {
 #pragma unroll
-        for (int d = 0; d < 3; ++d) vi[d] = tg.v[d][i];
+        for (int d = 0; d < 3; ++d) I.v[d] = tg.v[d][i];
     }
 
-    Sum<real> acc[NOUT];
+    Acc acc[NOUT];
 #pragma unroll
     for (int k = 0; k < NOUT; ++k) {
         real *hi = PASS == SPH_PASS_FORCE ? R.hi[k] : R.Lhi[k];
         real *lo = PASS == SPH_PASS_FORCE ? R.lo[k] : R.Llo[k];
-        acc[k].s = zero_first ? real(0) : hi[i];
-        acc[k].c = (zero_first || !SPLIT) ? real(0) : lo[i];
+        double s0 = 0.0;
+        if (!zero_first && valid) {
+            s0 = (double)hi[i];
+            if (SPLIT) s0 += (double)lo[i];
+        }
+        acc[k].s = s0;
     }
 
-    for (int dz = -1; dz <= 1; ++dz) {
-        const int z = cz + dz;
-        if (z < 0 || z >= g.nz) continue;
-        for (int dy = -1; dy <= 1; ++dy) {
-            const int y = cy + dy;
-            if (y < 0 || y >= g.ny) continue;
-            const uint32_t row = (uint32_t)g.nx * ((uint32_t)y + (uint32_t)g.ny * (uint32_t)z);
-            const uint32_t jb = sstart[row + x0];
-            const uint32_t je = sstart[row + x1 + 1];
-            const uint32_t sA = sstart[row + cx];
-            const uint32_t sB = sstart[row + cx + 1];
-            const real ddy = (real)dy * Lf, ddz = (real)dz * Lf;
-            for (uint32_t j = jb; j < je; ++j) {
-                if (SELF && j == i) continue;
-                real d[3];
-                if constexpr (SPLIT) {
-                    const int dcx = (int)(j >= sB) - (int)(j < sA);
-                    d[0] = (real)dcx * Lf + (sr.off[0][j] - oi[0]);
-                    d[1] = ddy + (sr.off[1][j] - oi[1]);
-                    d[2] = ddz + (sr.off[2][j] - oi[2]);
-                } else {
-                    d[0] = sr.x[0][j] - xi[0];
-                    d[1] = sr.x[1][j] - xi[1];
-                    d[2] = sr.x[2][j] - xi[2];
+    int cnt = 0;
+    // evaluate the pair terms of every listed hit, then empty the lists
+    auto flush = [&]() {
+        for (int s = 0; s < cnt; ++s) {
+            const uint32_t e = hits[s][tid];
+            const uint32_t slot = e >> kWinBits;
+            const uint32_t jj = wbase[wave][slot] + (e & (kWinLen - 1));
+            const int rr = (int)wrow[wave][slot];
+            const real qy = (real)(rr % 3 - 1) * T.Lf, qz = (real)(rr / 3 - 1) * T.Lf;
+            real d[3];
+            diff<real>(T, src.pos[jj], qy, qz, d);
+            const real r2 = r2_of<real>(d);
+            const v4 a = src.va[jj];
+            if constexpr (PASS == SPH_PASS_FORCE) {
+                const v4 b = src.vb[jj];
+                Part<real, SOLID> J;
+                J.v[0] = a.x;
+                J.v[1] = a.y;
+                J.v[2] = a.z;
+                J.w = a.w;
+                J.rho = b.x;
+                J.p = b.y;
+                J.c = b.z;
+                J.e = b.w;
+                if constexpr (SOLID) {
+                    const v4 c0 = src.s0[jj], c1 = src.s1[jj];
+                    J.S[0] = c0.x;
+                    J.S[1] = c0.y;
+                    J.S[2] = c0.z;
+                    J.S[3] = c0.w;
+                    J.S[4] = c1.x;
+                    J.S[5] = c1.y;
                 }
-                const real r2 = r2_of<real>(d);
-                if (!(r2 < R2)) continue;
-                if constexpr (PASS == SPH_PASS_FORCE) {
-                    Part<real, SOLID> J;
-                    load_part<real, SOLID>(sr, j, J);
-                    real o[6];
-                    pair_force<real, SOLID>(d, r2, I, J, K, o);
+                real o[6];
+                pair_force<real, SOLID>(d, r2, I, J, K, o);
 #pragma unroll
-                    for (int k = 0; k < 6; ++k) acc[k].add(o[k]);
-                } else {
-                    real vj[3] = {sr.v[0][j], sr.v[1][j], sr.v[2][j]};
-                    real o[9];
-                    pair_grad<real>(d, r2, vi, vj, sr.w[j], K, o);
+                for (int k = 0; k < 6; ++k) acc[k].add(o[k]);
+            } else {
+                const real vj[3] = {a.x, a.y, a.z};
+                real o[9];
+                pair_grad<real>(d, r2, I.v, vj, a.w, K, o);
 #pragma unroll
-                    for (int k = 0; k < 9; ++k) acc[k].add(o[k]);
+                for (int k = 0; k < 9; ++k) acc[k].add(o[k]);
+            }
+        }
+        cnt = 0;
+    };
+
+    const real kFar = SPLIT ? real(1e30f) : real(1e300);
+
+    uint64_t pending = __ballot(valid);
+    while (pending) {
+        // the next group: lanes whose target shares the first pending lane's bucket row
+        const int leader = __ffsll((unsigned long long)pending) - 1;
+        const uint32_t key = __shfl(rowkey, leader, kWave);
+        const bool in = valid && rowkey == key;
+        pending &= ~__ballot(in);
+        const int gx0 = wave_min(in ? x0 : 0x7FFFFFFF);
+        const int gx1 = wave_max(in ? x1 : -1);
+        const int gy = (int)(key % (uint32_t)g.ny), gz = (int)(key / (uint32_t)g.ny);
+        const real R2in = in ? R2 : real(-1);
+        int nwin = 0;
+        for (int r = 0; r < 9; ++r) {
+            const int dz = r / 3 - 1, dy = r % 3 - 1;
+            const int z = gz + dz, y = gy + dy;
+            if (z < 0 || z >= g.nz || y < 0 || y >= g.ny) continue;
+            const uint32_t row = (uint32_t)g.nx * ((uint32_t)y + (uint32_t)g.ny * (uint32_t)z);
+            const uint32_t ub = sstart[row + gx0], ue = sstart[row + gx1 + 1];
+            const real ddy = (real)dy * T.Lf, ddz = (real)dz * T.Lf;
+            for (uint32_t wb = ub; wb < ue; wb += kWinLen) {
+                if (nwin == kMaxWin) {
+                    flush();
+                    nwin = 0;
+                }
+                const int slot = nwin++;
+                if (lane == 0) {
+                    wbase[wave][slot] = wb;
+                    wrow[wave][slot] = (uint32_t)r;
+                }
+                const uint32_t we = (ue - wb > kWinLen) ? wb + kWinLen : ue;
+                for (uint32_t c = wb; c < we; c += kChunk) {
+                    const uint32_t k = c + lane;
+                    wave_lds_sync();   // earlier reads of the stage are done
+                    // records past the window are a far-away sentinel that fails every test
+                    v4 rec;
+                    if (k < we) {
+                        rec = src.pos[k];
+                    } else {
+                        rec.x = rec.y = rec.z = kFar;
+                        rec.w = real(0);
+                    }
+                    stage[wave][lane] = rec;
+                    wave_lds_sync();
+                    const int nsub = (int)((((we - c) < (uint32_t)kChunk ? (we - c) : (uint32_t)kChunk) + kSub - 1) / kSub);
+                    for (int sb = 0; sb < nsub; ++sb) {
+                        if (__ballot(cnt > kHitCap - kSub)) flush();
+                        uint32_t mask = 0;
+#pragma unroll
+                        for (int m = 0; m < kSub; ++m) {
+                            real d[3];
+                            diff<real>(T, stage[wave][sb * kSub + m], ddy, ddz, d);
+                            mask |= (r2_of<real>(d) < R2in) ? (1u << m) : 0u;
+                        }
+                        // list the hits in ascending source index
+                        const uint32_t base = ((uint32_t)slot << kWinBits) + (c - wb) + (uint32_t)(sb * kSub);
+                        while (mask) {
+                            const int b = __ffs(mask) - 1;
+                            mask &= mask - 1;
+                            hits[cnt][tid] = (uint16_t)(base + (uint32_t)b);
+                            ++cnt;
+                        }
+                    }
                 }
             }
         }
+        flush();
     }
+    if (!valid) return;
 #pragma unroll
     for (int k = 0; k < NOUT; ++k) {
         real *hi = PASS == SPH_PASS_FORCE ? R.hi[k] : R.Lhi[k];
         real *lo = PASS == SPH_PASS_FORCE ? R.lo[k] : R.Llo[k];
-        hi[i] = acc[k].s;
-        if (SPLIT) lo[i] = acc[k].c;
+        const real hv = (real)acc[k].s;
+        hi[i] = hv;
+        if (SPLIT) lo[i] = (real)(acc[k].s - (double)hv);
     }
 }
 
-// Candidates and hits of one pass, same traversal and predicate as k_interact.
+// Candidates and hits of one pass, with the predicate of the pair kernel.
 template <typename real, bool SELF>
 __global__ __launch_bounds__(kBlock) void k_count(Params P, Grid g, PV<real> tg, const uint32_t *__restrict__ tidx,
                                                   const uint32_t *__restrict__ ntdev, PV<real> sr,
@@ -209,7 +435,8 @@ __global__ __launch_bounds__(kBlock) void k_count(Params P, Grid g, PV<real> tg,
                         d[2] = sr.x[2][j] - xi[2];
                     }
                     ++cand;
-                    hits += (r2_of<real>(d) < R2) ? 1u : 0u;
+                    const real r2 = r2_of<real>(d);
+                    hits += (r2 < R2 && r2 > real(0)) ? 1u : 0u;
                 }
             }
         }
@@ -229,31 +456,31 @@ __global__ __launch_bounds__(kBlock) void k_count(Params P, Grid g, PV<real> tg,
 template <typename real, int PASS, bool SOLID>
 hipError_t go(const Params &P, const Grid &g, const sph_particles &tg, const uint32_t *tidx,
               const uint32_t *nt, const sph_particles &sr, const uint32_t *sstart, bool self, int zero_first,
-              const sph_rates &r, hipStream_t s)
+              const sph_rates &r, const Workspace &ws, hipStream_t s)
 {
-    uint32_t blocks = div_up(tg.n, kBlock);
-    if (blocks == 0) return hipSuccess;
+    if (tg.n == 0) return hipSuccess;
+    Stage<real> st = stage_view<real>(ws, sr.n, SOLID);
+    if (sr.n > 0) k_stage<real, SOLID><<<div_up(sr.n, kBlock), kBlock, 0, s>>>(g, view<real>(sr), st);
+    uint32_t blocks = div_up(tg.n, kPairBlock);
     if (self)
-        k_interact<real, PASS, SOLID, true><<<blocks, kBlock, 0, s>>>(P, g, view<real>(tg), tidx, nt,
-                                                                      view<real>(sr), sstart, zero_first,
-                                                                      view<real>(r));
+        k_pairs<real, PASS, SOLID, true><<<blocks, kPairBlock, 0, s>>>(P, g, view<real>(tg), tidx, nt, st, sstart,
+                                                                     zero_first, view<real>(r));
     else
-        k_interact<real, PASS, SOLID, false><<<blocks, kBlock, 0, s>>>(P, g, view<real>(tg), tidx, nt,
-                                                                       view<real>(sr), sstart, zero_first,
-                                                                       view<real>(r));
+        k_pairs<real, PASS, SOLID, false><<<blocks, kPairBlock, 0, s>>>(P, g, view<real>(tg), tidx, nt, st, sstart,
+                                                                      zero_first, view<real>(r));
     return hipGetLastError();
 }
 
 template <typename real>
 hipError_t go_prec(const Params &P, const Grid &g, int pass, const sph_particles &tg, const uint32_t *tidx,
                    const uint32_t *nt, const sph_particles &sr, const uint32_t *sstart, bool self,
-                   int zero_first, const sph_rates &r, hipStream_t s)
+                   int zero_first, const sph_rates &r, const Workspace &ws, hipStream_t s)
 {
     if (pass == SPH_PASS_GRADIENT)
-        return go<real, SPH_PASS_GRADIENT, false>(P, g, tg, tidx, nt, sr, sstart, self, zero_first, r, s);
+        return go<real, SPH_PASS_GRADIENT, false>(P, g, tg, tidx, nt, sr, sstart, self, zero_first, r, ws, s);
     if (P.material == SPH_SOLID_J2)
-        return go<real, SPH_PASS_FORCE, true>(P, g, tg, tidx, nt, sr, sstart, self, zero_first, r, s);
-    return go<real, SPH_PASS_FORCE, false>(P, g, tg, tidx, nt, sr, sstart, self, zero_first, r, s);
+        return go<real, SPH_PASS_FORCE, true>(P, g, tg, tidx, nt, sr, sstart, self, zero_first, r, ws, s);
+    return go<real, SPH_PASS_FORCE, false>(P, g, tg, tidx, nt, sr, sstart, self, zero_first, r, ws, s);
 }
 
 }  // namespace
@@ -285,11 +512,12 @@ hipError_t launch_count_pairs(const Params &P, const Grid &g, int prec, const sp
 
 hipError_t launch_interact(const Params &P, const Grid &g, int prec, int pass, const sph_particles &tg,
                            const uint32_t *tidx, const uint32_t *nt, const sph_particles &sr,
-                           const uint32_t *sstart, bool self, int zero_first, const sph_rates &r, hipStream_t s)
+                           const uint32_t *sstart, bool self, int zero_first, const sph_rates &r,
+                           const Workspace &ws, hipStream_t s)
 {
     if (prec == SPH_FP64)
-        return go_prec<double>(P, g, pass, tg, tidx, nt, sr, sstart, self, zero_first, r, s);
-    return go_prec<float>(P, g, pass, tg, tidx, nt, sr, sstart, self, zero_first, r, s);
+        return go_prec<double>(P, g, pass, tg, tidx, nt, sr, sstart, self, zero_first, r, ws, s);
+    return go_prec<float>(P, g, pass, tg, tidx, nt, sr, sstart, self, zero_first, r, ws, s);
 }
 
 }  // namespace sph

@@ -35,20 +35,22 @@ __device__ inline double rcp<double>(double x)
     return 1.0 / x;
 }
 
-// 1 / sqrt(r2) and sqrt(r2).
+// 1 / sqrt(r2) and sqrt(r2); r2 = 0 (a particle with itself, or a
+// coincident pair) gives r = 0 and rinv = 0, so n = 0 and, with F(0) = 0,
+// every pair term is exactly zero.
 template <typename real>
 __device__ inline void inv_len(real r2, real &r, real &rinv);
 template <>
 __device__ inline void inv_len<float>(float r2, float &r, float &rinv)
 {
-    rinv = __builtin_amdgcn_rsqf(r2);
+    rinv = r2 > 0.0f ? __builtin_amdgcn_rsqf(r2) : 0.0f;
     r = r2 * rinv;
 }
 template <>
 __device__ inline void inv_len<double>(double r2, double &r, double &rinv)
 {
     r = sqrt(r2);
-    rinv = 1.0 / r;
+    rinv = r2 > 0.0 ? 1.0 / r : 0.0;
 }
 
 // Compensated (hi, lo) accumulator for float (TwoSum: the rounding error of

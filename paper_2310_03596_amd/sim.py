@@ -29,7 +29,7 @@ class Sim:
         self.B = Particles(self.n, prec, self.solid, device)
         self.perm = torch.zeros(self.n, dtype=torch.int32, device=device)
         self.start = torch.zeros(self.nc + 1, dtype=torch.int32, device=device)
-        self.ws_bytes = L.sph_workspace_size(self.grid, self.n)
+        self.ws_bytes = L.sph_workspace_size(self.grid, self.n, prec, int(wl.params["material"]))
         self.ws = torch.zeros(self.ws_bytes, dtype=torch.uint8, device=device)
         self.rates = Rates(self.n, prec, self.solid, device)
         self.diag = torch.zeros((2, 8), dtype=torch.float64, device=device)
@@ -56,7 +56,8 @@ class Sim:
     def interact(self, pass_=L.SPH_PASS_FORCE):
         a = self.A.struct()
         r = self.rates.struct()
-        L.sph_interact(self.params, self.grid, pass_, a, None, None, a, self.cells, 1, r, stream_handle())
+        L.sph_interact(self.params, self.grid, pass_, a, None, None, a, self.cells, 1, r, self.ws.data_ptr(),
+                       self.ws_bytes, stream_handle())
 
     def dt_ptr(self, dt_ptr=None):
         if dt_ptr is not None:
@@ -74,11 +75,13 @@ class Sim:
         r = self.rates.struct()
         st = stream_handle()
         if self.solid:
-            L.sph_interact(self.params, self.grid, L.SPH_PASS_GRADIENT, a, None, None, a, self.cells, 1, r, st)
+            L.sph_interact(self.params, self.grid, L.SPH_PASS_GRADIENT, a, None, None, a, self.cells, 1, r,
+                           self.ws.data_ptr(), self.ws_bytes, st)
             L.sph_integrate(self.params, L.SPH_STAGE_STRESS, a, r, dtp, None, None, 0, st)
         if force_events is not None:
             force_events[0].record()
-        L.sph_interact(self.params, self.grid, L.SPH_PASS_FORCE, a, None, None, a, self.cells, 1, r, st)
+        L.sph_interact(self.params, self.grid, L.SPH_PASS_FORCE, a, None, None, a, self.cells, 1, r,
+                       self.ws.data_ptr(), self.ws_bytes, st)
         if force_events is not None:
             force_events[1].record()
         nxt = 1 - self.cur
@@ -140,7 +143,7 @@ class SharePass:
         self.lstart = torch.zeros(self.nc + 1, dtype=torch.int32, device=device)
         self.rstart = torch.zeros(self.nc + 1, dtype=torch.int32, device=device)
         nmax = max(self.nl, self.nr)
-        self.ws_bytes = L.sph_workspace_size(self.grid, nmax)
+        self.ws_bytes = L.sph_workspace_size(self.grid, nmax, prec, L.SPH_FLUID_TAIT)
         self.ws = torch.zeros(self.ws_bytes, dtype=torch.uint8, device=device)
         self.comm = torch.zeros(self.nl, dtype=torch.int32, device=device)
         self.bidx = torch.zeros(self.nl, dtype=torch.int32, device=device)
@@ -172,12 +175,13 @@ class SharePass:
     def interact_local(self):
         a = self.LB.struct()
         L.sph_interact(self.params, self.grid, L.SPH_PASS_FORCE, a, None, None, a,
-                       cells_struct(self.lstart, self.nc), 1, self.rates.struct(), stream_handle())
+                       cells_struct(self.lstart, self.nc), 1, self.rates.struct(), self.ws.data_ptr(),
+                       self.ws_bytes, stream_handle())
 
     def interact_remote(self):
         L.sph_interact(self.params, self.grid, L.SPH_PASS_FORCE, self.LB.struct(), self.bidx.data_ptr(),
                        self.nb.data_ptr(), self.RB.struct(), cells_struct(self.rstart, self.nc), 0,
-                       self.rates.struct(), stream_handle())
+                       self.rates.struct(), self.ws.data_ptr(), self.ws_bytes, stream_handle())
 
     def run(self):
         self.build()

@@ -12,14 +12,14 @@ import numpy as np
 
 
 def neighbor_pairs(x_t: np.ndarray, x_s: np.ndarray, h: float, self_pass: bool):
-    """Set of (i, j) with ((dx^2 + dy^2) + dz^2) < (2h)^2, j != i when self_pass."""
+    """Set of (i, j) with 0 < ((dx^2 + dy^2) + dz^2) < (2h)^2, j != i when self_pass."""
     R = 2.0 * h
     R2 = R * R
     out = set()
     for i in range(x_t.shape[0]):
         d = x_s - x_t[i]
         r2 = (d[:, 0] * d[:, 0] + d[:, 1] * d[:, 1]) + d[:, 2] * d[:, 2]
-        js = np.flatnonzero(r2 < R2)
+        js = np.flatnonzero((r2 < R2) & (r2 > 0.0))
         for j in js:
             if self_pass and j == i:
                 continue

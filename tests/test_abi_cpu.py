@@ -69,9 +69,11 @@ def _last():
 
 def test_workspace_size_grows_with_n():
     g = _grid()
-    a, b = L.sph_workspace_size(g, 1000), L.sph_workspace_size(g, 100000)
+    a, b = L.sph_workspace_size(g, 1000, 0, 0), L.sph_workspace_size(g, 100000, 0, 0)
     assert 0 < a < b
-    assert L.sph_workspace_size(g, 0) > 0
+    assert L.sph_workspace_size(g, 0, 0, 0) > 0
+    # FP64 and solid records are larger
+    assert L.sph_workspace_size(g, 1000, 1, 0) < a < L.sph_workspace_size(g, 1000, 0, 1)
 
 
 def test_build_cells_rejects_bad_arguments():
@@ -80,7 +82,7 @@ def test_build_cells_rejects_bad_arguments():
     cells = L.SphCells(FAKE, 64, 0)
     a, b = _particles(10), _particles(10)
     b.x[0] = 0x2000
-    ws = L.sph_workspace_size(g, 10)
+    ws = L.sph_workspace_size(g, 10, 0, 0)
     # grid too large for 32-bit hashes
     big = _grid(dims=(1 << 11, 1 << 11, 1 << 10))
     assert lib.sph_build_cells(C.byref(big), C.byref(a), C.byref(b), FAKE, cells, FAKE, ws, None) == L.SPH_ERR_ARG
@@ -96,8 +98,9 @@ def test_build_cells_rejects_bad_arguments():
     # in/out overlap
     assert lib.sph_build_cells(C.byref(g), C.byref(a), C.byref(a), FAKE, cells, FAKE, ws, None) == L.SPH_ERR_ARG
     # workspace too small
-    assert (lib.sph_build_cells(C.byref(g), C.byref(a), C.byref(b), FAKE, cells, FAKE, ws - 1, None)
+    assert (lib.sph_build_cells(C.byref(g), C.byref(a), C.byref(b), FAKE, cells, FAKE, 64, None)
             == L.SPH_ERR_WORKSPACE)
+    assert lib.sph_build_cells(C.byref(g), C.byref(a), C.byref(b), FAKE, cells, None, ws, None) == L.SPH_ERR_WORKSPACE
     # n mismatch
     d = _particles(11)
     assert lib.sph_build_cells(C.byref(g), C.byref(a), C.byref(d), FAKE, cells, FAKE, ws, None) == L.SPH_ERR_ARG
@@ -116,34 +119,34 @@ def test_interact_rejects_bad_arguments():
         r.hi[k] = FAKE
     # bucket smaller than the support 2h
     assert lib.sph_interact(C.byref(_params(h=0.6)), C.byref(g), 0, C.byref(p), None, None, C.byref(p), cells, 1,
-                            C.byref(r), None) == L.SPH_ERR_ARG
+                            C.byref(r), FAKE, 1 << 30, None) == L.SPH_ERR_ARG
     assert "smaller than the support" in _last()
     # precision mismatch
     assert lib.sph_interact(C.byref(_params(prec=L.SPH_FP32_SPLIT)), C.byref(g), 0, C.byref(p), None, None,
-                            C.byref(p), cells, 1, C.byref(r), None) == L.SPH_ERR_ARG
+                            C.byref(p), cells, 1, C.byref(r), FAKE, 1 << 30, None) == L.SPH_ERR_ARG
     # FP32 split needs the compensation buffers and offsets
     q = _particles(10, L.SPH_FP32_SPLIT)
     assert lib.sph_interact(C.byref(_params(prec=L.SPH_FP32_SPLIT)), C.byref(g), 0, C.byref(q), None, None,
-                            C.byref(q), cells, 1, C.byref(r), None) == L.SPH_ERR_ARG
+                            C.byref(q), cells, 1, C.byref(r), FAKE, 1 << 30, None) == L.SPH_ERR_ARG
     assert "lo" in _last()
     # target list without a device count
     assert lib.sph_interact(C.byref(_params()), C.byref(g), 0, C.byref(p), FAKE, None, C.byref(p), cells, 0,
-                            C.byref(r), None) == L.SPH_ERR_ARG
+                            C.byref(r), FAKE, 1 << 30, None) == L.SPH_ERR_ARG
     # unknown pass
     assert lib.sph_interact(C.byref(_params()), C.byref(g), 7, C.byref(p), None, None, C.byref(p), cells, 1,
-                            C.byref(r), None) == L.SPH_ERR_ARG
+                            C.byref(r), FAKE, 1 << 30, None) == L.SPH_ERR_ARG
     # solid FORCE pass needs the stress fields
     ps = _params()
     ps.material, ps.K, ps.G = L.SPH_SOLID_J2, 1e9, 1e9
     assert lib.sph_interact(C.byref(ps), C.byref(g), 0, C.byref(p), None, None, C.byref(p), cells, 1, C.byref(r),
-                            None) == L.SPH_ERR_ARG
+                            FAKE, 1 << 30, None) == L.SPH_ERR_ARG
     assert "S[0]" in _last()
 
 
 def test_integrate_and_adjoint_reject_bad_arguments():
     lib = L.load()
     p = _particles(10)
-    ws = L.sph_workspace_size(_grid(), 10)
+    ws = L.sph_workspace_size(_grid(), 10, 0, 0)
     # stress stage on a fluid
     assert lib.sph_integrate(C.byref(_params()), L.SPH_STAGE_STRESS, C.byref(p), None, FAKE, None, None, 0,
                              None) == L.SPH_ERR_ARG
@@ -178,7 +181,7 @@ def test_zero_particles_is_a_noop():
     for k in range(6):
         r.hi[k] = FAKE
     assert lib.sph_interact(C.byref(_params()), C.byref(g), 0, C.byref(p), None, None, C.byref(p), cells, 1,
-                            C.byref(r), None) == L.SPH_OK
+                            C.byref(r), FAKE, 1 << 30, None) == L.SPH_OK
     out = L.SphParticles()
     out.n = 5
     assert lib.sph_pack_boundary(C.byref(p), None, None, C.byref(L.SphParticles()), None) == L.SPH_OK
