@@ -45,6 +45,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the CPU oracle sample")
     ap.add_argument("--only", choices=["fp32", "fp64", "both"], default="both")
+    ap.add_argument("--calib-copy-mb", type=int, default=0,
+                    help="also run one plain device copy of this many MiB (scale for HBM counters)")
     return ap.parse_args()
 
 
@@ -176,6 +178,14 @@ def main():
                             "force_tflops": res[0]["force_tflops"],
                             "frac_of_fp64_peak": res[0]["force_tflops"] / PEAK_TFLOPS[0]}
         out["fp32_over_fp64"] = res[1]["value"] / res[0]["value"]
+    if args.calib_copy_mb > 0:
+        nbytes = args.calib_copy_mb << 20
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        out["calib_copy_bytes"] = nbytes
     if not args.no_cpu:
         cb, err = cpu_leg(wl, args.cpu_seconds)
         out["cpu_baseline"] = cb

@@ -48,9 +48,15 @@ constexpr int kWinBits = 12;               // hit entry: window slot (4 bits) | 
 constexpr uint32_t kWinLen = 1u << kWinBits;
 constexpr int kMaxWin = 16;
 #ifndef SPH_PAIR_WAVES_PER_EU
-#define SPH_PAIR_WAVES_PER_EU 4
+#define SPH_PAIR_WAVES_PER_EU 5
 #endif
-constexpr int kPairWavesPerEU = SPH_PAIR_WAVES_PER_EU;   // occupancy target: caps VGPRs at 512 / 4
+// Occupancy target (waves per SIMD; caps VGPRs at 512 / target) per
+// variant: the fluid FP32 pass fits 5 without spills, the larger solid and
+// FP64 bodies fit 4 and 3.
+template <typename real, bool SOLID>
+struct PairOccupancy {
+    static constexpr int value = sizeof(real) == 4 ? (SOLID ? 4 : SPH_PAIR_WAVES_PER_EU) : (SOLID ? 3 : 4);
+};
 
 // (2h)^2 predicate on FP64 differences without FMA contraction, identical
 // to a left-to-right IEEE evaluation of ((dx dx + dy dy) + dz dz).
@@ -175,7 +181,7 @@ struct Acc {
 };
 
 template <typename real, int PASS, bool SOLID, bool SELF>
-__global__ __launch_bounds__(kPairBlock) __attribute__((amdgpu_waves_per_eu(kPairWavesPerEU)))
+__global__ __launch_bounds__(kPairBlock) __attribute__((amdgpu_waves_per_eu(PairOccupancy<real, SOLID>::value)))
 void k_pairs(Params P, Grid g, PV<real> tg,
                                                       const uint32_t *__restrict__ tidx,
                                                       const uint32_t *__restrict__ ntdev, Stage<real> src,
@@ -187,8 +193,9 @@ void k_pairs(Params P, Grid g, PV<real> tg,
     constexpr int NOUT = PASS == SPH_PASS_FORCE ? 6 : 9;
     __shared__ uint16_t hits[kHitCap][kPairBlock];
     __shared__ v4 stage[kWaves][kChunk];
-    __shared__ uint32_t wbase[kWaves][kMaxWin];
-    __shared__ uint32_t wrow[kWaves][kMaxWin];
+    __shared__ uint32_t wbase[kWaves][kMaxWin];   // first source index of each window
+    __shared__ real wdy[kWaves][kMaxWin];         // (c_j - c_i) L in y and z of the window's row
+    __shared__ real wdz[kWaves][kMaxWin];
 
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
     const uint32_t t = blockIdx.x * kPairBlock + tid;
@@ -250,20 +257,40 @@ void k_pairs(Params P, Grid g, PV<real> tg,
     }
 
     int cnt = 0;
+    // Records of one listed hit; the next hit's are loaded while the current
+    // pair is evaluated (software pipelining hides the L2 latency).
+    struct Rec {
+        v4 p, a, b, s0, s1;
+        real qy, qz;
+    };
+    auto fetch = [&](int s) {
+        Rec q;
+        const uint32_t e = hits[s][tid];
+        const uint32_t slot = e >> kWinBits;
+        const uint32_t jj = wbase[wave][slot] + (e & (kWinLen - 1));
+        q.qy = wdy[wave][slot];
+        q.qz = wdz[wave][slot];
+        q.p = src.pos[jj];
+        q.a = src.va[jj];
+        if constexpr (PASS == SPH_PASS_FORCE) q.b = src.vb[jj];
+        if constexpr (PASS == SPH_PASS_FORCE && SOLID) {
+            q.s0 = src.s0[jj];
+            q.s1 = src.s1[jj];
+        }
+        return q;
+    };
     // evaluate the pair terms of every listed hit, then empty the lists
     auto flush = [&]() {
+        Rec cur;
+        if (cnt > 0) cur = fetch(0);
         for (int s = 0; s < cnt; ++s) {
-            const uint32_t e = hits[s][tid];
-            const uint32_t slot = e >> kWinBits;
-            const uint32_t jj = wbase[wave][slot] + (e & (kWinLen - 1));
-            const int rr = (int)wrow[wave][slot];
-            const real qy = (real)(rr % 3 - 1) * T.Lf, qz = (real)(rr / 3 - 1) * T.Lf;
+            const Rec nxt = fetch(s + 1 < cnt ? s + 1 : s);
             real d[3];
-            diff<real>(T, src.pos[jj], qy, qz, d);
+            diff<real>(T, cur.p, cur.qy, cur.qz, d);
             const real r2 = r2_of<real>(d);
-            const v4 a = src.va[jj];
+            const v4 a = cur.a;
             if constexpr (PASS == SPH_PASS_FORCE) {
-                const v4 b = src.vb[jj];
+                const v4 b = cur.b;
                 Part<real, SOLID> J;
                 J.v[0] = a.x;
                 J.v[1] = a.y;
@@ -274,13 +301,12 @@ void k_pairs(Params P, Grid g, PV<real> tg,
                 J.c = b.z;
                 J.e = b.w;
                 if constexpr (SOLID) {
-                    const v4 c0 = src.s0[jj], c1 = src.s1[jj];
-                    J.S[0] = c0.x;
-                    J.S[1] = c0.y;
-                    J.S[2] = c0.z;
-                    J.S[3] = c0.w;
-                    J.S[4] = c1.x;
-                    J.S[5] = c1.y;
+                    J.S[0] = cur.s0.x;
+                    J.S[1] = cur.s0.y;
+                    J.S[2] = cur.s0.z;
+                    J.S[3] = cur.s0.w;
+                    J.S[4] = cur.s1.x;
+                    J.S[5] = cur.s1.y;
                 }
                 real o[6];
                 pair_force<real, SOLID>(d, r2, I, J, K, o);
@@ -293,6 +319,7 @@ void k_pairs(Params P, Grid g, PV<real> tg,
 #pragma unroll
                 for (int k = 0; k < 9; ++k) acc[k].add(o[k]);
             }
+            cur = nxt;
         }
         cnt = 0;
     };
@@ -310,6 +337,23 @@ void k_pairs(Params P, Grid g, PV<real> tg,
         const int gx1 = wave_max(in ? x1 : -1);
         const int gy = (int)(key % (uint32_t)g.ny), gz = (int)(key / (uint32_t)g.ny);
         const real R2in = in ? R2 : real(-1);
+        // Filter frame.  FP32 split: positions relative to the corner of bucket
+        // column gx0 of the target's row, ((c - gx0) L + off) in x and
+        // (dy L + off) in y, z, so a test is three subtractions.  The filter
+        // only shortlists: every listed pair is re-evaluated from the exact,
+        // odd d and has F = 0 beyond 2h.  FP64: absolute positions (the test is
+        // then exactly the neighbour predicate).
+        real fo[3];
+        const real gx0f = (real)gx0;
+        if constexpr (SPLIT) {
+            fo[0] = (T.cxf - gx0f) * T.Lf + T.o[0];
+            fo[1] = T.o[1];
+            fo[2] = T.o[2];
+        } else {
+            fo[0] = T.x[0];
+            fo[1] = T.x[1];
+            fo[2] = T.x[2];
+        }
         int nwin = 0;
         for (int r = 0; r < 9; ++r) {
             const int dz = r / 3 - 1, dy = r % 3 - 1;
@@ -326,7 +370,8 @@ void k_pairs(Params P, Grid g, PV<real> tg,
                 const int slot = nwin++;
                 if (lane == 0) {
                     wbase[wave][slot] = wb;
-                    wrow[wave][slot] = (uint32_t)r;
+                    wdy[wave][slot] = ddy;
+                    wdz[wave][slot] = ddz;
                 }
                 const uint32_t we = (ue - wb > kWinLen) ? wb + kWinLen : ue;
                 for (uint32_t c = wb; c < we; c += kChunk) {
@@ -336,6 +381,11 @@ void k_pairs(Params P, Grid g, PV<real> tg,
                     v4 rec;
                     if (k < we) {
                         rec = src.pos[k];
+                        if constexpr (SPLIT) {
+                            rec.x = (rec.w - gx0f) * T.Lf + rec.x;
+                            rec.y = ddy + rec.y;
+                            rec.z = ddz + rec.z;
+                        }
                     } else {
                         rec.x = rec.y = rec.z = kFar;
                         rec.w = real(0);
@@ -343,22 +393,18 @@ void k_pairs(Params P, Grid g, PV<real> tg,
                     stage[wave][lane] = rec;
                     wave_lds_sync();
                     const int nsub = (int)((((we - c) < (uint32_t)kChunk ? (we - c) : (uint32_t)kChunk) + kSub - 1) / kSub);
+                    const uint32_t base0 = ((uint32_t)slot << kWinBits) + (c - wb);
                     for (int sb = 0; sb < nsub; ++sb) {
+                        // at most kSub more entries per lane before the next check
                         if (__ballot(cnt > kHitCap - kSub)) flush();
-                        uint32_t mask = 0;
+                        const uint32_t base = base0 + (uint32_t)(sb * kSub);
 #pragma unroll
                         for (int m = 0; m < kSub; ++m) {
-                            real d[3];
-                            diff<real>(T, stage[wave][sb * kSub + m], ddy, ddz, d);
-                            mask |= (r2_of<real>(d) < R2in) ? (1u << m) : 0u;
-                        }
-                        // list the hits in ascending source index
-                        const uint32_t base = ((uint32_t)slot << kWinBits) + (c - wb) + (uint32_t)(sb * kSub);
-                        while (mask) {
-                            const int b = __ffs(mask) - 1;
-                            mask &= mask - 1;
-                            hits[cnt][tid] = (uint16_t)(base + (uint32_t)b);
-                            ++cnt;
+                            const v4 q = stage[wave][sb * kSub + m];
+                            const real d[3] = {q.x - fo[0], q.y - fo[1], q.z - fo[2]};
+                            // the entry is written always and kept only when it is a hit
+                            hits[cnt][tid] = (uint16_t)(base + (uint32_t)m);
+                            cnt += (r2_of<real>(d) < R2in) ? 1 : 0;
                         }
                     }
                 }

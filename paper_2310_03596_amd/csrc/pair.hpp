@@ -85,7 +85,7 @@ template <typename real>
 __device__ inline real kernel_F(real r, const PairK<real> &K)
 {
     real q = r * K.hinv;
-    real t = real(2) - q;
+    real t = max(real(2) - q, real(0));      // zero beyond the support
     real fin = q * (real(3) - real(2.25) * q);
     real fout = real(0.75) * t * t;
     return K.Fc * (q < real(1) ? fin : fout);
@@ -124,50 +124,73 @@ __device__ inline void sym_mul(const real *S, const real n[3], real o[3])
     o[2] = S[4] * n[0] + S[5] * n[1] + S[2] * n[2];
 }
 
-// FORCE terms of target i from source j; d = x_j - x_i, r2 = |d|^2 > 0.
+// FORCE terms of target i from source j; d = x_j - x_i, r2 = |d|^2.
+// The formulas above, evaluated on the unnormalised d with one reciprocal
+// square root (n = d rinv, g = G d with G = F rinv), the sums and
+// differences of the two velocities (sv = v_i + v_j even, dv = v_j - v_i
+// odd) and their projections s1 = dv . d (even) and s2 = sv . d (odd):
+//   u_i - u_j = -s1 rinv,  v* = sv / 2 + du rinv d,
+//   |v*|^2 = |sv|^2 / 4 + du (s2 rinv + du),  v* . d = s2 / 2 + du r,
+//   wdot = w_i w_j G s1.
+// Every product keeps the parity of its factors, so each term stays exactly
+// even (volume) or odd (mass, momentum, energy) under i <-> j.
 template <typename real, bool SOLID>
 __device__ inline void pair_force(const real d[3], real r2, const Part<real, SOLID> &I,
                                   const Part<real, SOLID> &J, const PairK<real> &K, real out[6])
 {
     real r, rinv;
     inv_len<real>(r2, r, rinv);
-    real F = kernel_F<real>(r, K);
-    real n[3] = {d[0] * rinv, d[1] * rinv, d[2] * rinv};
-    real g[3] = {F * n[0], F * n[1], F * n[2]};
-    real ui = I.v[0] * n[0] + I.v[1] * n[1] + I.v[2] * n[2];
-    real uj = J.v[0] * n[0] + J.v[1] * n[1] + J.v[2] * n[2];
-    real rb = real(0.5) * (I.rho + J.rho);
-    real cb = real(0.5) * (I.c + J.c);
-    real pb = real(0.5) * (I.p + J.p);
-    real Z = rb * cb;
+    const real F = kernel_F<real>(r, K);
+    const real G = F * rinv;
+    const real sv[3] = {I.v[0] + J.v[0], I.v[1] + J.v[1], I.v[2] + J.v[2]};
+    const real dv[3] = {J.v[0] - I.v[0], J.v[1] - I.v[1], J.v[2] - I.v[2]};
+    const real s1 = dv[0] * d[0] + dv[1] * d[1] + dv[2] * d[2];
+    const real s2 = sv[0] * d[0] + sv[1] * d[1] + sv[2] * d[2];
+    const real rb = real(0.5) * (I.rho + J.rho);
+    const real cb = real(0.5) * (I.c + J.c);
+    const real pb = real(0.5) * (I.p + J.p);
+    const real Z = rb * cb;
     real Pi = I.p, Pj = J.p;
-    real Snb[3] = {real(0), real(0), real(0)};
+    real Sd[3] = {real(0), real(0), real(0)};   // (S_i + S_j) d
     if constexpr (SOLID) {
         real si[3], sj[3];
-        sym_mul<real>(I.S, n, si);
-        sym_mul<real>(J.S, n, sj);
-        Pi = I.p - (n[0] * si[0] + n[1] * si[1] + n[2] * si[2]);
-        Pj = J.p - (n[0] * sj[0] + n[1] * sj[1] + n[2] * sj[2]);
+        sym_mul<real>(I.S, d, si);
+        sym_mul<real>(J.S, d, sj);
+        const real r2inv = rinv * rinv;
+        Pi = I.p - (d[0] * si[0] + d[1] * si[1] + d[2] * si[2]) * r2inv;
+        Pj = J.p - (d[0] * sj[0] + d[1] * sj[1] + d[2] * sj[2]) * r2inv;
 #pragma unroll
-        for (int a = 0; a < 3; ++a) Snb[a] = real(0.5) * (si[a] + sj[a]);
+        for (int a = 0; a < 3; ++a) Sd[a] = si[a] + sj[a];
     }
-    real du = K.half_beta * (Pi - Pj) * rcp<real>(Z);
-    real ps = pb + K.half_beta * Z * (ui - uj);
-    real vs[3];
+    const real du = K.half_beta * (Pi - Pj) * rcp<real>(Z);
+    const real ps = pb - (K.half_beta * Z * s1) * rinv;
+    const real A = real(2) * I.w * J.w;
+    const real Phi = rb * du * F;
+    const real mA = -A;
+    const real psG = ps * G;
+    out[0] = mA * Phi;
+    const real ca = real(0.5) * out[0];                       // -A Phi / 2
+    const real k1 = mA * ((Phi * du) * rinv + psG);            // even
+    const real kS = real(0.5) * A * G;                         // traction of mean(S): +A F Snb = kS Sd
 #pragma unroll
-    for (int a = 0; a < 3; ++a) vs[a] = real(0.5) * (I.v[a] + J.v[a]) + du * n[a];
-    real Es = real(0.5) * (I.e + J.e) + real(0.5) * (vs[0] * vs[0] + vs[1] * vs[1] + vs[2] * vs[2]);
-    real A = real(2) * I.w * J.w;
-    real Phi = rb * du * F;
-    real t[3];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) t[a] = ps * g[a] - F * Snb[a];
-    out[0] = -A * Phi;
-#pragma unroll
-    for (int a = 0; a < 3; ++a) out[1 + a] = -A * (Phi * vs[a] + t[a]);
-    out[4] = -A * (Phi * Es + (t[0] * vs[0] + t[1] * vs[1] + t[2] * vs[2]));
-    real dv[3] = {J.v[0] - I.v[0], J.v[1] - I.v[1], J.v[2] - I.v[2]};
-    out[5] = I.w * J.w * (dv[0] * g[0] + dv[1] * g[1] + dv[2] * g[2]);
+    for (int a = 0; a < 3; ++a) {
+        real m = ca * sv[a] + k1 * d[a];
+        if constexpr (SOLID) m += kS * Sd[a];
+        out[1 + a] = m;
+    }
+    const real sv2 = sv[0] * sv[0] + sv[1] * sv[1] + sv[2] * sv[2];
+    const real vs2 = real(0.25) * sv2 + du * (s2 * rinv + du);
+    const real Es = real(0.5) * (I.e + J.e) + real(0.5) * vs2;
+    const real vsd = real(0.5) * s2 + du * r;                  // v* . d
+    real tv = psG * vsd;                                       // t . v* (fluid part)
+    if constexpr (SOLID) {
+        // - F mean(S) n . v* = -(G / 2) Sd . (sv / 2 + du rinv d)
+        const real sdsv = Sd[0] * sv[0] + Sd[1] * sv[1] + Sd[2] * sv[2];
+        const real sdd = Sd[0] * d[0] + Sd[1] * d[1] + Sd[2] * d[2];
+        tv -= real(0.5) * G * (real(0.5) * sdsv + du * rinv * sdd);
+    }
+    out[4] = mA * (Phi * Es + tv);
+    out[5] = real(0.5) * A * G * s1;
 }
 
 // GRADIENT terms: L_ab = w_j (v_j - v_i)_a g_b.
