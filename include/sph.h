@@ -225,12 +225,16 @@ int sph_count_pairs(const sph_params *params, const sph_grid *grid, const sph_pa
 /* Adjoint of the local-local FORCE pass (step e) of a fluid.  With rates_bar
  * the cotangents of the rates (hi only), accumulates into `bar` the
  * cotangents of x, v, omega, rho, p, c and e of every particle of the
- * hash-sorted array p.  Uses the pair terms' exact (anti)symmetry so each
- * particle gathers from its neighbours without atomics.  Errors:
- * SPH_ERR_ARG, SPH_ERR_UNSUPPORTED (solids). */
+ * hash-sorted array p.  Each pair term T(s_i, s_j) equals +-T(s_j, s_i)
+ * (odd for mass, momentum and energy, even for volume), so a particle
+ * gathers its whole cotangent from its neighbours' rate cotangents without
+ * atomics.  The workspace (sph_workspace_size with SPH_SOLID_J2, which has
+ * room for the extra staged records) receives packed copies of the
+ * particles and their rate cotangents.  Errors: SPH_ERR_ARG,
+ * SPH_ERR_WORKSPACE, SPH_ERR_UNSUPPORTED (solids). */
 int sph_interact_adjoint(const sph_params *params, const sph_grid *grid, const sph_particles *p,
                          sph_cells cells, const sph_rates *rates_bar, const sph_adjoint *bar,
-                         void *stream);
+                         void *ws, size_t ws_bytes, void *stream);
 
 /* Adjoint of step (g) for a fluid.  stage = SPH_STAGE_MOTION: p is the state
  * BEFORE the update (hash-sorted), rates its FORCE rates; on entry bar holds

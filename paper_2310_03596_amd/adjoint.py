@@ -1,0 +1,168 @@
+"""Checkpointed hand adjoint of a fluid rollout, behind torch.autograd.
+
+Objective: the kinetic energy J = sum m |v|^2 / 2 after `nsteps` fixed-dt
+steps of the fluid path (hash + sort + FORCE pass + update; free boundaries,
+no gravity).  Differentiable inputs: the initial velocities (at fixed
+specific internal energy, so E0 = e0 + |v0|^2 / 2) and the sound speed c0.
+
+Forward keeps a copy of the whole particle state every `ckpt` steps.
+Backward walks the segments in reverse: it restores a segment's checkpoint,
+recomputes its steps (so the neighbour tables are rebuilt) keeping each
+step's sorted state, permutation, bucket table and rates, then runs the
+library's reverse kernels step by step.  Every step of the path, forward and
+reverse, runs in libsph; this module only sequences calls and owns buffers.
+"""
+from __future__ import annotations
+
+import copy
+
+import numpy as np
+import torch
+
+from . import _lib as L
+from .sim import Sim
+from .state import Particles, Rates, cells_struct, real_dtype, stream_handle
+
+
+def _clone_particles(p: Particles) -> Particles:
+    q = copy.copy(p)
+    for f in ("x", "off", "hash", "id", "v", "m", "w", "rho", "p", "c", "e", "E", "S", "ep"):
+        a = getattr(p, f)
+        setattr(q, f, None if a is None else a.clone())
+    return q
+
+
+def _copy_into(dst: Particles, src: Particles):
+    for f in ("x", "off", "hash", "id", "v", "m", "w", "rho", "p", "c", "e", "E"):
+        a = getattr(src, f)
+        if a is not None:
+            getattr(dst, f).copy_(a)
+
+
+class Cotangent:
+    """Device buffers of a state cotangent (sph_adjoint), in the form's precision."""
+
+    def __init__(self, n: int, prec: int, device):
+        real = real_dtype(prec)
+        self.x = torch.zeros((3, n), dtype=real, device=device)
+        self.v = torch.zeros((3, n), dtype=real, device=device)
+        self.m, self.w, self.E, self.rho, self.p, self.c, self.e = [
+            torch.zeros(n, dtype=real, device=device) for _ in range(7)]
+
+    def struct(self) -> L.SphAdjoint:
+        a = L.SphAdjoint()
+        for d in range(3):
+            a.x[d] = self.x[d].data_ptr()
+            a.v[d] = self.v[d].data_ptr()
+        a.m, a.omega, a.E = self.m.data_ptr(), self.w.data_ptr(), self.E.data_ptr()
+        a.rho, a.p, a.c, a.e = self.rho.data_ptr(), self.p.data_ptr(), self.c.data_ptr(), self.e.data_ptr()
+        return a
+
+    def state_struct(self) -> L.SphAdjoint:
+        """Only the state fields (what a permutation carries)."""
+        a = L.SphAdjoint()
+        for d in range(3):
+            a.x[d] = self.x[d].data_ptr()
+            a.v[d] = self.v[d].data_ptr()
+        a.m, a.omega, a.E = self.m.data_ptr(), self.w.data_ptr(), self.E.data_ptr()
+        return a
+
+
+class KineticEnergyRollout:
+    """Forward rollout with checkpoints, and its reverse pass."""
+
+    def __init__(self, wl, prec: int, nsteps: int, ckpt: int, dt: float, device="cuda"):
+        self.wl, self.prec, self.nsteps, self.ckpt, self.dt = wl, prec, nsteps, max(1, ckpt), dt
+        self.device = device
+        self.e0 = wl.E - 0.5 * np.einsum("ij,ij->i", wl.v, wl.v)   # specific internal energy, held fixed
+
+    def _workload(self, v0: np.ndarray, c0: float):
+        w = copy.copy(self.wl)
+        w.v = np.ascontiguousarray(v0, dtype=np.float64)
+        w.E = self.e0 + 0.5 * np.einsum("ij,ij->i", w.v, w.v)
+        w.params = dict(self.wl.params, c0=float(c0))
+        return w
+
+    def forward(self, v0: np.ndarray, c0: float) -> float:
+        sim = Sim(self._workload(v0, c0), self.prec, self.device, fixed_dt=self.dt)
+        self.sim = sim
+        self.ckpts = []
+        for k in range(self.nsteps):
+            if k % self.ckpt == 0:
+                self.ckpts.append(_clone_particles(sim.A))
+            sim.step()
+        torch.cuda.synchronize()
+        self.final = sim.A
+        return float(sim.diagnostics()[6])
+
+    def backward(self, gJ: float):
+        sim = self.sim
+        n, prec, dev = sim.n, self.prec, self.device
+        real = real_dtype(prec)
+        st = stream_handle()
+        bar = Cotangent(n, prec, dev)
+        tmp = Cotangent(n, prec, dev)
+        # dJ/d(final state): J = sum m |v|^2 / 2
+        v = self.final.v.double()
+        bar.v.copy_((gJ * self.final.m.double() * v).to(real))
+        bar.m.copy_((gJ * 0.5 * (v * v).sum(0)).to(real))
+        c0bar = torch.zeros(1, dtype=torch.float64, device=dev)
+        rbar = Rates(n, prec, False, dev)
+        ws_adj_bytes = L.sph_workspace_size(sim.grid, n, prec, L.SPH_SOLID_J2)
+        ws_adj = torch.zeros(ws_adj_bytes, dtype=torch.uint8, device=dev)
+        fixed = sim.fixed.data_ptr()
+        for seg in reversed(range(len(self.ckpts))):
+            k0 = seg * self.ckpt
+            k1 = min(k0 + self.ckpt, self.nsteps)
+            _copy_into(sim.A, self.ckpts[seg])
+            saved = []
+            for _ in range(k0, k1):
+                sim.build()
+                srt = _clone_particles(sim.A)
+                perm = sim.perm.clone()
+                start = sim.start.clone()
+                a = sim.A.struct()
+                r = sim.rates.struct()
+                L.sph_interact(sim.params, sim.grid, L.SPH_PASS_FORCE, a, None, None, a, sim.cells, 1, r,
+                               sim.ws.data_ptr(), sim.ws_bytes, st)
+                rates = Rates(n, prec, False, dev)
+                rates.hi.copy_(sim.rates.hi)
+                if rates.lo is not None:
+                    rates.lo.copy_(sim.rates.lo)
+                L.sph_integrate(sim.params, L.SPH_STAGE_MOTION, a, r, fixed, sim.diag[0].data_ptr(),
+                                sim.ws.data_ptr(), sim.ws_bytes, st)
+                saved.append((srt, perm, start, rates))
+            for srt, perm, start, rates in reversed(saved):
+                ps = srt.struct()
+                L.sph_integrate_adjoint(sim.params, L.SPH_STAGE_MOTION, ps, rates.struct(), fixed, bar.struct(),
+                                        rbar.struct(), None, None, 0, st)
+                L.sph_interact_adjoint(sim.params, sim.grid, ps, cells_struct(start, sim.nc), rbar.struct(),
+                                       bar.struct(), ws_adj.data_ptr(), ws_adj_bytes, st)
+                L.sph_integrate_adjoint(sim.params, L.SPH_STAGE_EOS, ps, None, None, bar.struct(), None,
+                                        c0bar.data_ptr(), sim.ws.data_ptr(), sim.ws_bytes, st)
+                L.sph_permute_adjoint(prec, n, perm.data_ptr(), bar.state_struct(), tmp.state_struct(), st)
+                bar, tmp = tmp, bar
+        torch.cuda.synchronize()
+        # the initial state is in id order; E0 = e0 + |v0|^2 / 2 adds dJ/dE0 v0 to dJ/dv0
+        v0 = self.ckpts[0].v.double()
+        vbar = bar.v.double() + bar.E.double()[None, :] * v0
+        return vbar.T.cpu().numpy(), float(c0bar.cpu()[0])
+
+
+class KineticEnergy(torch.autograd.Function):
+    """J(v0, c0) with the hand adjoint as its backward.
+
+    v0: (n, 3) float64 tensor (host), c0: 0-dim float64 tensor.  `rollout`
+    is a KineticEnergyRollout that fixes the rest of the problem.
+    """
+
+    @staticmethod
+    def forward(ctx, v0, c0, rollout):
+        J = rollout.forward(v0.detach().cpu().numpy(), float(c0))
+        ctx.rollout = rollout
+        return torch.tensor(J, dtype=torch.float64)
+
+    @staticmethod
+    def backward(ctx, gJ):
+        vbar, c0bar = ctx.rollout.backward(float(gJ))
+        return torch.from_numpy(vbar), torch.tensor(c0bar, dtype=torch.float64), None

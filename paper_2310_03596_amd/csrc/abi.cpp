@@ -306,7 +306,7 @@ int sph_integrate(const sph_params *params, int stage, sph_particles *p, const s
 }
 
 int sph_interact_adjoint(const sph_params *params, const sph_grid *grid, const sph_particles *p, sph_cells cells,
-                         const sph_rates *rates_bar, const sph_adjoint *bar, void *stream)
+                         const sph_rates *rates_bar, const sph_adjoint *bar, void *ws, size_t ws_bytes, void *stream)
 {
     Grid g;
     Params P;
@@ -323,7 +323,10 @@ int sph_interact_adjoint(const sph_params *params, const sph_grid *grid, const s
     if (!bar->omega || !bar->rho || !bar->p || !bar->c || !bar->e)
         return fail(SPH_ERR_ARG, "bar.omega/rho/p/c/e is NULL");
     if (p->n == 0) return SPH_OK;
-    return hip_status(launch_interact_adjoint(P, g, params->prec, *p, cells.start, *rates_bar, *bar,
+    if (p->n >= (1u << 28)) return fail(SPH_ERR_ARG, "n = %u must be below 2^28", p->n);
+    Workspace w;
+    if (!check_ws(ws, ws_bytes, p->n, w, stage_bytes(params->prec, SPH_SOLID_J2))) return SPH_ERR_WORKSPACE;
+    return hip_status(launch_interact_adjoint(P, g, params->prec, *p, cells.start, *rates_bar, *bar, w,
                                               (hipStream_t)stream),
                       "sph_interact_adjoint");
 }

@@ -1,9 +1,136 @@
-// Hand-written adjoint of the fluid step (reverse of steps e and g).
-#include "pair.hpp"
+// Hand-written adjoint of the fluid step (reverse of steps g and e of
+// Section II; the pair-pass reverse lives with the pair kernel).
+//
+// State of one step: x, v, m, omega, E (per particle).  Derived fields that
+// the pair terms read: rho = m / omega, p and c from the Tait EOS, e = E -
+// |v|^2 / 2.  One reverse step, for a step that started from the hash-sorted
+// state s (saved or recomputed) with rates R and time step dt:
+//   1. MOTION:  cotangent of the updated state -> direct cotangent of s and
+//               cotangents of the rates (k_motion_adj);
+//   2. pair pass reverse (sph_interact_adjoint) -> cotangents of x, v, omega
+//               and of the derived rho, p, c, e;
+//   3. EOS:     fold the derived cotangents into m, omega, v, E and c0
+//               (k_eos_adj, deterministic sum for c0);
+//   4. permute: scatter back through the step's sort permutation.
+// Elementwise and HBM-bound; arithmetic in FP64, storage in the form's
+// precision.
+#include "common.hpp"
 
 namespace sph {
 
 namespace {
+
+template <typename real, bool SPLIT>
+__global__ __launch_bounds__(kBlock) void k_motion_adj(PV<real> s, RV<real> R, const double *__restrict__ dtp,
+                                                       AV<real> bar, RV<real> rbar)
+{
+    uint32_t i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= s.n) return;
+    const double dt = *dtp;
+    double r[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) r[k] = (double)R.hi[k][i] + (SPLIT ? (double)R.lo[k][i] : 0.0);
+    const double m = (double)s.m[i];
+    const double E = s.E[i];
+    double v[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) v[a] = (double)s.v[a][i];
+    // forward: mn = m + dt r0, V = m v + dt r_{1+a}, vn = V / mn,
+    // EE = m E + dt r4, En = EE / mn, wn = w + dt r5, xn = x + dt vn
+    const double mn = m + dt * r[0];
+    const double minv = 1.0 / mn;
+    double vn[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) vn[a] = (m * v[a] + dt * r[1 + a]) * minv;
+    const double En = (m * E + dt * r[4]) * minv;
+    // reverse
+    double bxn[3], bvn[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        bxn[a] = (double)bar.x[a][i];
+        bvn[a] = (double)bar.v[a][i] + dt * bxn[a];
+    }
+    const double bEn = (double)bar.E[i];
+    const double bwn = (double)bar.w[i];
+    double bmn = (double)bar.m[i] - bEn * En * minv;
+    double bV[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        bmn -= bvn[a] * vn[a] * minv;
+        bV[a] = bvn[a] * minv;
+    }
+    const double bEE = bEn * minv;
+    double bm = bmn + bEE * E;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        bm += bV[a] * v[a];
+        bar.x[a][i] = (real)bxn[a];
+        bar.v[a][i] = (real)(bV[a] * m);
+        rbar.hi[1 + a][i] = (real)(dt * bV[a]);
+    }
+    bar.m[i] = (real)bm;
+    bar.E[i] = (real)(bEE * m);
+    bar.w[i] = (real)bwn;
+    rbar.hi[0][i] = (real)(dt * bmn);
+    rbar.hi[4][i] = (real)(dt * bEE);
+    rbar.hi[5][i] = (real)(dt * bwn);
+}
+
+// Fold the cotangents of rho, p, c, e into m, omega, v, E; clear them; the
+// per-block partial of d/dc0 goes to partials (slot 0).
+template <typename real>
+__global__ __launch_bounds__(kBlock) void k_eos_adj(Params P, PV<real> s, AV<real> bar, double *__restrict__ partials)
+{
+    __shared__ double sh[kBlock / kWave];
+    uint32_t i = blockIdx.x * kBlock + threadIdx.x;
+    double dc0 = 0.0;
+    if (i < s.n) {
+        const double m = (double)s.m[i], w = (double)s.w[i];
+        const double rho = m / w;
+        const double sr = rho / P.rho0;
+        const double p = P.B * (pow(sr, P.gamma) - 1.0);
+        const double c = P.c0 * pow(sr, 0.5 * (P.gamma - 1.0));
+        const double bp = (double)bar.p[i], bc = (double)bar.c[i], be = (double)bar.e[i];
+        // p' = c^2, c' = c (gamma - 1) / (2 rho); p and c scale as c0^2 and c0
+        const double brho = (double)bar.rho[i] + bp * c * c + bc * c * (P.gamma - 1.0) / (2.0 * rho);
+        dc0 = (bp * 2.0 * p + bc * c) / P.c0;
+        bar.m[i] = (real)((double)bar.m[i] + brho / w);
+        bar.w[i] = (real)((double)bar.w[i] - brho * rho / w);
+        bar.E[i] = (real)((double)bar.E[i] + be);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) bar.v[a][i] = (real)((double)bar.v[a][i] - be * (double)s.v[a][i]);
+        bar.rho[i] = real(0);
+        bar.p[i] = real(0);
+        bar.c[i] = real(0);
+        bar.e[i] = real(0);
+    }
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) dc0 += __shfl_down(dc0, off, kWave);
+    if (lane == 0) sh[wave] = dc0;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int k = 0; k < kBlock / kWave; ++k) t += sh[k];
+        partials[blockIdx.x] = t;
+    }
+}
+
+// One workgroup folds the block partials in a fixed order and adds to *out.
+__global__ __launch_bounds__(kBlock) void k_sum_into(const double *__restrict__ partials, uint32_t nblocks,
+                                                     double *__restrict__ out)
+{
+    __shared__ double sh[kBlock];
+    double t = 0.0;
+    for (uint32_t b = threadIdx.x; b < nblocks; b += kBlock) t += partials[b];
+    sh[threadIdx.x] = t;
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out += sh[0];
+}
 
 template <typename real>
 __global__ __launch_bounds__(kBlock) void k_permute(uint32_t n, const uint32_t *__restrict__ perm, AV<real> in,
@@ -22,19 +149,31 @@ __global__ __launch_bounds__(kBlock) void k_permute(uint32_t n, const uint32_t *
     if (in.E) out.E[d] = in.E[k];
 }
 
-}  // namespace
-
-hipError_t launch_interact_adjoint(const Params &, const Grid &, int, const sph_particles &, const uint32_t *,
-                                   const sph_rates &, const sph_adjoint &, hipStream_t)
+template <typename real>
+hipError_t go(const Params &P, int stage, const sph_particles &p, const sph_rates &r, const double *dt,
+              const sph_adjoint &bar, const sph_rates &rbar, double *pbar, const Workspace &ws, hipStream_t s)
 {
-    return hipErrorNotSupported;
+    constexpr bool SPLIT = sizeof(real) == 4;
+    uint32_t blocks = div_up(p.n, kBlock);
+    if (stage == SPH_STAGE_MOTION) {
+        if (blocks)
+            k_motion_adj<real, SPLIT><<<blocks, kBlock, 0, s>>>(view<real>(p), view<real>(r), dt, view<real>(bar),
+                                                                view<real>(rbar));
+    } else {
+        if (blocks) k_eos_adj<real><<<blocks, kBlock, 0, s>>>(P, view<real>(p), view<real>(bar), ws.partials);
+        k_sum_into<<<1, kBlock, 0, s>>>(ws.partials, blocks, pbar);
+    }
+    return hipGetLastError();
 }
 
-hipError_t launch_integrate_adjoint(const Params &, int, int, const sph_particles &, const sph_rates &,
-                                    const double *, const sph_adjoint &, const sph_rates &, double *,
-                                    const Workspace &, hipStream_t)
+}  // namespace
+
+hipError_t launch_integrate_adjoint(const Params &P, int prec, int stage, const sph_particles &p, const sph_rates &r,
+                                    const double *dt, const sph_adjoint &bar, const sph_rates &rbar, double *pbar,
+                                    const Workspace &ws, hipStream_t s)
 {
-    return hipErrorNotSupported;
+    if (prec == SPH_FP64) return go<double>(P, stage, p, r, dt, bar, rbar, pbar, ws, s);
+    return go<float>(P, stage, p, r, dt, bar, rbar, pbar, ws, s);
 }
 
 hipError_t launch_permute_adjoint(int prec, uint32_t n, const uint32_t *perm, const sph_adjoint &in,

@@ -235,7 +235,7 @@ hipError_t launch_integrate(const Params &P, int prec, int stage, const sph_part
                             hipStream_t s);
 hipError_t launch_interact_adjoint(const Params &P, const Grid &g, int prec, const sph_particles &p,
                                    const uint32_t *start, const sph_rates &rbar, const sph_adjoint &bar,
-                                   hipStream_t s);
+                                   const Workspace &ws, hipStream_t s);
 hipError_t launch_integrate_adjoint(const Params &P, int prec, int stage, const sph_particles &p,
                                     const sph_rates &r, const double *dt, const sph_adjoint &bar,
                                     const sph_rates &rbar, double *pbar, const Workspace &ws,

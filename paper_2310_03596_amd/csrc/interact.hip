@@ -47,15 +47,18 @@ constexpr int kHitCap = 48;                // listed hits per lane (u16 entries)
 constexpr int kWinBits = 12;               // hit entry: window slot (4 bits) | offset (12 bits)
 constexpr uint32_t kWinLen = 1u << kWinBits;
 constexpr int kMaxWin = 16;
+constexpr int kPassAdjoint = 2;            // reverse mode of the FORCE pass (fluid)
 #ifndef SPH_PAIR_WAVES_PER_EU
 #define SPH_PAIR_WAVES_PER_EU 5
 #endif
 // Occupancy target (waves per SIMD; caps VGPRs at 512 / target) per
 // variant: the fluid FP32 pass fits 5 without spills, the larger solid and
-// FP64 bodies fit 4 and 3.
-template <typename real, bool SOLID>
+// FP64 bodies fit 4 and 3; the adjoint body (11 cotangents) 3 and 2.
+template <typename real, bool SOLID, bool ADJ>
 struct PairOccupancy {
-    static constexpr int value = sizeof(real) == 4 ? (SOLID ? 4 : SPH_PAIR_WAVES_PER_EU) : (SOLID ? 3 : 4);
+    static constexpr int fp32 = ADJ ? 3 : (SOLID ? 4 : SPH_PAIR_WAVES_PER_EU);
+    static constexpr int fp64 = ADJ ? 2 : (SOLID ? 3 : 4);
+    static constexpr int value = sizeof(real) == 4 ? fp32 : fp64;
 };
 
 // (2h)^2 predicate on FP64 differences without FMA contraction, identical
@@ -181,16 +184,15 @@ struct Acc {
 };
 
 template <typename real, int PASS, bool SOLID, bool SELF>
-__global__ __launch_bounds__(kPairBlock) __attribute__((amdgpu_waves_per_eu(PairOccupancy<real, SOLID>::value)))
-void k_pairs(Params P, Grid g, PV<real> tg,
-                                                      const uint32_t *__restrict__ tidx,
-                                                      const uint32_t *__restrict__ ntdev, Stage<real> src,
-                                                      const uint32_t *__restrict__ sstart, int zero_first,
-                                                      RV<real> R)
+__global__ __launch_bounds__(kPairBlock)
+__attribute__((amdgpu_waves_per_eu(PairOccupancy<real, SOLID, PASS == kPassAdjoint>::value)))
+void k_pairs(Params P, Grid g, PV<real> tg, const uint32_t *__restrict__ tidx, const uint32_t *__restrict__ ntdev,
+             Stage<real> src, const uint32_t *__restrict__ sstart, int zero_first, RV<real> R, AV<real> B)
 {
     using v4 = typename Vec4<real>::type;
     constexpr bool SPLIT = sizeof(real) == 4;
-    constexpr int NOUT = PASS == SPH_PASS_FORCE ? 6 : 9;
+    constexpr bool ADJ = PASS == kPassAdjoint;
+    constexpr int NOUT = PASS == SPH_PASS_FORCE ? 6 : (ADJ ? 11 : 9);
     __shared__ uint16_t hits[kHitCap][kPairBlock];
     __shared__ v4 stage[kWaves][kChunk];
     __shared__ uint32_t wbase[kWaves][kMaxWin];   // first source index of each window
@@ -236,22 +238,29 @@ void k_pairs(Params P, Grid g, PV<real> tg,
         }
     }
     Part<real, SOLID> I;
-    if constexpr (PASS == SPH_PASS_FORCE) {
+    real rbi[6];   // adjoint: the target's rate cotangents
+    if constexpr (PASS == SPH_PASS_FORCE || ADJ) {
         load_part<real, SOLID>(tg, i, I);
     } else {
 #pragma unroll
         for (int d = 0; d < 3; ++d) I.v[d] = tg.v[d][i];
     }
+    if constexpr (ADJ) {
+#pragma unroll
+        for (int k = 0; k < 6; ++k) rbi[k] = R.hi[k][i];
+    }
 
     Acc acc[NOUT];
 #pragma unroll
     for (int k = 0; k < NOUT; ++k) {
-        real *hi = PASS == SPH_PASS_FORCE ? R.hi[k] : R.Lhi[k];
-        real *lo = PASS == SPH_PASS_FORCE ? R.lo[k] : R.Llo[k];
         double s0 = 0.0;
-        if (!zero_first && valid) {
-            s0 = (double)hi[i];
-            if (SPLIT) s0 += (double)lo[i];
+        if constexpr (!ADJ) {
+            real *hi = PASS == SPH_PASS_FORCE ? R.hi[k] : R.Lhi[k];
+            real *lo = PASS == SPH_PASS_FORCE ? R.lo[k] : R.Llo[k];
+            if (!zero_first && valid) {
+                s0 = (double)hi[i];
+                if (SPLIT) s0 += (double)lo[i];
+            }
         }
         acc[k].s = s0;
     }
@@ -272,8 +281,8 @@ void k_pairs(Params P, Grid g, PV<real> tg,
         q.qz = wdz[wave][slot];
         q.p = src.pos[jj];
         q.a = src.va[jj];
-        if constexpr (PASS == SPH_PASS_FORCE) q.b = src.vb[jj];
-        if constexpr (PASS == SPH_PASS_FORCE && SOLID) {
+        if constexpr (PASS == SPH_PASS_FORCE || ADJ) q.b = src.vb[jj];
+        if constexpr ((PASS == SPH_PASS_FORCE && SOLID) || ADJ) {
             q.s0 = src.s0[jj];
             q.s1 = src.s1[jj];
         }
@@ -312,6 +321,34 @@ void k_pairs(Params P, Grid g, PV<real> tg,
                 pair_force<real, SOLID>(d, r2, I, J, K, o);
 #pragma unroll
                 for (int k = 0; k < 6; ++k) acc[k].add(o[k]);
+            } else if constexpr (ADJ) {
+                Part<real, false> J, Ii;
+                J.v[0] = a.x;
+                J.v[1] = a.y;
+                J.v[2] = a.z;
+                J.w = a.w;
+                J.rho = cur.b.x;
+                J.p = cur.b.y;
+                J.c = cur.b.z;
+                J.e = cur.b.w;
+#pragma unroll
+                for (int k = 0; k < 3; ++k) Ii.v[k] = I.v[k];
+                Ii.w = I.w;
+                Ii.rho = I.rho;
+                Ii.p = I.p;
+                Ii.c = I.c;
+                Ii.e = I.e;
+                // T(s_j, s_i) = sigma T(s_i, s_j): mass, momentum and energy terms
+                // are odd (sigma = -1), the volume term even (+1)
+                const real rbj[6] = {cur.s0.x, cur.s0.y, cur.s0.z, cur.s0.w, cur.s1.x, cur.s1.y};
+                real wb[6];
+#pragma unroll
+                for (int k = 0; k < 5; ++k) wb[k] = rbi[k] - rbj[k];
+                wb[5] = rbi[5] + rbj[5];
+                real o[11] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+                pair_force_vjp<real>(d, r2, Ii, J, K, wb, o);
+#pragma unroll
+                for (int k = 0; k < 11; ++k) acc[k].add(o[k]);
             } else {
                 const real vj[3] = {a.x, a.y, a.z};
                 real o[9];
@@ -413,14 +450,40 @@ void k_pairs(Params P, Grid g, PV<real> tg,
         flush();
     }
     if (!valid) return;
+    if constexpr (ADJ) {
+        // accumulate the cotangents of x, v, omega, rho, p, c, e
+        real *out[11] = {B.x[0], B.x[1], B.x[2], B.v[0], B.v[1], B.v[2], B.w, B.rho, B.p, B.c, B.e};
 #pragma unroll
-    for (int k = 0; k < NOUT; ++k) {
-        real *hi = PASS == SPH_PASS_FORCE ? R.hi[k] : R.Lhi[k];
-        real *lo = PASS == SPH_PASS_FORCE ? R.lo[k] : R.Llo[k];
-        const real hv = (real)acc[k].s;
-        hi[i] = hv;
-        if (SPLIT) lo[i] = (real)(acc[k].s - (double)hv);
+        for (int k = 0; k < 11; ++k) out[k][i] = (real)((double)out[k][i] + acc[k].s);
+    } else {
+#pragma unroll
+        for (int k = 0; k < NOUT; ++k) {
+            real *hi = PASS == SPH_PASS_FORCE ? R.hi[k] : R.Lhi[k];
+            real *lo = PASS == SPH_PASS_FORCE ? R.lo[k] : R.Llo[k];
+            const real hv = (real)acc[k].s;
+            hi[i] = hv;
+            if (SPLIT) lo[i] = (real)(acc[k].s - (double)hv);
+        }
     }
+}
+
+// Adjoint pass: the sources' rate cotangents in the two spare records.
+template <typename real>
+__global__ __launch_bounds__(kBlock) void k_stage_rbar(uint32_t n, RV<real> rb, Stage<real> st)
+{
+    uint32_t j = blockIdx.x * kBlock + threadIdx.x;
+    if (j >= n) return;
+    typename Vec4<real>::type a, b;
+    a.x = rb.hi[0][j];
+    a.y = rb.hi[1][j];
+    a.z = rb.hi[2][j];
+    a.w = rb.hi[3][j];
+    b.x = rb.hi[4][j];
+    b.y = rb.hi[5][j];
+    b.z = 0;
+    b.w = 0;
+    st.s0[j] = a;
+    st.s1[j] = b;
 }
 
 // Candidates and hits of one pass, with the predicate of the pair kernel.
@@ -502,18 +565,22 @@ __global__ __launch_bounds__(kBlock) void k_count(Params P, Grid g, PV<real> tg,
 template <typename real, int PASS, bool SOLID>
 hipError_t go(const Params &P, const Grid &g, const sph_particles &tg, const uint32_t *tidx,
               const uint32_t *nt, const sph_particles &sr, const uint32_t *sstart, bool self, int zero_first,
-              const sph_rates &r, const Workspace &ws, hipStream_t s)
+              const sph_rates &r, const sph_adjoint &bar, const Workspace &ws, hipStream_t s)
 {
     if (tg.n == 0) return hipSuccess;
-    Stage<real> st = stage_view<real>(ws, sr.n, SOLID);
-    if (sr.n > 0) k_stage<real, SOLID><<<div_up(sr.n, kBlock), kBlock, 0, s>>>(g, view<real>(sr), st);
+    constexpr bool ADJ = PASS == kPassAdjoint;
+    Stage<real> st = stage_view<real>(ws, sr.n, SOLID || ADJ);
+    if (sr.n > 0) {
+        k_stage<real, SOLID><<<div_up(sr.n, kBlock), kBlock, 0, s>>>(g, view<real>(sr), st);
+        if constexpr (ADJ) k_stage_rbar<real><<<div_up(sr.n, kBlock), kBlock, 0, s>>>(sr.n, view<real>(r), st);
+    }
     uint32_t blocks = div_up(tg.n, kPairBlock);
     if (self)
         k_pairs<real, PASS, SOLID, true><<<blocks, kPairBlock, 0, s>>>(P, g, view<real>(tg), tidx, nt, st, sstart,
-                                                                     zero_first, view<real>(r));
+                                                                     zero_first, view<real>(r), view<real>(bar));
     else
         k_pairs<real, PASS, SOLID, false><<<blocks, kPairBlock, 0, s>>>(P, g, view<real>(tg), tidx, nt, st, sstart,
-                                                                      zero_first, view<real>(r));
+                                                                      zero_first, view<real>(r), view<real>(bar));
     return hipGetLastError();
 }
 
@@ -522,11 +589,12 @@ hipError_t go_prec(const Params &P, const Grid &g, int pass, const sph_particles
                    const uint32_t *nt, const sph_particles &sr, const uint32_t *sstart, bool self,
                    int zero_first, const sph_rates &r, const Workspace &ws, hipStream_t s)
 {
+    const sph_adjoint none{};
     if (pass == SPH_PASS_GRADIENT)
-        return go<real, SPH_PASS_GRADIENT, false>(P, g, tg, tidx, nt, sr, sstart, self, zero_first, r, ws, s);
+        return go<real, SPH_PASS_GRADIENT, false>(P, g, tg, tidx, nt, sr, sstart, self, zero_first, r, none, ws, s);
     if (P.material == SPH_SOLID_J2)
-        return go<real, SPH_PASS_FORCE, true>(P, g, tg, tidx, nt, sr, sstart, self, zero_first, r, ws, s);
-    return go<real, SPH_PASS_FORCE, false>(P, g, tg, tidx, nt, sr, sstart, self, zero_first, r, ws, s);
+        return go<real, SPH_PASS_FORCE, true>(P, g, tg, tidx, nt, sr, sstart, self, zero_first, r, none, ws, s);
+    return go<real, SPH_PASS_FORCE, false>(P, g, tg, tidx, nt, sr, sstart, self, zero_first, r, none, ws, s);
 }
 
 }  // namespace
@@ -554,6 +622,15 @@ hipError_t launch_count_pairs(const Params &P, const Grid &g, int prec, const sp
                                                             sstart, c);
     }
     return hipGetLastError();
+}
+
+hipError_t launch_interact_adjoint(const Params &P, const Grid &g, int prec, const sph_particles &p,
+                                   const uint32_t *start, const sph_rates &rbar, const sph_adjoint &bar,
+                                   const Workspace &ws, hipStream_t s)
+{
+    if (prec == SPH_FP64)
+        return go<double, kPassAdjoint, false>(P, g, p, nullptr, nullptr, p, start, true, 0, rbar, bar, ws, s);
+    return go<float, kPassAdjoint, false>(P, g, p, nullptr, nullptr, p, start, true, 0, rbar, bar, ws, s);
 }
 
 hipError_t launch_interact(const Params &P, const Grid &g, int prec, int pass, const sph_particles &tg,

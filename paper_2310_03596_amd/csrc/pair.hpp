@@ -193,6 +193,131 @@ __device__ inline void pair_force(const real d[3], real r2, const Part<real, SOL
     out[5] = real(0.5) * A * G * s1;
 }
 
+// Reverse mode of pair_force (fluid) with respect to the TARGET's inputs:
+// given cotangents wb[6] of the six terms, adds to g[11] the cotangents of
+// (x_i[3], v_i[3], omega_i, rho_i, p_i, c_i, e_i).  Every intermediate of
+// the forward evaluation is recomputed, then differentiated in reverse
+// order.  A pair with r = 0 contributes nothing.
+template <typename real>
+__device__ inline void pair_force_vjp(const real d[3], real r2, const Part<real, false> &I,
+                                      const Part<real, false> &J, const PairK<real> &K, const real wb[6],
+                                      real g[11])
+{
+    if (!(r2 > real(0))) return;
+    // forward
+    real r, rinv;
+    inv_len<real>(r2, r, rinv);
+    const real q = r * K.hinv;
+    const real tq = max(real(2) - q, real(0));
+    const bool inner = q < real(1);
+    const real f = inner ? q * (real(3) - real(2.25) * q) : real(0.75) * tq * tq;
+    const real fp = inner ? real(3) - real(4.5) * q : real(-1.5) * tq;   // df/dq
+    const real F = K.Fc * f;
+    const real G = F * rinv;
+    const real sv[3] = {I.v[0] + J.v[0], I.v[1] + J.v[1], I.v[2] + J.v[2]};
+    const real dv[3] = {J.v[0] - I.v[0], J.v[1] - I.v[1], J.v[2] - I.v[2]};
+    const real s1 = dv[0] * d[0] + dv[1] * d[1] + dv[2] * d[2];
+    const real s2 = sv[0] * d[0] + sv[1] * d[1] + sv[2] * d[2];
+    const real rb = real(0.5) * (I.rho + J.rho);
+    const real cb = real(0.5) * (I.c + J.c);
+    const real pb = real(0.5) * (I.p + J.p);
+    const real Z = rb * cb;
+    const real Zinv = rcp<real>(Z);
+    const real du = K.half_beta * (I.p - J.p) * Zinv;
+    const real ps = pb - (K.half_beta * Z * s1) * rinv;
+    const real A = real(2) * I.w * J.w;
+    const real Phi = rb * du * F;
+    const real k1 = -A * ((Phi * du) * rinv + ps * G);
+    const real ca = real(-0.5) * A * Phi;
+    const real sv2 = sv[0] * sv[0] + sv[1] * sv[1] + sv[2] * sv[2];
+    const real vs2 = real(0.25) * sv2 + du * (s2 * rinv + du);
+    const real Es = real(0.5) * (I.e + J.e) + real(0.5) * vs2;
+    const real vsd = real(0.5) * s2 + du * r;
+    const real tv = ps * G * vsd;
+    // reverse
+    real bA = 0, bG = 0, bs1 = 0, bs2 = 0, bPhi = 0, bdu = 0, bps = 0, br = 0, brinv = 0, bF = 0;
+    real bsv[3] = {0, 0, 0}, bd[3] = {0, 0, 0};
+    // o5 = A G s1 / 2
+    bA += real(0.5) * wb[5] * G * s1;
+    bG += real(0.5) * wb[5] * A * s1;
+    bs1 += real(0.5) * wb[5] * A * G;
+    // o4 = -A (Phi Es + tv)
+    bA -= wb[4] * (Phi * Es + tv);
+    bPhi -= wb[4] * A * Es;
+    const real bEs = -wb[4] * A * Phi;
+    const real btv = -wb[4] * A;
+    // tv = ps G vsd
+    bps += btv * G * vsd;
+    bG += btv * ps * vsd;
+    const real bvsd = btv * ps * G;
+    // vsd = s2 / 2 + du r
+    bs2 += real(0.5) * bvsd;
+    bdu += bvsd * r;
+    br += bvsd * du;
+    // Es = (e_i + e_j) / 2 + vs2 / 2
+    g[10] += real(0.5) * bEs;
+    const real bvs2 = real(0.5) * bEs;
+    // vs2 = sv2 / 4 + du (s2 rinv + du)
+    const real bsv2 = real(0.25) * bvs2;
+    bdu += bvs2 * (s2 * rinv + real(2) * du);
+    bs2 += bvs2 * du * rinv;
+    brinv += bvs2 * du * s2;
+    // o_{1+a} = ca sv_a + k1 d_a
+    real bca = 0, bk1 = 0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        bca += wb[1 + a] * sv[a];
+        bsv[a] += wb[1 + a] * ca + real(2) * bsv2 * sv[a];
+        bk1 += wb[1 + a] * d[a];
+        bd[a] += wb[1 + a] * k1;
+    }
+    // k1 = -A (Phi du rinv + ps G)
+    bA -= bk1 * ((Phi * du) * rinv + ps * G);
+    bPhi -= bk1 * A * du * rinv;
+    bdu -= bk1 * A * Phi * rinv;
+    brinv -= bk1 * A * Phi * du;
+    bps -= bk1 * A * G;
+    bG -= bk1 * A * ps;
+    // ca = -A Phi / 2 ; o0 = -A Phi
+    bA -= (real(0.5) * bca + wb[0]) * Phi;
+    bPhi -= (real(0.5) * bca + wb[0]) * A;
+    // Phi = rb du F
+    real brb = bPhi * du * F;
+    bdu += bPhi * rb * F;
+    bF += bPhi * rb * du;
+    // A = 2 w_i w_j
+    g[6] += real(2) * bA * J.w;
+    // ps = pb - hb Z s1 rinv
+    const real bpb = bps;
+    real bZ = -bps * K.half_beta * s1 * rinv;
+    bs1 -= bps * K.half_beta * Z * rinv;
+    brinv -= bps * K.half_beta * Z * s1;
+    // du = hb (p_i - p_j) / Z
+    g[8] += bdu * K.half_beta * Zinv;
+    bZ -= bdu * du * Zinv;
+    // Z = rb cb ; rb, cb, pb are means
+    brb += bZ * cb;
+    const real bcb = bZ * rb;
+    g[7] += real(0.5) * brb;
+    g[9] += real(0.5) * bcb;
+    g[8] += real(0.5) * bpb;
+    // s1 = dv . d, s2 = sv . d ; sv = v_i + v_j, dv = v_j - v_i
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        bd[a] += bs1 * dv[a] + bs2 * sv[a];
+        bsv[a] += bs2 * d[a];
+        g[3 + a] += bsv[a] - bs1 * d[a];
+    }
+    // G = F rinv ; F = Fc f(q), q = r hinv
+    bF += bG * rinv;
+    brinv += bG * F;
+    br += bF * K.Fc * fp * K.hinv;
+    // r = sqrt(r2), rinv = r2^-1/2 ; r2 = d . d ; d = x_j - x_i
+    const real br2 = real(0.5) * rinv * (br - brinv * rinv * rinv);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) g[a] -= bd[a] + real(2) * br2 * d[a];
+}
+
 // GRADIENT terms: L_ab = w_j (v_j - v_i)_a g_b.
 template <typename real>
 __device__ inline void pair_grad(const real d[3], real r2, const real vi[3], const real vj[3], real wj,

@@ -169,7 +169,7 @@ def test_integrate_and_adjoint_reject_bad_arguments():
     ps = _params()
     ps.material, ps.K, ps.G = L.SPH_SOLID_J2, 1e9, 1e9
     assert lib.sph_interact_adjoint(C.byref(ps), C.byref(_grid()), C.byref(p), L.SphCells(FAKE, 64, 0),
-                                    C.byref(r), C.byref(bar), None) == L.SPH_ERR_UNSUPPORTED
+                                    C.byref(r), C.byref(bar), FAKE, 1 << 30, None) == L.SPH_ERR_UNSUPPORTED
 
 
 def test_zero_particles_is_a_noop():
