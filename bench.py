@@ -45,6 +45,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the CPU oracle sample")
     ap.add_argument("--only", choices=["fp32", "fp64", "both"], default="both")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward ratio leg")
+    ap.add_argument("--no-share", action="store_true", help="skip the 8M + 2M share pass-set leg")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="also run one plain device copy of this many MiB (scale for HBM counters)")
     return ap.parse_args()
@@ -78,6 +80,73 @@ def time_form(wl, prec, steps, warmup):
         "pair_evals_per_s": pairs / (force_ms * 1e-3),
         "diag": sim.diagnostics().tolist(),
     }
+
+
+def adjoint_leg(prec, reps=2):
+    """Adjoint/forward time ratio on the 250,047-particle box: 50 fixed-dt
+    steps with checkpoints every 10 (forward), then the reverse pass
+    (recompute of every segment + reverse kernels).  Best of `reps`."""
+    import torch
+
+    import sph_synth as S
+    from paper_2310_03596_amd.adjoint import KineticEnergyRollout
+
+    wl = S.c5_box()
+    best = None
+    for _ in range(reps + 1):      # the first round warms up
+        ro = KineticEnergyRollout(wl, prec, wl.extra["steps"], wl.extra["ckpt"], wl.extra["dt"])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ro.forward(wl.v, wl.params["c0"])
+        t1 = time.perf_counter()
+        ro.backward(1.0)
+        t2 = time.perf_counter()
+        cur = (t1 - t0, t2 - t1)
+        best = cur if best is None or sum(cur) < sum(best) else best
+    fwd, bwd = best
+    return {"n_particles": wl.n, "steps": wl.extra["steps"], "checkpoint_every": wl.extra["ckpt"],
+            "forward_s": fwd, "backward_s": bwd, "adjoint_over_forward": bwd / fwd,
+            "form": "FP32 split" if prec == 1 else "FP64"}
+
+
+def share_leg(reps=5):
+    """One GPU's share of a 16-GPU decomposition (8M local + 2M remote), FP32:
+    hash/sort/tables of both arrays, communication hash + compaction, payload
+    packing, local-local and local-remote FORCE passes, timed per pass set."""
+    import torch
+
+    import sph_synth as S
+    from paper_2310_03596_amd.sim import SharePass
+
+    out = {}
+    for layout in ("slab", "mixed"):
+        loc, rem = S.c4_share(layout)
+        sp = SharePass(loc, rem, 1)
+        sp.run()
+        torch.cuda.synchronize()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+        t_ll = t_lr = 0.0
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            sp.build()
+            sp.mark()
+            sp.pack()
+            ev[0].record()
+            sp.interact_local()
+            ev[1].record()
+            sp.interact_remote()
+            ev[2].record()
+            torch.cuda.synchronize()
+            t_ll += ev[0].elapsed_time(ev[1])
+            t_lr += ev[1].elapsed_time(ev[2])
+        wall = (time.perf_counter() - t0) / reps
+        nb = int(sp.nb.cpu()[0])
+        out[layout] = {"local": loc.n, "remote": rem.n, "boundary": nb, "pass_set_ms": 1e3 * wall,
+                       "local_particle_updates_per_s": loc.n / wall, "local_local_ms": t_ll / reps,
+                       "local_remote_ms": t_lr / reps}
+        del sp
+        torch.cuda.empty_cache()
+    return out
 
 
 def cpu_leg(wl, budget_s):
@@ -178,6 +247,11 @@ def main():
                             "force_tflops": res[0]["force_tflops"],
                             "frac_of_fp64_peak": res[0]["force_tflops"] / PEAK_TFLOPS[0]}
         out["fp32_over_fp64"] = res[1]["value"] / res[0]["value"]
+    if not args.no_adjoint:
+        out["adjoint"] = {"fp32_split": adjoint_leg(1), "fp64": adjoint_leg(0)}
+        out["adjoint_forward_ratio"] = out["adjoint"]["fp32_split"]["adjoint_over_forward"]
+    if not args.no_share:
+        out["share_pass"] = share_leg()
     if args.calib_copy_mb > 0:
         nbytes = args.calib_copy_mb << 20
         src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")

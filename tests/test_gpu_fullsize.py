@@ -1,0 +1,133 @@
+"""GPU parity at the workloads' full sizes, in the launch configuration the
+benchmark uses.  Integer outputs are compared whole (the oracle computes them
+quickly); pair sums on a seeded sample of targets that the oracle evaluates
+one by one from the same device state (tolerances as in test_gpu_parity)."""
+import numpy as np
+import pytest
+import torch
+
+import sph_synth as S
+from oracle import cpu
+from tests.gpu_helpers import assert_within, oracle_state, rate_bound
+
+pytestmark = [pytest.mark.gpu, pytest.mark.timeout(900)]
+
+FP64, FP32 = 0, 1
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _sample(n, k, seed):
+    rng = np.random.default_rng(seed)
+    return np.sort(rng.choice(n, size=min(k, n), replace=False)).astype(np.uint32)
+
+
+@pytest.mark.parametrize("prec", [FP32, FP64])
+def test_column_full_size(prec):
+    from paper_2310_03596_amd.sim import Sim
+    wl = S.c2_column()
+    print(f"[column full] n={wl.n} prec={prec}", flush=True)
+    sim = Sim(wl, prec)
+    sim.build()
+    sim.interact()
+    torch.cuda.synchronize()
+    h = sim.A.host()
+    s = cpu.State.from_workload(wl)
+    o, operm, ostart = cpu.build_cells(wl.grid, s)
+    assert np.array_equal(sim.perm.cpu().numpy().view(np.uint32), operm)
+    assert np.array_equal(sim.start.cpu().numpy().view(np.uint32), ostart)
+    assert np.array_equal(h["hash"], o.hash)
+    st = oracle_state(h, False)
+    tidx = _sample(wl.n, 4096, 90)
+    ref = cpu.interact(wl.params, wl.grid, cpu.FORCE, st, st, ostart, True, tidx=tidx)[tidx]
+    bound = rate_bound(wl.params, wl.grid, cpu.FORCE, st, st, ostart, True, prec, tidx=tidx)[tidx]
+    got = sim.rates.force().T.cpu().numpy()[tidx]
+    assert_within(got, ref, bound, "column rates (sample)")
+
+
+def test_cylinder_full_size_solid_loops():
+    """4M-particle cylinder, FP32 split: GRADIENT pass, stress stage and FORCE
+    pass of one solid step, each checked on a sample from the device's inputs."""
+    from paper_2310_03596_amd import _lib as L
+    from paper_2310_03596_amd.sim import Sim
+    from paper_2310_03596_amd.state import stream_handle
+    wl = S.c3_cylinder()
+    print(f"[cylinder full] n={wl.n}", flush=True)
+    sim = Sim(wl, FP32)
+    sim.build()
+    sim.interact(pass_=L.SPH_PASS_GRADIENT)
+    torch.cuda.synchronize()
+    st = oracle_state(sim.A.host(), True)
+    start = cpu.cell_start(st.hash, cpu.ncells(wl.grid))
+    tidx = _sample(wl.n, 2048, 91)
+    refL = cpu.interact(wl.params, wl.grid, cpu.GRADIENT, st, st, start, True, tidx=tidx)[tidx]
+    bL = rate_bound(wl.params, wl.grid, cpu.GRADIENT, st, st, start, True, FP32, tidx=tidx)[tidx]
+    Lgpu = sim.rates.grad().T.cpu().numpy()
+    assert_within(Lgpu[tidx], refL, bL, "cylinder velocity gradient (sample)")
+    # stress stage from the device's L
+    dt = 5e-9
+    dtt = torch.full((1,), dt, dtype=torch.float64, device="cuda")
+    S0 = sim.A.host()["S"].copy()
+    L.sph_integrate(sim.params, L.SPH_STAGE_STRESS, sim.A.struct(), sim.rates.struct(), dtt.data_ptr(), None,
+                    None, 0, stream_handle())
+    torch.cuda.synchronize()
+    h1 = sim.A.host()
+    o = cpu.State(len(tidx), True)
+    o.m[:] = 1.0
+    o.w[:] = 1.0
+    o.S[:] = S0[tidx].astype(np.float32).astype(np.float64)
+    cpu.integrate(wl.params, cpu.STRESS, o, L=Lgpu[tidx], dt=dt)
+    scale = np.abs(o.S).max() + wl.params["G"] * 1e-6
+    assert np.abs(h1["S"][tidx] - o.S).max() <= 2e-6 * scale
+    # FORCE pass with the updated stress
+    sim.interact()
+    torch.cuda.synchronize()
+    st2 = oracle_state(sim.A.host(), True)
+    ref = cpu.interact(wl.params, wl.grid, cpu.FORCE, st2, st2, start, True, tidx=tidx)[tidx]
+    b = rate_bound(wl.params, wl.grid, cpu.FORCE, st2, st2, start, True, FP32, tidx=tidx)[tidx]
+    assert_within(sim.rates.force().T.cpu().numpy()[tidx], ref, b, "cylinder FORCE (sample)")
+
+
+@pytest.mark.parametrize("layout", ["slab", "mixed"])
+def test_share_full_size(layout):
+    from paper_2310_03596_amd.sim import SharePass
+    loc, rem = S.c4_share(layout)
+    print(f"[share full] layout={layout} local={loc.n} remote={rem.n}", flush=True)
+    sp = SharePass(loc, rem, FP32)
+    sp.run()
+    torch.cuda.synchronize()
+    nb = int(sp.nb.cpu()[0])
+    hl, hr = sp.LB.host(), sp.RB.host()
+    nc = cpu.ncells(loc.grid)
+    lstart = cpu.cell_start(hl["hash"], nc)
+    rstart = cpu.cell_start(hr["hash"], nc)
+    assert np.array_equal(sp.lstart.cpu().numpy().view(np.uint32), lstart)
+    assert np.array_equal(sp.rstart.cpu().numpy().view(np.uint32), rstart)
+    # the local sort itself, bit for bit
+    s = cpu.State.from_workload(loc)
+    h = cpu.hash_cells(loc.grid, s.x)
+    assert np.array_equal(sp.lperm.cpu().numpy().view(np.uint32), cpu.sort_perm(h, nc))
+    comm, bidx = cpu.mark_boundary(loc.grid, hl["hash"], rstart)
+    if layout == "slab":
+        assert nb == 80000
+    assert nb == bidx.size
+    assert np.array_equal(sp.comm.cpu().numpy().view(np.uint32), comm)
+    assert np.array_equal(sp.bidx.cpu().numpy().view(np.uint32)[:nb], bidx)
+    hp = sp.payload.host()
+    ks = _sample(nb, 4096, 92)
+    for f in ("x", "v", "rho", "p", "id"):
+        assert np.array_equal(hp[f][ks], hl[f][bidx[ks]]), f
+    # rates on a sample of boundary and interior targets
+    sl, sr = oracle_state(hl, False), oracle_state(hr, False)
+    tidx = np.unique(np.concatenate([bidx[_sample(nb, 1024, 93)], _sample(loc.n, 1024, 94)])).astype(np.uint32)
+    inB = np.isin(tidx, bidx)
+    ref = cpu.interact(loc.params, loc.grid, cpu.FORCE, sl, sl, lstart, True, tidx=tidx)
+    ref = cpu.interact(loc.params, loc.grid, cpu.FORCE, sl, sr, rstart, False, rates=ref, tidx=tidx[inB])
+    bound = rate_bound(loc.params, loc.grid, cpu.FORCE, sl, sl, lstart, True, FP32, tidx=tidx)
+    bound += rate_bound(loc.params, loc.grid, cpu.FORCE, sl, sr, rstart, False, FP32, tidx=tidx[inB])
+    got = sp.rates.force().T.cpu().numpy()
+    assert_within(got[tidx], ref[tidx], bound[tidx], f"share {layout} rates (sample)")
