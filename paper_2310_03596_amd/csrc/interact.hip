@@ -10,19 +10,21 @@
 //     (cy, cz); consecutive sorted targets almost always do;
 //   * for each of the 9 neighbour rows the group's candidates form one
 //     contiguous source range (the union of the lanes' 3-bucket ranges); the
-//     wavefront streams it through LDS in coalesced 64-record chunks and every
-//     lane tests every staged record against its own target (LDS broadcast
-//     reads, no divergence, no per-lane gathers whose latency would serialise
-//     the test);
+//     wavefront stages it in LDS with coalesced loads (in pages when it is
+//     long), and then each lane walks its OWN 3-bucket range inside the page
+//     (a per-lane LDS offset), all lanes in step, so a lane tests about its
+//     27 buckets' worth of candidates instead of the whole union (about half
+//     as many on the column workload);
 //   * hits go to a per-lane list in LDS; when any lane's list is nearly full
 //     (and at the end of the group) every lane evaluates the pair terms of its
 //     listed hits.  Only ~1 candidate in 6 is a neighbour, so separating the
 //     cheap test from the ~140-flop pair body keeps the body dense.
 // A candidate outside a lane's own 3-bucket range is farther than one bucket
-// side >= 2h on some axis and fails the distance test, so testing the union
-// changes no neighbour set.  Hits are listed, and summed, in ascending source
-// index.  A pair with r = 0 (the target itself, or a coincident particle)
-// adds nothing: its terms all carry F(0) = 0.
+// side >= 2h on some axis and fails the distance test, so the lanes that run
+// past the end of their range while the longest one finishes change no
+// neighbour set.  Hits are listed, and summed, in ascending source index.  A
+// pair with r = 0 (the target itself, or a coincident particle) adds
+// nothing: its terms all carry F(0) = 0.
 //
 // In the FP32-split form the position difference is rebuilt from bucket
 // indices and float offsets, d = (c_j - c_i) L + (off_j - off_i), which is
@@ -38,15 +40,25 @@ namespace {
 
 constexpr int kPairBlock = 256;            // targets per workgroup
 constexpr int kWaves = kPairBlock / kWave;
-constexpr int kChunk = 64;                 // source records staged per wavefront load
 #ifndef SPH_PAIR_SUB
 #define SPH_PAIR_SUB 4   // measured best of 4, 8, 16 on the 810k column (fewer live VGPRs)
 #endif
 constexpr int kSub = SPH_PAIR_SUB;         // candidates tested between list-fill checks
-constexpr int kHitCap = 48;                // listed hits per lane (u16 entries)
-constexpr int kWinBits = 12;               // hit entry: window slot (4 bits) | offset (12 bits)
+constexpr int kHitCap = 40;                // listed hits per lane (u16 entries)
+constexpr int kWinBits = 12;               // hit entry: page slot (4 bits) | index in page (12 bits)
 constexpr uint32_t kWinLen = 1u << kWinBits;
 constexpr int kMaxWin = 16;
+// Source records staged per page (one neighbour row of a group, split into
+// pages when longer).  Sized so that a workgroup's LDS (hit lists + pages +
+// page tables) stays within 32 KB for FP32 (five workgroups per CU) and
+// within 40 KB for FP64 (four); the page covers the row union of a group in
+// about 97 % (FP32) and 75 % (FP64) of the cases on the column workload.
+template <typename real>
+struct Page {
+    static constexpr int len = sizeof(real) == 4 ? 160 : 96;
+};
+static_assert(Page<float>::len <= (int)kWinLen && Page<double>::len <= (int)kWinLen, "page index must fit an entry");
+static_assert(Page<float>::len % kSub == 0 && Page<double>::len % kSub == 0, "reads stay below len + kSub");
 constexpr int kPassAdjoint = 2;            // reverse mode of the FORCE pass (fluid)
 #ifndef SPH_PAIR_WAVES_PER_EU
 #define SPH_PAIR_WAVES_PER_EU 5
@@ -94,14 +106,14 @@ __device__ inline int wave_min(int v)
 {
 #pragma unroll
     for (int off = kWave / 2; off > 0; off >>= 1) v = min(v, __shfl_xor(v, off, kWave));
-    return v;
+    return __builtin_amdgcn_readfirstlane(v);   // equal in every lane
 }
 
 __device__ inline int wave_max(int v)
 {
 #pragma unroll
     for (int off = kWave / 2; off > 0; off >>= 1) v = max(v, __shfl_xor(v, off, kWave));
-    return v;
+    return __builtin_amdgcn_readfirstlane(v);   // equal in every lane
 }
 
 // Packs the pair inputs of every source particle (see Stage).
@@ -193,10 +205,11 @@ void k_pairs(Params P, Grid g, PV<real> tg, const uint32_t *__restrict__ tidx, c
     constexpr bool SPLIT = sizeof(real) == 4;
     constexpr bool ADJ = PASS == kPassAdjoint;
     constexpr int NOUT = PASS == SPH_PASS_FORCE ? 6 : (ADJ ? 11 : 9);
+    constexpr int kPage = Page<real>::len;
     __shared__ uint16_t hits[kHitCap][kPairBlock];
-    __shared__ v4 stage[kWaves][kChunk];
-    __shared__ uint32_t wbase[kWaves][kMaxWin];   // first source index of each window
-    __shared__ real wdy[kWaves][kMaxWin];         // (c_j - c_i) L in y and z of the window's row
+    __shared__ v4 stage[kWaves][kPage + kSub];    // a page, then far sentinels
+    __shared__ uint32_t wbase[kWaves][kMaxWin];   // first source index of each staged page
+    __shared__ real wdy[kWaves][kMaxWin];         // (c_j - c_i) L in y and z of the page's row
     __shared__ real wdz[kWaves][kMaxWin];
 
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
@@ -265,7 +278,7 @@ void k_pairs(Params P, Grid g, PV<real> tg, const uint32_t *__restrict__ tidx, c
         acc[k].s = s0;
     }
 
-    int cnt = 0;
+    int cnt = 0;   // entries in the lane's list
     // Records of one listed hit; the next hit's are loaded while the current
     // pair is evaluated (software pipelining hides the L2 latency).
     struct Rec {
@@ -288,17 +301,17 @@ void k_pairs(Params P, Grid g, PV<real> tg, const uint32_t *__restrict__ tidx, c
         }
         return q;
     };
-    // evaluate the pair terms of every listed hit, then empty the lists
-    auto flush = [&]() {
-        Rec cur;
-        if (cnt > 0) cur = fetch(0);
-        for (int s = 0; s < cnt; ++s) {
-            const Rec nxt = fetch(s + 1 < cnt ? s + 1 : s);
+    // the pair terms of one listed hit, added to the lane's sums
+    auto eval = [&](const Rec &cur) {
             real d[3];
             diff<real>(T, cur.p, cur.qy, cur.qz, d);
             const real r2 = r2_of<real>(d);
             const v4 a = cur.a;
-            if constexpr (PASS == SPH_PASS_FORCE) {
+            // the neighbour predicate, on the exact and odd d (so a pair is in or
+            // out for both of its particles); the filter's shortlist is wider
+            if (!(r2 < R2)) {
+                // outside the support: nothing to add
+            } else if constexpr (PASS == SPH_PASS_FORCE) {
                 const v4 b = cur.b;
                 Part<real, SOLID> J;
                 J.v[0] = a.x;
@@ -356,7 +369,22 @@ void k_pairs(Params P, Grid g, PV<real> tg, const uint32_t *__restrict__ tidx, c
 #pragma unroll
                 for (int k = 0; k < 9; ++k) acc[k].add(o[k]);
             }
-            cur = nxt;
+    };
+    // evaluate the pair terms of every listed hit, two at a time: the records
+    // of the next two are loaded while the current two are evaluated, into
+    // alternating buffers (no register copies); indices past the list end are
+    // clamped to its last entry, so every load reads a listed record
+    auto flush = [&]() {
+        if (cnt > 0) {
+            const int last = cnt - 1;
+            Rec A = fetch(0);
+            Rec B = fetch(last < 1 ? last : 1);
+            for (int s = 0; s < cnt; s += 2) {
+                eval(A);
+                A = fetch(s + 2 < last ? s + 2 : last);
+                if (s + 1 < cnt) eval(B);
+                B = fetch(s + 3 < last ? s + 3 : last);
+            }
         }
         cnt = 0;
     };
@@ -367,19 +395,22 @@ void k_pairs(Params P, Grid g, PV<real> tg, const uint32_t *__restrict__ tidx, c
     while (pending) {
         // the next group: lanes whose target shares the first pending lane's bucket row
         const int leader = __ffsll((unsigned long long)pending) - 1;
-        const uint32_t key = __shfl(rowkey, leader, kWave);
+        const uint32_t key = __builtin_amdgcn_readfirstlane(__shfl(rowkey, leader, kWave));
         const bool in = valid && rowkey == key;
         pending &= ~__ballot(in);
         const int gx0 = wave_min(in ? x0 : 0x7FFFFFFF);
         const int gx1 = wave_max(in ? x1 : -1);
         const int gy = (int)(key % (uint32_t)g.ny), gz = (int)(key / (uint32_t)g.ny);
-        const real R2in = in ? R2 : real(-1);
-        // Filter frame.  FP32 split: positions relative to the corner of bucket
-        // column gx0 of the target's row, ((c - gx0) L + off) in x and
-        // (dy L + off) in y, z, so a test is three subtractions.  The filter
-        // only shortlists: every listed pair is re-evaluated from the exact,
-        // odd d and has F = 0 beyond 2h.  FP64: absolute positions (the test is
-        // then exactly the neighbour predicate).
+        // Filter frame.  Split form: positions relative to the corner of bucket
+        // (gx0, gy, gz), ((c - gx0) L + off) in x and (dy L + off) in y, z;
+        // FP64: absolute positions.  The test is the expanded form
+        // |q|^2 - 2 q.f < R2 - |f|^2, with (2q, |q|^2) staged for each record,
+        // so a candidate costs three FMAs and a compare.  For a candidate within 2h
+        // of the target (|q| <= |f| + 2h) its rounding, with that of the
+        // frame, stays below 2^-18 (|f| + 2h)^2 in FP32 and 2^-46 (...)^2 in
+        // FP64; the bound is widened by four times that, so the shortlist
+        // keeps every neighbour.  The pair body applies the neighbour
+        // predicate itself, on the exact, odd d.
         real fo[3];
         const real gx0f = (real)gx0;
         if constexpr (SPLIT) {
@@ -391,6 +422,10 @@ void k_pairs(Params P, Grid g, PV<real> tg, const uint32_t *__restrict__ tidx, c
             fo[1] = T.x[1];
             fo[2] = T.x[2];
         }
+        const real f2 = fo[0] * fo[0] + fo[1] * fo[1] + fo[2] * fo[2];
+        const real fl = sqrt(f2) + (real)(2.0 * P.h);
+        const real margin = (SPLIT ? real(0x1p-16) : real(0x1p-44)) * fl * fl;
+        const real Tl = in ? (R2 - f2) + margin : -kFar;
         int nwin = 0;
         for (int r = 0; r < 9; ++r) {
             const int dz = r / 3 - 1, dy = r % 3 - 1;
@@ -398,51 +433,77 @@ void k_pairs(Params P, Grid g, PV<real> tg, const uint32_t *__restrict__ tidx, c
             if (z < 0 || z >= g.nz || y < 0 || y >= g.ny) continue;
             const uint32_t row = (uint32_t)g.nx * ((uint32_t)y + (uint32_t)g.ny * (uint32_t)z);
             const uint32_t ub = sstart[row + gx0], ue = sstart[row + gx1 + 1];
+            if (ub >= ue) continue;
+            // the lane's own 3-bucket range of this row (a sub-range of [ub, ue))
+            const uint32_t lo = in ? sstart[row + x0] : ub;
+            const uint32_t hi = in ? sstart[row + x1 + 1] : ub;
             const real ddy = (real)dy * T.Lf, ddz = (real)dz * T.Lf;
-            for (uint32_t wb = ub; wb < ue; wb += kWinLen) {
+            for (uint32_t pb = ub; pb < ue; pb += (uint32_t)kPage) {
+                const uint32_t len = ue - pb < (uint32_t)kPage ? ue - pb : (uint32_t)kPage;
                 if (nwin == kMaxWin) {
                     flush();
                     nwin = 0;
                 }
                 const int slot = nwin++;
                 if (lane == 0) {
-                    wbase[wave][slot] = wb;
+                    wbase[wave][slot] = pb;
                     wdy[wave][slot] = ddy;
                     wdz[wave][slot] = ddz;
                 }
-                const uint32_t we = (ue - wb > kWinLen) ? wb + kWinLen : ue;
-                for (uint32_t c = wb; c < we; c += kChunk) {
-                    const uint32_t k = c + lane;
-                    wave_lds_sync();   // earlier reads of the stage are done
-                    // records past the window are a far-away sentinel that fails every test
+                wave_lds_sync();   // earlier reads of the stage are done
+                // the page in the group's filter frame, then far sentinels up to
+                // kPage + kSub so that every read below stays in the array and
+                // nothing past the page can pass a test
+                for (uint32_t u = (uint32_t)lane; u < (uint32_t)(kPage + kSub); u += kWave) {
                     v4 rec;
-                    if (k < we) {
-                        rec = src.pos[k];
+                    if (u < len) {
+                        rec = src.pos[pb + u];
                         if constexpr (SPLIT) {
                             rec.x = (rec.w - gx0f) * T.Lf + rec.x;
                             rec.y = ddy + rec.y;
                             rec.z = ddz + rec.z;
                         }
+                        rec.w = rec.x * rec.x + rec.y * rec.y + rec.z * rec.z;
+                        rec.x *= real(2);   // staged as (2q, |q|^2)
+                        rec.y *= real(2);
+                        rec.z *= real(2);
                     } else {
-                        rec.x = rec.y = rec.z = kFar;
-                        rec.w = real(0);
+                        rec.x = rec.y = rec.z = real(0);
+                        rec.w = kFar;
                     }
-                    stage[wave][lane] = rec;
-                    wave_lds_sync();
-                    const int nsub = (int)((((we - c) < (uint32_t)kChunk ? (we - c) : (uint32_t)kChunk) + kSub - 1) / kSub);
-                    const uint32_t base0 = ((uint32_t)slot << kWinBits) + (c - wb);
-                    for (int sb = 0; sb < nsub; ++sb) {
-                        // at most kSub more entries per lane before the next check
-                        if (__ballot(cnt > kHitCap - kSub)) flush();
-                        const uint32_t base = base0 + (uint32_t)(sb * kSub);
+                    stage[wave][u] = rec;
+                }
+                wave_lds_sync();
+                // Each lane walks its own range clipped to the page.  Lanes whose
+                // range is shorter than the longest keep reading past its end:
+                // those records lie in farther buckets of the same row (or are
+                // sentinels) and are more than one bucket side away, so no lane
+                // needs a bound check per candidate.
+                const uint32_t pe = pb + len;
+                const uint32_t la = lo > pb ? lo - pb : 0u;
+                const uint32_t hc = hi < pe ? hi : pe;
+                const uint32_t le = hc > pb ? hc - pb : 0u;
+                const int nl = le > la ? (int)(le - la) : 0;
+                const int nmax = wave_max(nl);
+                // every lane reads `span` records from a; moving a lane's start
+                // back (to records before its own range: nearer buckets of the
+                // row, also more than one bucket side away) keeps the reads
+                // inside the array
+                const int span = (nmax + kSub - 1) / kSub * kSub;
+                const int a = (int)la < kPage + kSub - span ? (int)la : kPage + kSub - span;
+                const uint32_t ebase = ((uint32_t)slot << kWinBits) + (uint32_t)a;
+                for (int k0 = 0; k0 < nmax; k0 += kSub) {
+                    // at most kSub more entries per lane before the next check
+                    if (__ballot(cnt > kHitCap - kSub)) flush();
+                    const int base = a + k0;
+                    const uint32_t eb = ebase + (uint32_t)k0;
 #pragma unroll
-                        for (int m = 0; m < kSub; ++m) {
-                            const v4 q = stage[wave][sb * kSub + m];
-                            const real d[3] = {q.x - fo[0], q.y - fo[1], q.z - fo[2]};
-                            // the entry is written always and kept only when it is a hit
-                            hits[cnt][tid] = (uint16_t)(base + (uint32_t)m);
-                            cnt += (r2_of<real>(d) < R2in) ? 1 : 0;
-                        }
+                    for (int m = 0; m < kSub; ++m) {
+                        const v4 q = stage[wave][base + m];
+                        const real t = fma(-q.z, fo[2], fma(-q.y, fo[1], fma(-q.x, fo[0], q.w)));
+                        // the entry is written always and kept only when it is a hit
+                        hits[cnt][tid] = (uint16_t)(eb + (uint32_t)m);
+                        cnt += (t < Tl) ? 1 : 0;
                     }
                 }
             }

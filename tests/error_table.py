@@ -11,6 +11,7 @@ of the first step is taken in a child process before the GPU is touched.
 from __future__ import annotations
 
 import argparse
+import copy
 import json
 import os
 import subprocess
@@ -81,9 +82,14 @@ def main():
 
     from paper_2310_03596_amd.sim import Sim
 
+    # control: the FP64 form from positions moved by about one FP32 rounding of
+    # a bucket offset (|delta| <= 5e-10 m), to separate the flow's own
+    # sensitivity from the FP32 form's arithmetic
+    wlp = copy.copy(wl)
+    wlp.x = wl.x + np.random.default_rng(6).uniform(-5e-10, 5e-10, size=wl.x.shape)
     table = {}
-    for name, prec in (("fp32_split", 1), ("fp64", 0)):
-        sim = Sim(wl, prec)
+    for name, prec, w in (("fp32_split", 1, wl), ("fp64", 0, wl), ("fp64_x_perturbed_5e-10", 0, wlp)):
+        sim = Sim(w, prec)
         done = 0
         table[name] = {}
         for target in snaps:
