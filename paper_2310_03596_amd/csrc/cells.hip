@@ -2,12 +2,14 @@
 // step a of Section II), communication hash and boundary compaction (step c)
 // and the boundary payload packing for step d.
 //
-// The sort is a least-significant-digit radix sort with 8-bit digits over a
-// (hash, index) pair.  Each pass: (1) per-tile digit histograms in LDS,
-// (2) one workgroup per digit scans that digit's counts over tiles,
-// (3) each tile ranks its keys stably with wavefront ballots (8 ballots give
-// every lane the mask of lanes holding the same digit; popcount of the lanes
-// below gives the rank inside the wavefront) and scatters.
+// The sort is a least-significant-digit radix sort over a (hash, index)
+// pair, with digits of 8 to 10 bits chosen so that the key takes as few
+// passes as possible (two for keys of up to 20 bits).  Each pass: (1)
+// per-tile digit histograms in LDS, (2) one workgroup per digit scans that
+// digit's counts over tiles, (3) each tile ranks its keys stably with
+// wavefront ballots (one ballot per digit bit gives every lane the mask of
+// lanes holding the same digit; popcount of the lanes below gives the rank
+// inside the wavefront) and scatters.
 #include "common.hpp"
 
 namespace sph {
@@ -67,20 +69,22 @@ __device__ inline uint32_t block_excl_scan(uint32_t v, uint32_t &total)
     return before + inc - v;
 }
 
+template <int D>
 __global__ __launch_bounds__(kBlock) void k_upsweep(const uint32_t *__restrict__ keys, uint32_t n, int shift,
                                                     uint32_t *__restrict__ hist, uint32_t tiles)
 {
-    __shared__ uint32_t h[kRadixBins];
-    h[threadIdx.x] = 0;
+    constexpr int BINS = 1 << D;
+    __shared__ uint32_t h[BINS];
+    for (int b = threadIdx.x; b < BINS; b += kBlock) h[b] = 0;
     __syncthreads();
     uint32_t base = blockIdx.x * kSortTile;
 #pragma unroll
     for (int it = 0; it < kSortItems; ++it) {
         uint32_t e = base + it * kBlock + threadIdx.x;
-        if (e < n) atomicAdd(&h[(keys[e] >> shift) & (kRadixBins - 1)], 1u);
+        if (e < n) atomicAdd(&h[(keys[e] >> shift) & (BINS - 1)], 1u);
     }
     __syncthreads();
-    hist[(size_t)threadIdx.x * tiles + blockIdx.x] = h[threadIdx.x];
+    for (int b = threadIdx.x; b < BINS; b += kBlock) hist[(size_t)b * tiles + blockIdx.x] = h[b];
 }
 
 // One workgroup per digit: exclusive scan of that digit's tile counts.
@@ -100,6 +104,7 @@ __global__ __launch_bounds__(kBlock) void k_scan_digit(uint32_t *__restrict__ hi
     if (threadIdx.x == 0) totals[blockIdx.x] = run;
 }
 
+template <int D>
 __global__ __launch_bounds__(kBlock) void k_downsweep(const uint32_t *__restrict__ kin,
                                                       const uint32_t *__restrict__ vin,
                                                       uint32_t *__restrict__ kout,
@@ -107,17 +112,33 @@ __global__ __launch_bounds__(kBlock) void k_downsweep(const uint32_t *__restrict
                                                       const uint32_t *__restrict__ hist, uint32_t tiles,
                                                       const uint32_t *__restrict__ totals)
 {
+    constexpr int BINS = 1 << D;
+    constexpr int PT = BINS / kBlock;   // digits per thread in the bookkeeping
+    static_assert(BINS % kBlock == 0, "digits must cover the block");
     constexpr int NW = kBlock / kWave;
-    __shared__ uint32_t dbase[kRadixBins];
-    __shared__ uint32_t run[kRadixBins];
-    __shared__ uint32_t cnt[NW][kRadixBins];
+    __shared__ uint32_t dbase[BINS];
+    __shared__ uint32_t run[BINS];
+    __shared__ uint32_t cnt[NW][BINS];
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
-    uint32_t tot;
-    uint32_t ex = block_excl_scan(totals[tid], tot);
-    dbase[tid] = ex + hist[(size_t)tid * tiles + blockIdx.x];
-    run[tid] = 0;
+    // digit bases of this tile: exclusive scan of the digit totals (each
+    // thread holds PT consecutive digits) plus the tile's offset in its digit
+    uint32_t loc[PT];
+    uint32_t sum = 0;
 #pragma unroll
-    for (int w = 0; w < NW; ++w) cnt[w][tid] = 0;
+    for (int k = 0; k < PT; ++k) {
+        loc[k] = sum;
+        sum += totals[tid * PT + k];
+    }
+    uint32_t tot;
+    const uint32_t ex = block_excl_scan(sum, tot);
+#pragma unroll
+    for (int k = 0; k < PT; ++k) {
+        const int d = tid * PT + k;
+        dbase[d] = ex + loc[k] + hist[(size_t)d * tiles + blockIdx.x];
+        run[d] = 0;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) cnt[w][d] = 0;
+    }
     __syncthreads();
     const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     const uint32_t base = blockIdx.x * kSortTile;
@@ -126,10 +147,10 @@ __global__ __launch_bounds__(kBlock) void k_downsweep(const uint32_t *__restrict
         bool valid = e < n;
         uint32_t key = valid ? kin[e] : 0u;
         uint32_t val = valid ? vin[e] : 0u;
-        uint32_t d = (key >> shift) & (kRadixBins - 1);
+        uint32_t d = (key >> shift) & (BINS - 1);
         uint64_t mask = __ballot(valid);
 #pragma unroll
-        for (int b = 0; b < kRadixBits; ++b) {
+        for (int b = 0; b < D; ++b) {
             bool bit = (d >> b) & 1u;
             uint64_t bm = __ballot(bit);
             mask &= bit ? bm : ~bm;
@@ -146,15 +167,29 @@ __global__ __launch_bounds__(kBlock) void k_downsweep(const uint32_t *__restrict
             vout[pos] = val;
         }
         __syncthreads();
-        uint32_t add = 0;
 #pragma unroll
-        for (int w = 0; w < NW; ++w) {
-            add += cnt[w][tid];
-            cnt[w][tid] = 0;
+        for (int k = 0; k < PT; ++k) {
+            const int b = tid * PT + k;
+            uint32_t add = 0;
+#pragma unroll
+            for (int w = 0; w < NW; ++w) {
+                add += cnt[w][b];
+                cnt[w][b] = 0;
+            }
+            run[b] += add;
         }
-        run[tid] += add;
         __syncthreads();
     }
+}
+
+// One LSD pass with D-bit digits starting at bit `shift`.
+template <int D>
+void sort_pass(const Workspace &ws, uint32_t n, uint32_t tiles, int shift, int cur, hipStream_t s)
+{
+    k_upsweep<D><<<tiles, kBlock, 0, s>>>(ws.keys[cur], n, shift, ws.hist, tiles);
+    k_scan_digit<<<1u << D, kBlock, 0, s>>>(ws.hist, tiles, ws.totals);
+    k_downsweep<D><<<tiles, kBlock, 0, s>>>(ws.keys[cur], ws.vals[cur], ws.keys[cur ^ 1], ws.vals[cur ^ 1], n,
+                                            shift, ws.hist, tiles, ws.totals);
 }
 
 // Float offset from the bucket corner, ((x - o) - c L) evaluated in IEEE
@@ -344,17 +379,21 @@ hipError_t launch_build_cells(const Grid &g, int prec, const sph_particles &in, 
     uint32_t blocks = div_up(n, kBlock);
     if (n > 0) {
         k_hash<<<blocks, kBlock, 0, s>>>(g, n, in.x[0], in.x[1], in.x[2], ws.keys[0], ws.vals[0]);
-        int bits = key_bits(g.ncells);
-        int passes = (bits + kRadixBits - 1) / kRadixBits;
-        if (passes < 1) passes = 1;
-        uint32_t tiles = div_up(n, kSortTile);
+        // as few passes as digits of at most 10 bits allow, each of 8 to 10 bits
+        const int bits = key_bits(g.ncells);
+        const int passes = bits > 0 ? (bits + kMaxRadixBits - 1) / kMaxRadixBits : 1;
+        int dbits = (bits + passes - 1) / passes;
+        dbits = dbits < 8 ? 8 : dbits;
+        const uint32_t tiles = div_up(n, kSortTile);
         int cur = 0;
         for (int ps = 0; ps < passes; ++ps) {
-            int shift = ps * kRadixBits;
-            k_upsweep<<<tiles, kBlock, 0, s>>>(ws.keys[cur], n, shift, ws.hist, tiles);
-            k_scan_digit<<<kRadixBins, kBlock, 0, s>>>(ws.hist, tiles, ws.totals);
-            k_downsweep<<<tiles, kBlock, 0, s>>>(ws.keys[cur], ws.vals[cur], ws.keys[cur ^ 1],
-                                                 ws.vals[cur ^ 1], n, shift, ws.hist, tiles, ws.totals);
+            const int shift = ps * dbits;
+            if (dbits == 8)
+                sort_pass<8>(ws, n, tiles, shift, cur, s);
+            else if (dbits == 9)
+                sort_pass<9>(ws, n, tiles, shift, cur, s);
+            else
+                sort_pass<10>(ws, n, tiles, shift, cur, s);
             cur ^= 1;
         }
         if (prec == SPH_FP64)

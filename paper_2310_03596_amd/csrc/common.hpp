@@ -13,8 +13,8 @@ constexpr int kBlock = 256;          // threads per workgroup for streaming kern
 constexpr int kWave = 64;            // CDNA wavefront width
 constexpr int kSortItems = 8;        // keys per thread in a radix-sort tile
 constexpr int kSortTile = kBlock * kSortItems;
-constexpr int kRadixBits = 8;
-constexpr int kRadixBins = 1 << kRadixBits;
+constexpr int kMaxRadixBits = 10;     // digits of 8 to 10 bits: keys up to 20 bits sort in two passes
+constexpr int kMaxRadixBins = 1 << kMaxRadixBits;
 constexpr int kDiag = 7;             // integrate diagnostics
 constexpr int kDiagPartial = 8;      // per-block partial record (doubles)
 
@@ -160,8 +160,8 @@ inline size_t stage_bytes(int prec, int material)
 struct Workspace {
     uint32_t *keys[2];
     uint32_t *vals[2];
-    uint32_t *hist;        // kRadixBins * sort tiles
-    uint32_t *totals;      // kRadixBins
+    uint32_t *hist;        // kMaxRadixBins * sort tiles
+    uint32_t *totals;      // kMaxRadixBins
     uint32_t *counts;      // compaction block counts (+1)
     double *partials;      // kDiagPartial * reduction blocks
     char *stage;           // n * stage bytes
@@ -189,8 +189,8 @@ inline Workspace carve(void *base, uint32_t n, size_t stage_per_particle)
         w.keys[k] = reinterpret_cast<uint32_t *>(take(4 * nn));
         w.vals[k] = reinterpret_cast<uint32_t *>(take(4 * nn));
     }
-    w.hist = reinterpret_cast<uint32_t *>(take(4ull * kRadixBins * tiles));
-    w.totals = reinterpret_cast<uint32_t *>(take(4ull * kRadixBins));
+    w.hist = reinterpret_cast<uint32_t *>(take(4ull * kMaxRadixBins * tiles));
+    w.totals = reinterpret_cast<uint32_t *>(take(4ull * kMaxRadixBins));
     w.counts = reinterpret_cast<uint32_t *>(take(4ull * (blocks + 1)));
     w.partials = reinterpret_cast<double *>(take(8ull * kDiagPartial * blocks));
     w.stage = take(stage_per_particle * nn);

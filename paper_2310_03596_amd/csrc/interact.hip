@@ -44,28 +44,33 @@ constexpr int kWaves = kPairBlock / kWave;
 #define SPH_PAIR_SUB 4   // measured best of 4, 8, 16 on the 810k column (fewer live VGPRs)
 #endif
 constexpr int kSub = SPH_PAIR_SUB;         // candidates tested between list-fill checks
-constexpr int kHitCap = 40;                // listed hits per lane (u16 entries)
-constexpr int kWinBits = 12;               // hit entry: page slot (4 bits) | index in page (12 bits)
-constexpr uint32_t kWinLen = 1u << kWinBits;
-constexpr int kMaxWin = 16;
-// Source records staged per page (one neighbour row of a group, split into
-// pages when longer).  Sized so that a workgroup's LDS (hit lists + pages +
-// page tables) stays within 32 KB for FP32 (five workgroups per CU) and
-// within 40 KB for FP64 (four); the page covers the row union of a group in
-// about 97 % (FP32) and 75 % (FP64) of the cases on the column workload.
+constexpr int kMaxWin = 12;                // staged pages whose hits a list can hold at once
+// Per precision: source records staged per page (one neighbour row of a
+// group, split into pages when longer) and listed hits per lane (u8 entries:
+// the index inside the page).  A lane's hits arrive unevenly over the 9 rows
+// (its position inside its bucket favours some rows), so a list that fills
+// before the group ends forces every lane to evaluate while most lists are
+// part full; lists longer than the ~80 neighbours of a particle at h = 1.3 dx
+// are emptied once per group.  Sizes keep a workgroup's LDS (lists, page
+// marks, pages, page tables) within 40 KB, four workgroups per CU; the page
+// covers the row union of a group in about 97 % (FP32) and 70 % (FP64) of
+// the cases on the column workload.
 template <typename real>
-struct Page {
-    static constexpr int len = sizeof(real) == 4 ? 160 : 96;
+struct Tune {
+    static constexpr int page = sizeof(real) == 4 ? 160 : 80;
+    static constexpr int cap = 88;
 };
-static_assert(Page<float>::len <= (int)kWinLen && Page<double>::len <= (int)kWinLen, "page index must fit an entry");
-static_assert(Page<float>::len % kSub == 0 && Page<double>::len % kSub == 0, "reads stay below len + kSub");
+static_assert(Tune<float>::page + kSub <= 256 && Tune<double>::page + kSub <= 256, "page index must fit a u8 entry");
+static_assert(Tune<float>::page % kSub == 0 && Tune<double>::page % kSub == 0, "reads stay below page + kSub");
+static_assert(Tune<float>::cap <= 255 && Tune<double>::cap <= 255 && kMaxWin <= 255, "marks hold a u8 fill and slot");
 constexpr int kPassAdjoint = 2;            // reverse mode of the FORCE pass (fluid)
 #ifndef SPH_PAIR_WAVES_PER_EU
-#define SPH_PAIR_WAVES_PER_EU 5
+#define SPH_PAIR_WAVES_PER_EU 4
 #endif
 // Occupancy target (waves per SIMD; caps VGPRs at 512 / target) per
-// variant: the fluid FP32 pass fits 5 without spills, the larger solid and
-// FP64 bodies fit 4 and 3; the adjoint body (11 cotangents) 3 and 2.
+// variant: the LDS of a workgroup allows four per SIMD, which the fluid
+// passes and the FP32 solid pass reach; the FP64 solid body fits 3 and the
+// adjoint body (11 cotangents) 3 (FP32) and 2 (FP64).
 template <typename real, bool SOLID, bool ADJ>
 struct PairOccupancy {
     static constexpr int fp32 = ADJ ? 3 : (SOLID ? 4 : SPH_PAIR_WAVES_PER_EU);
@@ -205,8 +210,12 @@ void k_pairs(Params P, Grid g, PV<real> tg, const uint32_t *__restrict__ tidx, c
     constexpr bool SPLIT = sizeof(real) == 4;
     constexpr bool ADJ = PASS == kPassAdjoint;
     constexpr int NOUT = PASS == SPH_PASS_FORCE ? 6 : (ADJ ? 11 : 9);
-    constexpr int kPage = Page<real>::len;
-    __shared__ uint16_t hits[kHitCap][kPairBlock];
+    constexpr int kPage = Tune<real>::page;
+    constexpr int kHitCap = Tune<real>::cap;
+    __shared__ uint8_t hits[kHitCap][kPairBlock];   // index inside the page
+    // per lane, one mark per page in which it has hits: (slot << 8) | list fill
+    // at the end of that page's hits
+    __shared__ uint16_t marks[kMaxWin][kPairBlock];
     __shared__ v4 stage[kWaves][kPage + kSub];    // a page, then far sentinels
     __shared__ uint32_t wbase[kWaves][kMaxWin];   // first source index of each staged page
     __shared__ real wdy[kWaves][kMaxWin];         // (c_j - c_i) L in y and z of the page's row
@@ -285,11 +294,15 @@ void k_pairs(Params P, Grid g, PV<real> tg, const uint32_t *__restrict__ tidx, c
         v4 p, a, b, s0, s1;
         real qy, qz;
     };
-    auto fetch = [&](int s) {
+    // entry s of the lane's list; (mk, nb) walk the lane's marks as s ascends
+    // (each mark covers at least one entry, so one step suffices)
+    auto fetch = [&](int s, int &mk, int &nb) {
         Rec q;
-        const uint32_t e = hits[s][tid];
-        const uint32_t slot = e >> kWinBits;
-        const uint32_t jj = wbase[wave][slot] + (e & (kWinLen - 1));
+        mk += s >= nb ? 1 : 0;
+        const uint32_t m = marks[mk][tid];
+        nb = (int)(m & 0xFFu);
+        const uint32_t slot = m >> 8;
+        const uint32_t jj = wbase[wave][slot] + (uint32_t)hits[s][tid];
         q.qy = wdy[wave][slot];
         q.qz = wdz[wave][slot];
         q.p = src.pos[jj];
@@ -370,23 +383,34 @@ void k_pairs(Params P, Grid g, PV<real> tg, const uint32_t *__restrict__ tidx, c
                 for (int k = 0; k < 9; ++k) acc[k].add(o[k]);
             }
     };
-    // evaluate the pair terms of every listed hit, two at a time: the records
+    // Evaluate the pair terms of every listed hit, two at a time: the records
     // of the next two are loaded while the current two are evaluated, into
     // alternating buffers (no register copies); indices past the list end are
-    // clamped to its last entry, so every load reads a listed record
+    // clamped to its last entry, so every load reads a listed record.  Every
+    // page with hits must be marked first (close_page); the last mark ends at
+    // cnt, so the walk over the marks stays inside them.
+    int cnt0 = 0;   // list fill when the current page started
+    int npg = 0;    // marks written since the lists were last emptied
+    auto close_page = [&](int slot) {
+        if (cnt != cnt0) marks[npg++][tid] = (uint16_t)(((uint32_t)slot << 8) | (uint32_t)cnt);
+        cnt0 = cnt;
+    };
     auto flush = [&]() {
         if (cnt > 0) {
             const int last = cnt - 1;
-            Rec A = fetch(0);
-            Rec B = fetch(last < 1 ? last : 1);
+            int mk = 0, nb = (int)(marks[0][tid] & 0xFFu);
+            Rec A = fetch(0, mk, nb);
+            Rec B = fetch(last < 1 ? last : 1, mk, nb);
             for (int s = 0; s < cnt; s += 2) {
                 eval(A);
-                A = fetch(s + 2 < last ? s + 2 : last);
+                A = fetch(s + 2 < last ? s + 2 : last, mk, nb);
                 if (s + 1 < cnt) eval(B);
-                B = fetch(s + 3 < last ? s + 3 : last);
+                B = fetch(s + 3 < last ? s + 3 : last, mk, nb);
             }
         }
         cnt = 0;
+        cnt0 = 0;
+        npg = 0;
     };
 
     const real kFar = SPLIT ? real(1e30f) : real(1e300);
@@ -444,7 +468,7 @@ void k_pairs(Params P, Grid g, PV<real> tg, const uint32_t *__restrict__ tidx, c
                     flush();
                     nwin = 0;
                 }
-                const int slot = nwin++;
+                int slot = nwin++;
                 if (lane == 0) {
                     wbase[wave][slot] = pb;
                     wdy[wave][slot] = ddy;
@@ -491,21 +515,31 @@ void k_pairs(Params P, Grid g, PV<real> tg, const uint32_t *__restrict__ tidx, c
                 // inside the array
                 const int span = (nmax + kSub - 1) / kSub * kSub;
                 const int a = (int)la < kPage + kSub - span ? (int)la : kPage + kSub - span;
-                const uint32_t ebase = ((uint32_t)slot << kWinBits) + (uint32_t)a;
                 for (int k0 = 0; k0 < nmax; k0 += kSub) {
                     // at most kSub more entries per lane before the next check
-                    if (__ballot(cnt > kHitCap - kSub)) flush();
+                    if (__ballot(cnt > kHitCap - kSub)) {
+                        // empty the lists mid-page; the page keeps going as slot 0
+                        close_page(slot);
+                        flush();
+                        if (lane == 0) {
+                            wbase[wave][0] = pb;
+                            wdy[wave][0] = ddy;
+                            wdz[wave][0] = ddz;
+                        }
+                        slot = 0;
+                        nwin = 1;
+                    }
                     const int base = a + k0;
-                    const uint32_t eb = ebase + (uint32_t)k0;
 #pragma unroll
                     for (int m = 0; m < kSub; ++m) {
                         const v4 q = stage[wave][base + m];
                         const real t = fma(-q.z, fo[2], fma(-q.y, fo[1], fma(-q.x, fo[0], q.w)));
                         // the entry is written always and kept only when it is a hit
-                        hits[cnt][tid] = (uint16_t)(eb + (uint32_t)m);
+                        hits[cnt][tid] = (uint8_t)(base + m);
                         cnt += (t < Tl) ? 1 : 0;
                     }
                 }
+                close_page(slot);
             }
         }
         flush();
