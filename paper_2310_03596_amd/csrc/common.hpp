@@ -11,6 +11,18 @@ namespace sph {
 
 constexpr int kBlock = 256;          // threads per workgroup for streaming kernels
 constexpr int kWave = 64;            // CDNA wavefront width
+constexpr int kXcds = 8;             // accelerator dies (XCDs), each with its own L2
+
+// Workgroups are dispatched to the XCDs in turn (workgroup b runs on XCD
+// b mod 8).  This maps the launch index to a tile index so that each XCD
+// works through one contiguous run of tiles, keeping the data that
+// neighbouring tiles share in that XCD's L2.  A bijection on [0, n).
+__device__ inline uint32_t xcd_tile(uint32_t b, uint32_t n)
+{
+    const uint32_t x = b % kXcds, k = b / kXcds;
+    const uint32_t q = n / kXcds, r = n % kXcds;
+    return x * q + (x < r ? x : r) + k;
+}
 constexpr int kSortItems = 8;        // keys per thread in a radix-sort tile
 constexpr int kSortTile = kBlock * kSortItems;
 constexpr int kMaxRadixBits = 10;     // digits of 8 to 10 bits: keys up to 20 bits sort in two passes

@@ -212,24 +212,28 @@ void k_pairs(Params P, Grid g, PV<real> tg, const uint32_t *__restrict__ tidx, c
     constexpr int NOUT = PASS == SPH_PASS_FORCE ? 6 : (ADJ ? 11 : 9);
     constexpr int kPage = Tune<real>::page;
     constexpr int kHitCap = Tune<real>::cap;
-    __shared__ uint8_t hits[kHitCap][kPairBlock];   // index inside the page
+    // List entries and marks are laid out so that the 64 lanes of a wavefront
+    // always touch 64 different dwords (the wavefronts of the workgroup share
+    // each dword), whatever each lane's fill: no LDS bank conflicts.
+    __shared__ uint8_t hits[kHitCap][kWave][kWaves];   // index inside the page
     // per lane, one mark per page in which it has hits: (slot << 8) | list fill
     // at the end of that page's hits
-    __shared__ uint16_t marks[kMaxWin][kPairBlock];
+    __shared__ uint16_t marks[kMaxWin][kWaves / 2][kWave][2];
     __shared__ v4 stage[kWaves][kPage + kSub];    // a page, then far sentinels
     __shared__ uint32_t wbase[kWaves][kMaxWin];   // first source index of each staged page
     __shared__ real wdy[kWaves][kMaxWin];         // (c_j - c_i) L in y and z of the page's row
     __shared__ real wdz[kWaves][kMaxWin];
 
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
-    const uint32_t t = blockIdx.x * kPairBlock + tid;
+    const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);   // neighbouring tiles share sources
+    const uint32_t t = tile * kPairBlock + tid;
     uint32_t nt = tg.n;
     if (tidx) {
         uint32_t c = *ntdev;
         nt = c < nt ? c : nt;
     }
     // whole wavefronts beyond the targets leave; partial ones keep idle lanes
-    if (blockIdx.x * kPairBlock + wave * kWave >= nt) return;
+    if (tile * kPairBlock + wave * kWave >= nt) return;
     const bool valid = t < nt;
     const uint32_t i = valid ? (tidx ? tidx[t] : t) : 0u;
 
@@ -299,10 +303,10 @@ void k_pairs(Params P, Grid g, PV<real> tg, const uint32_t *__restrict__ tidx, c
     auto fetch = [&](int s, int &mk, int &nb) {
         Rec q;
         mk += s >= nb ? 1 : 0;
-        const uint32_t m = marks[mk][tid];
+        const uint32_t m = marks[mk][wave >> 1][lane][wave & 1];
         nb = (int)(m & 0xFFu);
         const uint32_t slot = m >> 8;
-        const uint32_t jj = wbase[wave][slot] + (uint32_t)hits[s][tid];
+        const uint32_t jj = wbase[wave][slot] + (uint32_t)hits[s][lane][wave];
         q.qy = wdy[wave][slot];
         q.qz = wdz[wave][slot];
         q.p = src.pos[jj];
@@ -392,13 +396,13 @@ void k_pairs(Params P, Grid g, PV<real> tg, const uint32_t *__restrict__ tidx, c
     int cnt0 = 0;   // list fill when the current page started
     int npg = 0;    // marks written since the lists were last emptied
     auto close_page = [&](int slot) {
-        if (cnt != cnt0) marks[npg++][tid] = (uint16_t)(((uint32_t)slot << 8) | (uint32_t)cnt);
+        if (cnt != cnt0) marks[npg++][wave >> 1][lane][wave & 1] = (uint16_t)(((uint32_t)slot << 8) | (uint32_t)cnt);
         cnt0 = cnt;
     };
     auto flush = [&]() {
         if (cnt > 0) {
             const int last = cnt - 1;
-            int mk = 0, nb = (int)(marks[0][tid] & 0xFFu);
+            int mk = 0, nb = (int)(marks[0][wave >> 1][lane][wave & 1] & 0xFFu);
             Rec A = fetch(0, mk, nb);
             Rec B = fetch(last < 1 ? last : 1, mk, nb);
             for (int s = 0; s < cnt; s += 2) {
@@ -535,7 +539,7 @@ void k_pairs(Params P, Grid g, PV<real> tg, const uint32_t *__restrict__ tidx, c
                         const v4 q = stage[wave][base + m];
                         const real t = fma(-q.z, fo[2], fma(-q.y, fo[1], fma(-q.x, fo[0], q.w)));
                         // the entry is written always and kept only when it is a hit
-                        hits[cnt][tid] = (uint8_t)(base + m);
+                        hits[cnt][lane][wave] = (uint8_t)(base + m);
                         cnt += (t < Tl) ? 1 : 0;
                     }
                 }
