@@ -52,6 +52,40 @@ def parse():
     return ap.parse_args()
 
 
+COUNTERS = os.path.join(ROOT, "profiles", "pair_force_column_counters.md")
+PAIR_SOURCES = ("paper_2310_03596_amd/csrc/interact.hip", "paper_2310_03596_amd/csrc/pair.hpp",
+                "paper_2310_03596_amd/csrc/common.hpp")
+
+
+def pair_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in PAIR_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def recorded_traffic(prec: int):
+    """HBM bytes per FORCE launch from the committed counter summary (FETCH_SIZE
+    + WRITE_SIZE, each scaled by the same counter on a copy of known size), or
+    None when the summary is missing or the kernel sources changed since."""
+    try:
+        with open(COUNTERS) as fh:
+            lines = fh.read().splitlines()
+    except OSError:
+        return None
+    kv = {}
+    for ln in lines:
+        if ln.startswith("    ") and ":" in ln:
+            k, v = ln.strip().split(":", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("source_sha256") != pair_source_hash():
+        return None
+    v = kv.get("traffic_bytes_per_launch_" + ("fp32" if prec == 1 else "fp64"))
+    return int(v) if v else None
+
+
 def time_form(wl, prec, steps, warmup):
     import torch
     from paper_2310_03596_amd.sim import Sim
@@ -161,7 +195,7 @@ def cpu_leg(wl, budget_s):
     t0 = time.perf_counter()
     dts1, _ = cpu.run(wl.params, wl.grid, st, 1)
     t1 = time.perf_counter() - t0
-    more = max(0, min(49, int(budget_s / max(t1, 1e-3)) - 1))
+    more = max(0, min(149, int(budget_s / max(t1, 1e-3)) - 1))
     t0 = time.perf_counter()
     # continuing run: its first dt is the EOS-stage dt of the current state,
     # which equals the previous step's next dt, so the schedule is unbroken
@@ -236,7 +270,7 @@ def main():
                    if main_prec == 1 else "plain FP64"},
         "roofline": {"bound": "alu", "kernel": "FORCE pass (k_interact)",
                      "achieved": r["force_tflops"], "peak": PEAK_TFLOPS[main_prec], "unit": "TFLOP/s",
-                     "frac": r["force_tflops"] / PEAK_TFLOPS[main_prec], "traffic": None,
+                     "frac": r["force_tflops"] / PEAK_TFLOPS[main_prec], "traffic": recorded_traffic(main_prec),
                      "avg_launch_ms": r["force_ms"], "flops_per_launch": r["flops_per_launch"],
                      "units_per_launch": {"candidates": r["candidates"], "pairs_within_2h": r["pairs"]}},
         "pair_evals_per_s": r["pair_evals_per_s"],
