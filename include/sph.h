@@ -183,8 +183,8 @@ int sph_pack_boundary(const sph_particles *local, const uint32_t *boundary_idx,
 /* Steps (e) and (f).  For every target i (all of `targets` when target_idx is
  * NULL, else target_idx[k] for k < *n_targets_dev, at most targets->n), sums
  * the pair terms over sources j with |x_j - x_i| < 2h found through the
- * sources' bucket table.  When sources and targets are the same array
- * (local-local pass, step e) j == i is skipped.  pass = SPH_PASS_FORCE: rates
+ * sources' bucket table.  Pairs with r = 0 (j == i in the local-local pass,
+ * step e, or coincident particles) add nothing.  pass = SPH_PASS_FORCE: rates
  * of mass, momentum, energy and volume from the acoustic Riemann solver
  * (solids: Cauchy stress -p I + S); SPH_PASS_GRADIENT: velocity gradient L.
  * zero_first = 1 overwrites the rate entries of the targets, 0 adds to them
@@ -192,7 +192,8 @@ int sph_pack_boundary(const sph_particles *local, const uint32_t *boundary_idx,
  * Summation over j runs in ascending source index.  Both arrays must be
  * hash-sorted on `grid`.  The workspace receives a packed copy of the
  * sources' pair inputs (sized by sph_workspace_size for sources->n).
- * Errors: SPH_ERR_ARG (precision or material mismatch, missing field),
+ * Errors: SPH_ERR_ARG (precision or material mismatch, missing field,
+ * sources->n at or above 2^28 in SPH_FP32_SPLIT or 2^27 in SPH_FP64),
  * SPH_ERR_WORKSPACE. */
 int sph_interact(const sph_params *params, const sph_grid *grid, int pass,
                  const sph_particles *targets, const uint32_t *target_idx,
@@ -230,8 +231,9 @@ int sph_count_pairs(const sph_params *params, const sph_grid *grid, const sph_pa
  * gathers its whole cotangent from its neighbours' rate cotangents without
  * atomics.  The workspace (sph_workspace_size with SPH_SOLID_J2, which has
  * room for the extra staged records) receives packed copies of the
- * particles and their rate cotangents.  Errors: SPH_ERR_ARG,
- * SPH_ERR_WORKSPACE, SPH_ERR_UNSUPPORTED (solids). */
+ * particles and their rate cotangents.  Errors: SPH_ERR_ARG (also p->n at
+ * or above 2^28 in SPH_FP32_SPLIT or 2^27 in SPH_FP64), SPH_ERR_WORKSPACE,
+ * SPH_ERR_UNSUPPORTED (solids). */
 int sph_interact_adjoint(const sph_params *params, const sph_grid *grid, const sph_particles *p,
                          sph_cells cells, const sph_rates *rates_bar, const sph_adjoint *bar,
                          void *ws, size_t ws_bytes, void *stream);

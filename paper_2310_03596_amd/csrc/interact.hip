@@ -309,12 +309,16 @@ void k_pairs(Params P, Grid g, PV<real> tg, const uint32_t *__restrict__ tidx, c
         const uint32_t jj = wbase[wave][slot] + (uint32_t)hits[s][lane][wave];
         q.qy = wdy[wave][slot];
         q.qz = wdz[wave][slot];
-        q.p = src.pos[jj];
-        q.a = src.va[jj];
-        if constexpr (PASS == SPH_PASS_FORCE || ADJ) q.b = src.vb[jj];
+        // a 32-bit byte offset from each array's base (sources are fewer than
+        // 2^28 FP32 / 2^27 FP64 records), so the loads take the scalar-base form
+        const uint32_t ob = jj * (uint32_t)sizeof(v4);
+        auto at = [&](const v4 *base) { return *reinterpret_cast<const v4 *>(reinterpret_cast<const char *>(base) + ob); };
+        q.p = at(src.pos);
+        q.a = at(src.va);
+        if constexpr (PASS == SPH_PASS_FORCE || ADJ) q.b = at(src.vb);
         if constexpr ((PASS == SPH_PASS_FORCE && SOLID) || ADJ) {
-            q.s0 = src.s0[jj];
-            q.s1 = src.s1[jj];
+            q.s0 = at(src.s0);
+            q.s1 = at(src.s1);
         }
         return q;
     };
