@@ -76,6 +76,12 @@ def _declare(L):
                          C.c_double, vp, vp, vp]
     L.or_run.restype = C.c_int
     L.or_num_threads.restype = C.c_int
+    L.or_centroid.argtypes = [C.POINTER(OState), vp]
+    L.or_balance_hash.argtypes = [C.POINTER(OState), vp, vp, C.c_uint32, vp]
+    L.or_balance_hash.restype = C.c_int64
+    L.or_balance_select.argtypes = [C.c_int64, vp, C.c_uint32, C.c_int64, vp]
+    L.or_balance_select.restype = C.c_int
+    L.or_swap.argtypes = [C.POINTER(OState), vp, C.POINTER(OState), vp, C.c_int64]
 
 
 def num_threads() -> int:
@@ -356,3 +362,43 @@ def run(params: dict, grid: dict, s: State, nsteps: int, fixed_dt: float = 0.0, 
 def prime(params: dict, s: State):
     """EOS stage on the initial state: rho = m / w, p, c; returns diagnostics."""
     return integrate(params, EOS, s)
+
+
+# ------------------------------------------------------------- balancing
+
+HMAX = 1000   # maximum balancing hash (Section III.A: "typically 1000")
+
+
+def centroid(s: State):
+    """(Cg (3,), total mass): mass-weighted centre of gravity (Section III.A)."""
+    out = np.zeros(4)
+    lib().or_centroid(C.byref(s.struct()), _ptr(out))
+    return out[:3].copy(), float(out[3])
+
+
+def balance_hash(s: State, cg_own, cg_other, hmax: int = HMAX):
+    """Balancing hash of every particle towards the other GPU's Cg, and the
+    number with a positive hash (Section III.A)."""
+    own = np.ascontiguousarray(cg_own, dtype=np.float64)
+    oth = np.ascontiguousarray(cg_other, dtype=np.float64)
+    h = np.zeros(s.n, dtype=np.uint32)
+    npos = lib().or_balance_hash(C.byref(s.struct()), _ptr(own), _ptr(oth), hmax, _ptr(h))
+    return h, int(npos)
+
+
+def balance_select(bhash: np.ndarray, k: int, hmax: int = HMAX) -> np.ndarray:
+    """Indices of the k largest balancing hashes, ties in ascending index."""
+    bhash = np.ascontiguousarray(bhash, dtype=np.uint32)
+    sel = np.zeros(max(k, 1), dtype=np.uint32)
+    if lib().or_balance_select(bhash.shape[0], _ptr(bhash), hmax, k, _ptr(sel)) != 0:
+        raise MemoryError
+    return sel[:k]
+
+
+def swap(a: State, sel_a: np.ndarray, b: State, sel_b: np.ndarray):
+    """Exchange the selected particles of a and b pairwise (in place)."""
+    k = len(sel_a)
+    assert len(sel_b) == k
+    sa = np.ascontiguousarray(sel_a, dtype=np.uint32)
+    sb = np.ascontiguousarray(sel_b, dtype=np.uint32)
+    lib().or_swap(C.byref(a.struct()), _ptr(sa), C.byref(b.struct()), _ptr(sb), k)

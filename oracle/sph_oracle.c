@@ -22,6 +22,9 @@
  *               pair terms (Section II, steps e and f); a coincident pair has
  *               no direction and every term carries F(0) = 0, so it adds 0
  *   integrate   symplectic Euler, reflective walls, EOS              (Section II, step g)
+ *   balance     centres of gravity, balancing hash towards the other GPU's
+ *               centre, selection of the k = min(n+_A, n+_B) largest, and
+ *               the pairwise swap                                    (Section III.A)
  *
  * Every floating-point operation is IEEE binary64, built without FMA
  * contraction.  Sums run over j in ascending sorted index, visiting the 27
@@ -715,4 +718,121 @@ int or_run(const op_t *P, const og_t *g, os_t *s, int nsteps, double fixed_dt,
     free_state(&w.tmp);
     free(w.perm); free(w.start); free(w.rates); free(w.L);
     return 0;
+}
+
+/* ------------------------------------------------------------- balancing
+ * Periodic swap heuristic between two GPUs A and B (Section III.A), the part
+ * one GPU computes.  Readings (the paper states them in words only):
+ *   centre of gravity  Cg = sum m_i x_i / sum m_i (mass-weighted), summed in
+ *                      index order;
+ *   balancing hash     with e = Cg_B - Cg_A and M = (Cg_A + Cg_B) / 2, the
+ *                      projection past the midpoint towards B is
+ *                      s = (x - M).e / |e|; hash 0 when s <= 0 (own side),
+ *                      hmax when s >= |e| / 2 (at or beyond the other Cg),
+ *                      else ceil(hmax s / (|e| / 2)).  Evaluated without a
+ *                      square root as v = hmax (2 t / |e|^2), t = (x - M).e,
+ *                      in this operation order:
+ *                        t = ((x0 - M0) e0 + (x1 - M1) e1) + (x2 - M2) e2
+ *                        ee = (e0 e0 + e1 e1) + e2 e2
+ *                        v = hmax * ((t + t) / ee)
+ *                        hash = t > 0 ? (v >= hmax ? hmax : ceil(v)) : 0
+ *                      and 0 for every particle when ee = 0;
+ *   swap count         k = min(number with positive hash on A, on B);
+ *   selection          the k particles of largest hash, ties in ascending
+ *                      index (a stable sort by descending hash);
+ *   swap               the selected particles of A and of B exchange places,
+ *                      pairwise in selection order (every field), so both
+ *                      GPUs keep their particle counts.
+ */
+void or_centroid(const os_t *s, double cg[4])
+{
+    double sx = 0.0, sy = 0.0, sz = 0.0, sm = 0.0;
+    for (int64_t i = 0; i < s->n; ++i) {
+        const double m = s->m[i];
+        sx += m * s->x[3 * i + 0];
+        sy += m * s->x[3 * i + 1];
+        sz += m * s->x[3 * i + 2];
+        sm += m;
+    }
+    cg[0] = sm > 0.0 ? sx / sm : 0.0;
+    cg[1] = sm > 0.0 ? sy / sm : 0.0;
+    cg[2] = sm > 0.0 ? sz / sm : 0.0;
+    cg[3] = sm;
+}
+
+int64_t or_balance_hash(const os_t *s, const double cg_own[3], const double cg_other[3], uint32_t hmax,
+                        uint32_t *bhash)
+{
+    double e[3], M[3];
+    for (int d = 0; d < 3; ++d) {
+        e[d] = cg_other[d] - cg_own[d];
+        M[d] = 0.5 * (cg_own[d] + cg_other[d]);
+    }
+    const double ee = (e[0] * e[0] + e[1] * e[1]) + e[2] * e[2];
+    int64_t npos = 0;
+    for (int64_t i = 0; i < s->n; ++i) {
+        uint32_t h = 0;
+        if (ee > 0.0) {
+            const double *x = s->x + 3 * i;
+            const double t = ((x[0] - M[0]) * e[0] + (x[1] - M[1]) * e[1]) + (x[2] - M[2]) * e[2];
+            if (t > 0.0) {
+                const double v = (double)hmax * ((t + t) / ee);
+                h = v >= (double)hmax ? hmax : (uint32_t)ceil(v);
+            }
+        }
+        bhash[i] = h;
+        npos += h > 0;
+    }
+    return npos;
+}
+
+/* Indices of the k particles of largest balancing hash, ties in ascending
+ * index: a stable counting sort by hmax - hash, first k entries. */
+int or_balance_select(int64_t n, const uint32_t *bhash, uint32_t hmax, int64_t k, uint32_t *sel)
+{
+    uint32_t *key = malloc(sizeof(uint32_t) * (n > 0 ? n : 1));
+    uint32_t *perm = malloc(sizeof(uint32_t) * (n > 0 ? n : 1));
+    if (!key || !perm) {
+        free(key);
+        free(perm);
+        return -1;
+    }
+    for (int64_t i = 0; i < n; ++i) key[i] = hmax - bhash[i];
+    or_sort_perm(n, key, hmax + 1, perm);
+    for (int64_t t = 0; t < k && t < n; ++t) sel[t] = perm[t];
+    free(key);
+    free(perm);
+    return 0;
+}
+
+static void swap_d(double *a, double *b, int k)
+{
+    for (int q = 0; q < k; ++q) {
+        const double t = a[q];
+        a[q] = b[q];
+        b[q] = t;
+    }
+}
+
+void or_swap(os_t *a, const uint32_t *sel_a, os_t *b, const uint32_t *sel_b, int64_t k)
+{
+    for (int64_t t = 0; t < k; ++t) {
+        const int64_t i = sel_a[t], j = sel_b[t];
+        swap_d(a->x + 3 * i, b->x + 3 * j, 3);
+        swap_d(a->v + 3 * i, b->v + 3 * j, 3);
+        swap_d(a->m + i, b->m + j, 1);
+        swap_d(a->w + i, b->w + j, 1);
+        swap_d(a->rho + i, b->rho + j, 1);
+        swap_d(a->p + i, b->p + j, 1);
+        swap_d(a->c + i, b->c + j, 1);
+        swap_d(a->E + i, b->E + j, 1);
+        if (a->S && b->S) swap_d(a->S + 6 * i, b->S + 6 * j, 6);
+        if (a->ep && b->ep) swap_d(a->ep + i, b->ep + j, 1);
+        const uint32_t id = a->id[i];
+        a->id[i] = b->id[j];
+        b->id[j] = id;
+        const uint32_t hh = a->hash[i];
+        a->hash[i] = b->hash[j];
+        b->hash[j] = hh;
+    }
 }
