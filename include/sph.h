@@ -258,6 +258,62 @@ int sph_integrate_adjoint(const sph_params *params, int stage, const sph_particl
 int sph_permute_adjoint(int prec, uint32_t n, const uint32_t *perm, const sph_adjoint *in,
                         const sph_adjoint *out, void *stream);
 
+/* ---------------------------------------------------------------------
+ * Periodic particle swapping between a pair of GPUs (Section III.A), the
+ * part one GPU computes.  A round between GPUs A and B: each computes its
+ * centre of gravity (sph_centroid) and, from the other's, the balancing hash
+ * of its particles and the count of positive hashes (sph_balance_hash); each
+ * selects its k = min(n+_A, n+_B) particles of largest hash
+ * (sph_balance_select); the selected particles change GPU pairwise
+ * (sph_swap, which exchanges them between two arrays on one device, the
+ * stand-in for the send and receive between the GPUs).  Both GPUs keep
+ * their particle counts.  The paper runs this every 20 integration loops
+ * and repeats it for every GPU pair.  The arrays need not be hash-sorted;
+ * after a swap the next sph_build_cells re-sorts them.
+ * --------------------------------------------------------------------- */
+
+/* Mass-weighted centre of gravity of p: cg_dev[0..2] = sum m x / sum m,
+ * cg_dev[3] = sum m (FP64; a fixed summation order, so repeated calls give
+ * identical results; 0 for an empty array).  Reads x and m.  The workspace is
+ * sized by sph_workspace_size for p->n.  Errors: SPH_ERR_ARG,
+ * SPH_ERR_WORKSPACE. */
+int sph_centroid(const sph_particles *p, double *cg_dev, void *ws, size_t ws_bytes, void *stream);
+
+/* Balancing hash of every particle of p (the GPU whose centre is
+ * cg_own_dev[0..2]) towards the other GPU's centre cg_other_dev[0..2]: with
+ * e = other - own and M their midpoint, t = ((x0 - M0) e0 + (x1 - M1) e1) +
+ * (x2 - M2) e2 and ee = (e0 e0 + e1 e1) + e2 e2 (IEEE binary64, no
+ * contraction), bhash_out[i] = 0 when t <= 0 or ee = 0, else
+ * min(ceil(hmax * ((t + t) / ee)), hmax): 0 on the own side of the midpoint,
+ * hmax at or beyond the other centre, proportional in between.
+ * *n_positive_dev receives the number of positive hashes.  hmax is the
+ * maximum swapping hash (the paper: typically 1000), 1 <= hmax < 2^20.
+ * The workspace is sized by sph_workspace_size for p->n.  Errors:
+ * SPH_ERR_ARG, SPH_ERR_WORKSPACE. */
+int sph_balance_hash(const sph_particles *p, const double *cg_own_dev, const double *cg_other_dev,
+                     uint32_t hmax, uint32_t *bhash_out, uint32_t *n_positive_dev, void *ws, size_t ws_bytes,
+                     void *stream);
+
+/* Selection for the swap: k = min(*n_positive_own_dev, *n_positive_other_dev,
+ * n) is written to *k_dev and sel_out[0..k) receives the indices of the k
+ * particles of largest balancing hash, ties in ascending index (a stable
+ * sort by descending hash).  bhash holds n hashes, each at most hmax;
+ * sel_out has room for n entries.  The workspace is sized by
+ * sph_workspace_size for n.  Errors: SPH_ERR_ARG, SPH_ERR_WORKSPACE. */
+int sph_balance_select(uint32_t n, const uint32_t *bhash, uint32_t hmax, const uint32_t *n_positive_own_dev,
+                       const uint32_t *n_positive_other_dev, uint32_t *sel_out, uint32_t *k_dev, void *ws,
+                       size_t ws_bytes, void *stream);
+
+/* Pairwise exchange: for t < min(*k_dev, k_max), particle sel_a[t] of a and
+ * particle sel_b[t] of b swap every field that both arrays hold (x, off,
+ * hash, id, v, m, omega, rho, p, c, e, E, S, eps_p).  The entries of sel_a
+ * must be distinct, and so must those of sel_b (sph_balance_select gives
+ * such lists); indices out of range are skipped.  k_max bounds the launch
+ * (for instance min(a->n, b->n)).  Errors: SPH_ERR_ARG (precisions differ,
+ * missing lists). */
+int sph_swap(sph_particles *a, const uint32_t *sel_a, sph_particles *b, const uint32_t *sel_b,
+             const uint32_t *k_dev, uint32_t k_max, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

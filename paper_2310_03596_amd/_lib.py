@@ -55,7 +55,8 @@ class SphAdjoint(C.Structure):
 
 EXPORTS = ("sph_version", "sph_last_error", "sph_workspace_size", "sph_build_cells", "sph_mark_boundary",
            "sph_pack_boundary", "sph_interact", "sph_count_pairs", "sph_integrate", "sph_interact_adjoint",
-           "sph_integrate_adjoint", "sph_permute_adjoint")
+           "sph_integrate_adjoint", "sph_permute_adjoint", "sph_centroid", "sph_balance_hash",
+           "sph_balance_select", "sph_swap")
 
 _lib = None
 
@@ -96,6 +97,10 @@ def load():
     L.sph_integrate_adjoint.argtypes = [P(SphParams), C.c_int, P(SphParticles), P(SphRates), _vp,
                                         P(SphAdjoint), P(SphRates), _vp, _vp, C.c_size_t, _vp]
     L.sph_permute_adjoint.argtypes = [C.c_int, C.c_uint32, _vp, P(SphAdjoint), P(SphAdjoint), _vp]
+    L.sph_centroid.argtypes = [P(SphParticles), _vp, _vp, C.c_size_t, _vp]
+    L.sph_balance_hash.argtypes = [P(SphParticles), _vp, _vp, C.c_uint32, _vp, _vp, _vp, C.c_size_t, _vp]
+    L.sph_balance_select.argtypes = [C.c_uint32, _vp, C.c_uint32, _vp, _vp, _vp, _vp, _vp, C.c_size_t, _vp]
+    L.sph_swap.argtypes = [P(SphParticles), _vp, P(SphParticles), _vp, _vp, C.c_uint32, _vp]
     for name in EXPORTS[3:]:
         getattr(L, name).restype = C.c_int
     _lib = L
@@ -173,3 +178,21 @@ def sph_integrate_adjoint(params, stage, p, rates, dt_ptr, bar, rates_bar, pbar_
 def sph_permute_adjoint(prec, n, perm_ptr, inp, out, stream):
     return check("sph_permute_adjoint", load().sph_permute_adjoint(prec, n, perm_ptr, C.byref(inp),
                                                                    C.byref(out), stream))
+
+
+def sph_centroid(p, cg_ptr, ws_ptr, ws_bytes, stream):
+    return check("sph_centroid", load().sph_centroid(C.byref(p), cg_ptr, ws_ptr, ws_bytes, stream))
+
+
+def sph_balance_hash(p, cg_own_ptr, cg_other_ptr, hmax, bhash_ptr, npos_ptr, ws_ptr, ws_bytes, stream):
+    return check("sph_balance_hash", load().sph_balance_hash(C.byref(p), cg_own_ptr, cg_other_ptr, hmax, bhash_ptr,
+                                                             npos_ptr, ws_ptr, ws_bytes, stream))
+
+
+def sph_balance_select(n, bhash_ptr, hmax, npos_own_ptr, npos_other_ptr, sel_ptr, k_ptr, ws_ptr, ws_bytes, stream):
+    return check("sph_balance_select", load().sph_balance_select(n, bhash_ptr, hmax, npos_own_ptr, npos_other_ptr,
+                                                                 sel_ptr, k_ptr, ws_ptr, ws_bytes, stream))
+
+
+def sph_swap(a, sel_a_ptr, b, sel_b_ptr, k_ptr, k_max, stream):
+    return check("sph_swap", load().sph_swap(C.byref(a), sel_a_ptr, C.byref(b), sel_b_ptr, k_ptr, k_max, stream))

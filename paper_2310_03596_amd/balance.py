@@ -1,0 +1,66 @@
+"""One round of the particle-swapping heuristic between two GPUs' particle
+sets (Section III.A), held as two arrays on one device.
+
+Every step runs in libsph; this module only owns the buffers and sequences
+the calls: both centres of gravity, both balancing hashes (each towards the
+other's centre) with their positive counts, both selections of
+k = min(n+_A, n+_B) particles, and the pairwise swap.
+"""
+from __future__ import annotations
+
+import torch
+
+from . import _lib as L
+from .state import Particles, grid_struct, stream_handle
+
+HMAX = 1000   # maximum swapping hash (the paper: "typically 1000")
+
+
+class BalancePair:
+    """Two particle sets A and B (e.g. the shares of two GPUs) on one device."""
+
+    def __init__(self, wl_a, wl_b, prec: int, device="cuda", hmax: int = HMAX):
+        self.prec, self.hmax = prec, hmax
+        self.A = Particles.upload(wl_a, prec, device)
+        self.B = Particles.upload(wl_b, prec, device)
+        n = max(self.A.n, self.B.n, 1)
+        solid = wl_a.S is not None
+        self.ws_bytes = L.sph_workspace_size(grid_struct(wl_a.grid), n, prec,
+                                             L.SPH_SOLID_J2 if solid else L.SPH_FLUID_TAIT)
+        self.ws = torch.zeros(self.ws_bytes, dtype=torch.uint8, device=device)
+        i32 = dict(dtype=torch.int32, device=device)
+        self.cg = torch.zeros((2, 4), dtype=torch.float64, device=device)
+        self.bh = [torch.zeros(max(self.A.n, 1), **i32), torch.zeros(max(self.B.n, 1), **i32)]
+        self.sel = [torch.zeros(max(self.A.n, 1), **i32), torch.zeros(max(self.B.n, 1), **i32)]
+        self.npos = torch.zeros(2, **i32)
+        self.k = torch.zeros(2, **i32)
+
+    def centroids(self):
+        st = stream_handle()
+        for q, p in enumerate((self.A, self.B)):
+            L.sph_centroid(p.struct(), self.cg[q].data_ptr(), self.ws.data_ptr(), self.ws_bytes, st)
+
+    def hashes(self):
+        st = stream_handle()
+        for q, p in enumerate((self.A, self.B)):
+            L.sph_balance_hash(p.struct(), self.cg[q].data_ptr(), self.cg[1 - q].data_ptr(), self.hmax,
+                               self.bh[q].data_ptr(), self.npos[q:q + 1].data_ptr(), self.ws.data_ptr(),
+                               self.ws_bytes, st)
+
+    def selections(self):
+        st = stream_handle()
+        for q, p in enumerate((self.A, self.B)):
+            L.sph_balance_select(p.n, self.bh[q].data_ptr(), self.hmax, self.npos[q:q + 1].data_ptr(),
+                                 self.npos[1 - q:2 - q].data_ptr(), self.sel[q].data_ptr(),
+                                 self.k[q:q + 1].data_ptr(), self.ws.data_ptr(), self.ws_bytes, st)
+
+    def swap(self):
+        L.sph_swap(self.A.struct(), self.sel[0].data_ptr(), self.B.struct(), self.sel[1].data_ptr(),
+                   self.k[0:1].data_ptr(), min(self.A.n, self.B.n), stream_handle())
+
+    def round(self):
+        """Enqueue one full round; returns nothing (k stays on the device)."""
+        self.centroids()
+        self.hashes()
+        self.selections()
+        self.swap()

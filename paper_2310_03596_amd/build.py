@@ -16,7 +16,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 OBJ_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libsph.so")
-SOURCES = ["cells.hip", "interact.hip", "integrate.hip", "adjoint.hip", "abi.cpp"]
+SOURCES = ["cells.hip", "interact.hip", "integrate.hip", "adjoint.hip", "balance.hip", "abi.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

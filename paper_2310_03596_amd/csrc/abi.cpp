@@ -387,4 +387,58 @@ int sph_permute_adjoint(int prec, uint32_t n, const uint32_t *perm, const sph_ad
     return hip_status(launch_permute_adjoint(prec, n, perm, *in, *out, (hipStream_t)stream), "sph_permute_adjoint");
 }
 
+// ------------------------------------------------------------- balancing
+
+int sph_centroid(const sph_particles *p, double *cg_dev, void *ws, size_t ws_bytes, void *stream)
+{
+    if (!p) return fail(SPH_ERR_ARG, "p is NULL");
+    if (p->prec != SPH_FP64 && p->prec != SPH_FP32_SPLIT) return fail(SPH_ERR_ARG, "unknown precision %d", p->prec);
+    if (!cg_dev) return fail(SPH_ERR_ARG, "cg_dev is NULL");
+    if (p->n > 0 && (!p->x[0] || !p->x[1] || !p->x[2] || !p->m)) return fail(SPH_ERR_ARG, "x or m is NULL");
+    Workspace w;
+    if (!check_ws(ws, ws_bytes, p->n, w)) return SPH_ERR_WORKSPACE;
+    return hip_status(launch_centroid(p->prec, *p, cg_dev, w, (hipStream_t)stream), "sph_centroid");
+}
+
+int sph_balance_hash(const sph_particles *p, const double *cg_own_dev, const double *cg_other_dev, uint32_t hmax,
+                     uint32_t *bhash_out, uint32_t *n_positive_dev, void *ws, size_t ws_bytes, void *stream)
+{
+    if (!p) return fail(SPH_ERR_ARG, "p is NULL");
+    if (!cg_own_dev || !cg_other_dev || !n_positive_dev) return fail(SPH_ERR_ARG, "a centre or the count is NULL");
+    if (hmax < 1 || hmax >= (1u << 20)) return fail(SPH_ERR_ARG, "hmax = %u must be in [1, 2^20)", hmax);
+    if (p->n > 0 && (!p->x[0] || !p->x[1] || !p->x[2] || !bhash_out))
+        return fail(SPH_ERR_ARG, "x or bhash_out is NULL");
+    Workspace w;
+    if (!check_ws(ws, ws_bytes, p->n, w)) return SPH_ERR_WORKSPACE;
+    return hip_status(launch_balance_hash(*p, cg_own_dev, cg_other_dev, hmax, bhash_out, n_positive_dev, w,
+                                          (hipStream_t)stream),
+                      "sph_balance_hash");
+}
+
+int sph_balance_select(uint32_t n, const uint32_t *bhash, uint32_t hmax, const uint32_t *n_positive_own_dev,
+                       const uint32_t *n_positive_other_dev, uint32_t *sel_out, uint32_t *k_dev, void *ws,
+                       size_t ws_bytes, void *stream)
+{
+    if (!n_positive_own_dev || !n_positive_other_dev || !k_dev)
+        return fail(SPH_ERR_ARG, "a count or k_dev is NULL");
+    if (hmax < 1 || hmax >= (1u << 20)) return fail(SPH_ERR_ARG, "hmax = %u must be in [1, 2^20)", hmax);
+    if (n > 0 && (!bhash || !sel_out)) return fail(SPH_ERR_ARG, "bhash or sel_out is NULL");
+    Workspace w;
+    if (!check_ws(ws, ws_bytes, n, w)) return SPH_ERR_WORKSPACE;
+    return hip_status(launch_balance_select(n, bhash, hmax, n_positive_own_dev, n_positive_other_dev, sel_out,
+                                            k_dev, w, (hipStream_t)stream),
+                      "sph_balance_select");
+}
+
+int sph_swap(sph_particles *a, const uint32_t *sel_a, sph_particles *b, const uint32_t *sel_b, const uint32_t *k_dev,
+             uint32_t k_max, void *stream)
+{
+    if (!a || !b) return fail(SPH_ERR_ARG, "a/b is NULL");
+    if (a->prec != b->prec) return fail(SPH_ERR_ARG, "a and b precisions differ");
+    if (a->prec != SPH_FP64 && a->prec != SPH_FP32_SPLIT) return fail(SPH_ERR_ARG, "unknown precision %d", a->prec);
+    if (k_max == 0) return SPH_OK;
+    if (!sel_a || !sel_b || !k_dev) return fail(SPH_ERR_ARG, "sel_a/sel_b/k_dev is NULL");
+    return hip_status(launch_swap(a->prec, *a, sel_a, *b, sel_b, k_dev, k_max, (hipStream_t)stream), "sph_swap");
+}
+
 }  // extern "C"

@@ -1,0 +1,260 @@
+// Periodic particle swapping between two GPUs (Section III.A), the part one
+// GPU computes: the centre of gravity of its particles, each particle's
+// balancing hash towards the other GPU's centre, the selection of the
+// k = min(n+_own, n+_other) particles of largest hash (a stable sort by
+// descending hash, reusing the bucket-sort machinery), and the pairwise
+// exchange of the selected particles between two particle arrays (the
+// single-device stand-in for the send/receive between the GPUs).
+//
+// The balancing hash, with e = Cg_other - Cg_own and M the midpoint: the
+// projection of x - M on e, measured in half distances, scaled to hmax:
+//   t = ((x0 - M0) e0 + (x1 - M1) e1) + (x2 - M2) e2,  ee = |e|^2,
+//   v = hmax (2 t / ee),  hash = t > 0 ? min(ceil(v), hmax) : 0,
+// in IEEE binary64 without contraction, so every particle's integer hash is
+// decided exactly as a plain CPU evaluation of the same expression decides it.
+#include "radix.hpp"
+
+namespace sph {
+
+namespace {
+
+constexpr int kCg = 4;   // sum m x, sum m y, sum m z, sum m
+
+// Sums of one block in a fixed order (wavefront butterfly, then waves in turn).
+__device__ inline void block_sum4(double r[kCg], double *out)
+{
+    __shared__ double sh[kCg][kBlock / kWave];
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+#pragma unroll
+    for (int k = 0; k < kCg; ++k) {
+        double v = r[k];
+#pragma unroll
+        for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_down(v, off, kWave);
+        if (lane == 0) sh[k][wave] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < kCg; ++k) {
+            double v = sh[k][0];
+            for (int w = 1; w < kBlock / kWave; ++w) v += sh[k][w];
+            out[k] = v;
+        }
+    }
+}
+
+template <typename real>
+__global__ __launch_bounds__(kBlock) void k_cg_partial(PV<real> s, double *__restrict__ partials)
+{
+    const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
+    double r[kCg] = {0.0, 0.0, 0.0, 0.0};
+    if (i < s.n) {
+        const double m = (double)s.m[i];
+        r[0] = m * s.x[0][i];
+        r[1] = m * s.x[1][i];
+        r[2] = m * s.x[2][i];
+        r[3] = m;
+    }
+    block_sum4(r, partials + (size_t)blockIdx.x * kDiagPartial);
+}
+
+__global__ __launch_bounds__(kBlock) void k_cg_final(const double *__restrict__ partials, uint32_t nblocks,
+                                                     double *__restrict__ cg)
+{
+    double r[kCg] = {0.0, 0.0, 0.0, 0.0};
+    for (uint32_t b = threadIdx.x; b < nblocks; b += kBlock) {
+#pragma unroll
+        for (int k = 0; k < kCg; ++k) r[k] += partials[(size_t)b * kDiagPartial + k];
+    }
+    __shared__ double out[kCg];
+    block_sum4(r, out);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const double sm = out[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) cg[d] = sm > 0.0 ? out[d] / sm : 0.0;
+        cg[3] = sm;
+    }
+}
+
+__device__ inline uint32_t balance_hash(const double x[3], const double e[3], const double M[3], double ee,
+                                        uint32_t hmax)
+{
+#pragma clang fp contract(off)
+    if (!(ee > 0.0)) return 0u;
+    const double t = ((x[0] - M[0]) * e[0] + (x[1] - M[1]) * e[1]) + (x[2] - M[2]) * e[2];
+    if (!(t > 0.0)) return 0u;
+    const double v = (double)hmax * ((t + t) / ee);
+    return v >= (double)hmax ? hmax : (uint32_t)ceil(v);
+}
+
+// Balancing hash of every particle and the per-block count of positive hashes.
+__global__ __launch_bounds__(kBlock) void k_bhash(uint32_t n, const double *__restrict__ x0,
+                                                  const double *__restrict__ x1, const double *__restrict__ x2,
+                                                  const double *__restrict__ cg_own,
+                                                  const double *__restrict__ cg_other, uint32_t hmax,
+                                                  uint32_t *__restrict__ bhash, uint32_t *__restrict__ counts)
+{
+    double e[3], M[3];
+    {
+#pragma clang fp contract(off)
+        for (int d = 0; d < 3; ++d) {
+            e[d] = cg_other[d] - cg_own[d];
+            M[d] = 0.5 * (cg_own[d] + cg_other[d]);
+        }
+    }
+    double ee;
+    {
+#pragma clang fp contract(off)
+        ee = (e[0] * e[0] + e[1] * e[1]) + e[2] * e[2];
+    }
+    const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
+    uint32_t h = 0;
+    if (i < n) {
+        const double x[3] = {x0[i], x1[i], x2[i]};
+        h = balance_hash(x, e, M, ee, hmax);
+        bhash[i] = h;
+    }
+    // positive hashes of this block (integer: the total is order-independent)
+    __shared__ uint32_t wc[kBlock / kWave];
+    const uint64_t b = __ballot(i < n && h > 0);
+    if ((threadIdx.x & (kWave - 1)) == 0) wc[threadIdx.x / kWave] = (uint32_t)__popcll(b);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t c = 0;
+        for (int w = 0; w < kBlock / kWave; ++w) c += wc[w];
+        counts[blockIdx.x] = c;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_sum_counts(const uint32_t *__restrict__ counts, uint32_t nblocks,
+                                                       uint32_t *__restrict__ total)
+{
+    __shared__ uint32_t sh[kBlock];
+    uint32_t c = 0;
+    for (uint32_t b = threadIdx.x; b < nblocks; b += kBlock) c += counts[b];
+    sh[threadIdx.x] = c;
+    __syncthreads();
+    for (int off = kBlock / 2; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *total = sh[0];
+}
+
+// Sort key hmax - hash (an ascending sort puts the largest hashes first,
+// ties in index order) and the identity index.
+__global__ __launch_bounds__(kBlock) void k_sel_keys(uint32_t n, const uint32_t *__restrict__ bhash, uint32_t hmax,
+                                                     uint32_t *__restrict__ keys, uint32_t *__restrict__ vals)
+{
+    const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t h = bhash[i];
+    keys[i] = hmax - (h < hmax ? h : hmax);
+    vals[i] = i;
+}
+
+// k = min(own, other) (both at most n); the first k sorted indices.
+__global__ __launch_bounds__(kBlock) void k_select(uint32_t n, const uint32_t *__restrict__ sorted_vals,
+                                                   const uint32_t *__restrict__ npos_own,
+                                                   const uint32_t *__restrict__ npos_other,
+                                                   uint32_t *__restrict__ sel, uint32_t *__restrict__ k_out)
+{
+    uint32_t k = *npos_own < *npos_other ? *npos_own : *npos_other;
+    k = k < n ? k : n;
+    const uint32_t t = blockIdx.x * kBlock + threadIdx.x;
+    if (t < k) sel[t] = sorted_vals[t];
+    if (t == 0) *k_out = k;
+}
+
+template <typename T>
+__device__ inline void swap_at(T *a, uint32_t i, T *b, uint32_t j)
+{
+    if (a && b) {
+        const T t = a[i];
+        a[i] = b[j];
+        b[j] = t;
+    }
+}
+
+// Exchange particle sel_a[t] of a with particle sel_b[t] of b, every field.
+template <typename real>
+__global__ __launch_bounds__(kBlock) void k_swap(PV<real> a, const uint32_t *__restrict__ sel_a, PV<real> b,
+                                                 const uint32_t *__restrict__ sel_b,
+                                                 const uint32_t *__restrict__ k_dev, uint32_t k_max)
+{
+    const uint32_t t = blockIdx.x * kBlock + threadIdx.x;
+    uint32_t k = *k_dev;
+    k = k < k_max ? k : k_max;
+    if (t >= k) return;
+    const uint32_t i = sel_a[t], j = sel_b[t];
+    if (i >= a.n || j >= b.n) return;   // out-of-range selections are ignored
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        swap_at(a.x[d], i, b.x[d], j);
+        swap_at(a.off[d], i, b.off[d], j);
+        swap_at(a.v[d], i, b.v[d], j);
+    }
+    swap_at(a.hash, i, b.hash, j);
+    swap_at(a.id, i, b.id, j);
+    swap_at(a.m, i, b.m, j);
+    swap_at(a.w, i, b.w, j);
+    swap_at(a.rho, i, b.rho, j);
+    swap_at(a.p, i, b.p, j);
+    swap_at(a.c, i, b.c, j);
+    swap_at(a.e, i, b.e, j);
+    swap_at(a.E, i, b.E, j);
+#pragma unroll
+    for (int q = 0; q < 6; ++q) swap_at(a.S[q], i, b.S[q], j);
+    swap_at(a.ep, i, b.ep, j);
+}
+
+}  // namespace
+
+hipError_t launch_centroid(int prec, const sph_particles &p, double *cg, const Workspace &ws, hipStream_t s)
+{
+    const uint32_t blocks = div_up(p.n > 0 ? p.n : 1, kBlock);
+    if (prec == SPH_FP64)
+        k_cg_partial<double><<<blocks, kBlock, 0, s>>>(view<double>(p), ws.partials);
+    else
+        k_cg_partial<float><<<blocks, kBlock, 0, s>>>(view<float>(p), ws.partials);
+    k_cg_final<<<1, kBlock, 0, s>>>(ws.partials, blocks, cg);
+    return hipGetLastError();
+}
+
+hipError_t launch_balance_hash(const sph_particles &p, const double *cg_own, const double *cg_other,
+                               uint32_t hmax, uint32_t *bhash, uint32_t *npos, const Workspace &ws, hipStream_t s)
+{
+    const uint32_t blocks = div_up(p.n > 0 ? p.n : 1, kBlock);
+    k_bhash<<<blocks, kBlock, 0, s>>>(p.n, p.x[0], p.x[1], p.x[2], cg_own, cg_other, hmax, bhash, ws.counts);
+    k_sum_counts<<<1, kBlock, 0, s>>>(ws.counts, blocks, npos);
+    return hipGetLastError();
+}
+
+hipError_t launch_balance_select(uint32_t n, const uint32_t *bhash, uint32_t hmax, const uint32_t *npos_own,
+                                 const uint32_t *npos_other, uint32_t *sel, uint32_t *k_out, const Workspace &ws,
+                                 hipStream_t s)
+{
+    const uint32_t blocks = div_up(n > 0 ? n : 1, kBlock);
+    int cur = 0;
+    if (n > 0) {
+        k_sel_keys<<<blocks, kBlock, 0, s>>>(n, bhash, hmax, ws.keys[0], ws.vals[0]);
+        cur = radix_sort(ws, n, hmax + 1, s);
+    }
+    k_select<<<blocks, kBlock, 0, s>>>(n, ws.vals[cur], npos_own, npos_other, sel, k_out);
+    return hipGetLastError();
+}
+
+hipError_t launch_swap(int prec, const sph_particles &a, const uint32_t *sel_a, const sph_particles &b,
+                       const uint32_t *sel_b, const uint32_t *k_dev, uint32_t k_max, hipStream_t s)
+{
+    if (k_max == 0) return hipSuccess;
+    const uint32_t blocks = div_up(k_max, kBlock);
+    if (prec == SPH_FP64)
+        k_swap<double><<<blocks, kBlock, 0, s>>>(view<double>(a), sel_a, view<double>(b), sel_b, k_dev, k_max);
+    else
+        k_swap<float><<<blocks, kBlock, 0, s>>>(view<float>(a), sel_a, view<float>(b), sel_b, k_dev, k_max);
+    return hipGetLastError();
+}
+
+}  // namespace sph

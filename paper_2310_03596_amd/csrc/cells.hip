@@ -1,16 +1,8 @@
 // Bucket hashing, stable radix sort, reorder, bucket table (Section I and
 // step a of Section II), communication hash and boundary compaction (step c)
-// and the boundary payload packing for step d.
-//
-// The sort is a least-significant-digit radix sort over a (hash, index)
-// pair, with digits of 8 to 10 bits chosen so that the key takes as few
-// passes as possible (two for keys of up to 20 bits).  Each pass: (1)
-// per-tile digit histograms in LDS, (2) one workgroup per digit scans that
-// digit's counts over tiles, (3) each tile ranks its keys stably with
-// wavefront ballots (one ballot per digit bit gives every lane the mask of
-// lanes holding the same digit; popcount of the lanes below gives the rank
-// inside the wavefront) and scatters.
-#include "common.hpp"
+// and the boundary payload packing for step d.  The sort itself is in
+// radix.hpp.
+#include "radix.hpp"
 
 namespace sph {
 
@@ -36,160 +28,6 @@ __global__ __launch_bounds__(kBlock) void k_hash(Grid g, uint32_t n, const doubl
     int cz = cell_coord(x2[i], g.o[2], g.L, g.nz);
     keys[i] = (uint32_t)cx + (uint32_t)g.nx * ((uint32_t)cy + (uint32_t)g.ny * (uint32_t)cz);
     vals[i] = i;
-}
-
-__device__ inline uint32_t wave_incl_scan(uint32_t v)
-{
-    int lane = threadIdx.x & (kWave - 1);
-#pragma unroll
-    for (int off = 1; off < kWave; off <<= 1) {
-        uint32_t t = __shfl_up(v, off, kWave);
-        if (lane >= off) v += t;
-    }
-    return v;
-}
-
-// Exclusive scan over the 256 threads of a block; every thread gets `total`.
-__device__ inline uint32_t block_excl_scan(uint32_t v, uint32_t &total)
-{
-    __shared__ uint32_t wsum[kBlock / kWave];
-    int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
-    uint32_t inc = wave_incl_scan(v);
-    if (lane == kWave - 1) wsum[wave] = inc;
-    __syncthreads();
-    uint32_t before = 0, tot = 0;
-#pragma unroll
-    for (int w = 0; w < kBlock / kWave; ++w) {
-        uint32_t s = wsum[w];
-        before += (w < wave) ? s : 0u;
-        tot += s;
-    }
-    __syncthreads();
-    total = tot;
-    return before + inc - v;
-}
-
-template <int D>
-__global__ __launch_bounds__(kBlock) void k_upsweep(const uint32_t *__restrict__ keys, uint32_t n, int shift,
-                                                    uint32_t *__restrict__ hist, uint32_t tiles)
-{
-    constexpr int BINS = 1 << D;
-    __shared__ uint32_t h[BINS];
-    for (int b = threadIdx.x; b < BINS; b += kBlock) h[b] = 0;
-    __syncthreads();
-    uint32_t base = blockIdx.x * kSortTile;
-#pragma unroll
-    for (int it = 0; it < kSortItems; ++it) {
-        uint32_t e = base + it * kBlock + threadIdx.x;
-        if (e < n) atomicAdd(&h[(keys[e] >> shift) & (BINS - 1)], 1u);
-    }
-    __syncthreads();
-    for (int b = threadIdx.x; b < BINS; b += kBlock) hist[(size_t)b * tiles + blockIdx.x] = h[b];
-}
-
-// One workgroup per digit: exclusive scan of that digit's tile counts.
-__global__ __launch_bounds__(kBlock) void k_scan_digit(uint32_t *__restrict__ hist, uint32_t tiles,
-                                                       uint32_t *__restrict__ totals)
-{
-    uint32_t *row = hist + (size_t)blockIdx.x * tiles;
-    uint32_t run = 0;
-    for (uint32_t b0 = 0; b0 < tiles; b0 += kBlock) {
-        uint32_t b = b0 + threadIdx.x;
-        uint32_t v = b < tiles ? row[b] : 0u;
-        uint32_t tot;
-        uint32_t ex = block_excl_scan(v, tot);
-        if (b < tiles) row[b] = run + ex;
-        run += tot;
-    }
-    if (threadIdx.x == 0) totals[blockIdx.x] = run;
-}
-
-template <int D>
-__global__ __launch_bounds__(kBlock) void k_downsweep(const uint32_t *__restrict__ kin,
-                                                      const uint32_t *__restrict__ vin,
-                                                      uint32_t *__restrict__ kout,
-                                                      uint32_t *__restrict__ vout, uint32_t n, int shift,
-                                                      const uint32_t *__restrict__ hist, uint32_t tiles,
-                                                      const uint32_t *__restrict__ totals)
-{
-    constexpr int BINS = 1 << D;
-    constexpr int PT = BINS / kBlock;   // digits per thread in the bookkeeping
-    static_assert(BINS % kBlock == 0, "digits must cover the block");
-    constexpr int NW = kBlock / kWave;
-    __shared__ uint32_t dbase[BINS];
-    __shared__ uint32_t run[BINS];
-    __shared__ uint32_t cnt[NW][BINS];
-    const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
-    // digit bases of this tile: exclusive scan of the digit totals (each
-    // thread holds PT consecutive digits) plus the tile's offset in its digit
-    uint32_t loc[PT];
-    uint32_t sum = 0;
-#pragma unroll
-    for (int k = 0; k < PT; ++k) {
-        loc[k] = sum;
-        sum += totals[tid * PT + k];
-    }
-    uint32_t tot;
-    const uint32_t ex = block_excl_scan(sum, tot);
-#pragma unroll
-    for (int k = 0; k < PT; ++k) {
-        const int d = tid * PT + k;
-        dbase[d] = ex + loc[k] + hist[(size_t)d * tiles + blockIdx.x];
-        run[d] = 0;
-#pragma unroll
-        for (int w = 0; w < NW; ++w) cnt[w][d] = 0;
-    }
-    __syncthreads();
-    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    const uint32_t base = blockIdx.x * kSortTile;
-    for (int it = 0; it < kSortItems; ++it) {
-        uint32_t e = base + it * kBlock + tid;
-        bool valid = e < n;
-        uint32_t key = valid ? kin[e] : 0u;
-        uint32_t val = valid ? vin[e] : 0u;
-        uint32_t d = (key >> shift) & (BINS - 1);
-        uint64_t mask = __ballot(valid);
-#pragma unroll
-        for (int b = 0; b < D; ++b) {
-            bool bit = (d >> b) & 1u;
-            uint64_t bm = __ballot(bit);
-            mask &= bit ? bm : ~bm;
-        }
-        uint32_t rank = (uint32_t)__popcll(mask & below);
-        bool leader = valid && ((mask >> lane) == 1ull);
-        if (leader) cnt[wave][d] = (uint32_t)__popcll(mask);
-        __syncthreads();
-        if (valid) {
-            uint32_t pre = run[d];
-            for (int w = 0; w < wave; ++w) pre += cnt[w][d];
-            uint32_t pos = dbase[d] + pre + rank;
-            kout[pos] = key;
-            vout[pos] = val;
-        }
-        __syncthreads();
-#pragma unroll
-        for (int k = 0; k < PT; ++k) {
-            const int b = tid * PT + k;
-            uint32_t add = 0;
-#pragma unroll
-            for (int w = 0; w < NW; ++w) {
-                add += cnt[w][b];
-                cnt[w][b] = 0;
-            }
-            run[b] += add;
-        }
-        __syncthreads();
-    }
-}
-
-// One LSD pass with D-bit digits starting at bit `shift`.
-template <int D>
-void sort_pass(const Workspace &ws, uint32_t n, uint32_t tiles, int shift, int cur, hipStream_t s)
-{
-    k_upsweep<D><<<tiles, kBlock, 0, s>>>(ws.keys[cur], n, shift, ws.hist, tiles);
-    k_scan_digit<<<1u << D, kBlock, 0, s>>>(ws.hist, tiles, ws.totals);
-    k_downsweep<D><<<tiles, kBlock, 0, s>>>(ws.keys[cur], ws.vals[cur], ws.keys[cur ^ 1], ws.vals[cur ^ 1], n,
-                                            shift, ws.hist, tiles, ws.totals);
 }
 
 // Float offset from the bucket corner, ((x - o) - c L) evaluated in IEEE
@@ -363,13 +201,6 @@ __global__ __launch_bounds__(kBlock) void k_pack(PV<real> in, const uint32_t *__
     if (out.ep) out.ep[k] = in.ep[s];
 }
 
-int key_bits(uint32_t ncells)
-{
-    int b = 0;
-    while (b < 32 && (uint64_t(1) << b) < ncells) ++b;
-    return b;
-}
-
 }  // namespace
 
 hipError_t launch_build_cells(const Grid &g, int prec, const sph_particles &in, const sph_particles &out,
@@ -379,23 +210,7 @@ hipError_t launch_build_cells(const Grid &g, int prec, const sph_particles &in, 
     uint32_t blocks = div_up(n, kBlock);
     if (n > 0) {
         k_hash<<<blocks, kBlock, 0, s>>>(g, n, in.x[0], in.x[1], in.x[2], ws.keys[0], ws.vals[0]);
-        // as few passes as digits of at most 10 bits allow, each of 8 to 10 bits
-        const int bits = key_bits(g.ncells);
-        const int passes = bits > 0 ? (bits + kMaxRadixBits - 1) / kMaxRadixBits : 1;
-        int dbits = (bits + passes - 1) / passes;
-        dbits = dbits < 8 ? 8 : dbits;
-        const uint32_t tiles = div_up(n, kSortTile);
-        int cur = 0;
-        for (int ps = 0; ps < passes; ++ps) {
-            const int shift = ps * dbits;
-            if (dbits == 8)
-                sort_pass<8>(ws, n, tiles, shift, cur, s);
-            else if (dbits == 9)
-                sort_pass<9>(ws, n, tiles, shift, cur, s);
-            else
-                sort_pass<10>(ws, n, tiles, shift, cur, s);
-            cur ^= 1;
-        }
+        const int cur = radix_sort(ws, n, g.ncells, s);
         if (prec == SPH_FP64)
             k_gather<double><<<blocks, kBlock, 0, s>>>(g, view<double>(in), view<double>(out), ws.keys[cur],
                                                        ws.vals[cur], perm, 0);

@@ -252,6 +252,14 @@ hipError_t launch_integrate_adjoint(const Params &P, int prec, int stage, const 
                                     const sph_rates &r, const double *dt, const sph_adjoint &bar,
                                     const sph_rates &rbar, double *pbar, const Workspace &ws,
                                     hipStream_t s);
+hipError_t launch_centroid(int prec, const sph_particles &p, double *cg, const Workspace &ws, hipStream_t s);
+hipError_t launch_balance_hash(const sph_particles &p, const double *cg_own, const double *cg_other,
+                               uint32_t hmax, uint32_t *bhash, uint32_t *npos, const Workspace &ws, hipStream_t s);
+hipError_t launch_balance_select(uint32_t n, const uint32_t *bhash, uint32_t hmax, const uint32_t *npos_own,
+                                 const uint32_t *npos_other, uint32_t *sel, uint32_t *k_out, const Workspace &ws,
+                                 hipStream_t s);
+hipError_t launch_swap(int prec, const sph_particles &a, const uint32_t *sel_a, const sph_particles &b,
+                       const uint32_t *sel_b, const uint32_t *k_dev, uint32_t k_max, hipStream_t s);
 hipError_t launch_permute_adjoint(int prec, uint32_t n, const uint32_t *perm, const sph_adjoint &in,
                                   const sph_adjoint &out, hipStream_t s);
 

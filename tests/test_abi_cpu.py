@@ -186,3 +186,25 @@ def test_zero_particles_is_a_noop():
     out.n = 5
     assert lib.sph_pack_boundary(C.byref(p), None, None, C.byref(L.SphParticles()), None) == L.SPH_OK
     assert lib.sph_permute_adjoint(0, 0, None, None, None, None) == L.SPH_OK
+
+
+def test_balancing_entry_points_reject_bad_arguments():
+    lib = L.load()
+    ARG, WS = L.SPH_ERR_ARG, L.SPH_ERR_WORKSPACE
+    p = _particles(10)
+    n_ws = L.sph_workspace_size(_grid(), 10, 0, 0)
+    assert lib.sph_centroid(None, FAKE, FAKE, n_ws, None) == ARG
+    assert lib.sph_centroid(C.byref(p), None, FAKE, n_ws, None) == ARG
+    assert lib.sph_centroid(C.byref(p), FAKE, FAKE, 64, None) == WS and "workspace" in _last()
+    for hmax in (0, 1 << 20):
+        assert lib.sph_balance_hash(C.byref(p), FAKE, FAKE, hmax, FAKE, FAKE, FAKE, n_ws, None) == ARG
+        assert "hmax" in _last()
+    assert lib.sph_balance_hash(C.byref(p), None, FAKE, 1000, FAKE, FAKE, FAKE, n_ws, None) == ARG
+    assert lib.sph_balance_hash(C.byref(p), FAKE, FAKE, 1000, None, FAKE, FAKE, n_ws, None) == ARG
+    assert lib.sph_balance_select(10, FAKE, 1000, None, FAKE, FAKE, FAKE, FAKE, n_ws, None) == ARG
+    assert lib.sph_balance_select(10, None, 1000, FAKE, FAKE, FAKE, FAKE, FAKE, n_ws, None) == ARG
+    assert lib.sph_balance_select(10, FAKE, 1000, FAKE, FAKE, FAKE, FAKE, None, n_ws, None) == WS
+    q = _particles(10, prec=L.SPH_FP32_SPLIT)
+    assert lib.sph_swap(C.byref(p), FAKE, C.byref(q), FAKE, FAKE, 10, None) == ARG and "precision" in _last()
+    assert lib.sph_swap(C.byref(p), None, C.byref(p), FAKE, FAKE, 10, None) == ARG
+    assert lib.sph_swap(C.byref(p), None, C.byref(p), None, None, 0, None) == L.SPH_OK   # nothing to do
