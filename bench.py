@@ -183,6 +183,42 @@ def share_leg(reps=5):
     return out
 
 
+def balance_leg(reps=3):
+    """One round of the swap heuristic (Section III.A) between an 8M and a 2M
+    particle set (the mixed share and its partner), FP32 split: both centres,
+    both balancing hashes, both selections, the swap.  Fresh sets each
+    repetition (a round changes them); the first round is the warm-up."""
+    import torch
+
+    import sph_synth as S
+    from paper_2310_03596_amd.balance import BalancePair
+
+    a, b = S.c4_share("mixed")
+    times, ks = [], []
+    for r in range(reps + 1):
+        bp = BalancePair(a, b, 1)
+        torch.cuda.synchronize()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
+        ev[0].record()
+        bp.centroids()
+        ev[1].record()
+        bp.hashes()
+        ev[2].record()
+        bp.selections()
+        ev[3].record()
+        bp.swap()
+        ev[4].record()
+        torch.cuda.synchronize()
+        if r > 0:
+            times.append([ev[q].elapsed_time(ev[q + 1]) for q in range(4)])
+            ks.append(int(bp.k.cpu()[0]))
+        del bp
+    t = [sum(x[q] for x in times) / len(times) for q in range(4)]
+    tot = sum(t)
+    return {"particles": a.n + b.n, "k_swapped": ks[0], "round_ms": tot, "centroids_ms": t[0], "hashes_ms": t[1],
+            "selections_ms": t[2], "swap_ms": t[3], "particles_per_s": (a.n + b.n) / (tot * 1e-3)}
+
+
 def cpu_leg(wl, budget_s):
     """FP64 oracle from the initial state for a bounded number of steps, then
     both GPU forms on the same dt schedule; per-field error by particle id."""
@@ -286,6 +322,7 @@ def main():
         out["adjoint_forward_ratio"] = out["adjoint"]["fp32_split"]["adjoint_over_forward"]
     if not args.no_share:
         out["share_pass"] = share_leg()
+        out["balance_round"] = balance_leg()
     if args.calib_copy_mb > 0:
         nbytes = args.calib_copy_mb << 20
         src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
