@@ -91,6 +91,9 @@ bool make_params(const sph_params *sp, const sph_grid *sg, Params &P)
     P.Fc = (1.0 / (M_PI * sp->h * sp->h * sp->h)) / sp->h;
     P.B = sp->material == SPH_FLUID_TAIT ? sp->rho0 * sp->c0 * sp->c0 / sp->gamma : 0.0;
     P.c_solid = sp->material == SPH_SOLID_J2 ? sqrt((sp->K + 4.0 * sp->G / 3.0) / sp->rho0) : 0.0;
+    P.gamma_odd = 0;
+    for (int k = 1; k < 16; k += 2)
+        if (sp->gamma == (double)k) P.gamma_odd = k;
     return true;
 }
 

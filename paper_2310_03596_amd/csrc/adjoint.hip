@@ -88,8 +88,10 @@ __global__ __launch_bounds__(kBlock) void k_eos_adj(Params P, PV<real> s, AV<rea
         const double m = (double)s.m[i], w = (double)s.w[i];
         const double rho = m / w;
         const double sr = rho / P.rho0;
-        const double p = P.B * (pow(sr, P.gamma) - 1.0);
-        const double c = P.c0 * pow(sr, 0.5 * (P.gamma - 1.0));
+        double s_gam, s_half;
+        tait_powers<real>(P, sr, s_gam, s_half);
+        const double p = P.B * (s_gam - 1.0);
+        const double c = P.c0 * s_half;
         const double bp = (double)bar.p[i], bc = (double)bar.c[i], be = (double)bar.e[i];
         // p' = c^2, c' = c (gamma - 1) / (2 rho); p and c scale as c0^2 and c0
         const double brho = (double)bar.rho[i] + bp * c * c + bc * c * (P.gamma - 1.0) / (2.0 * rho);

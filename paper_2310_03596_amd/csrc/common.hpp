@@ -50,7 +50,37 @@ struct Params {
     double Fc;            // 1 / (pi h^4): F = Fc f(q)
     double B;             // Tait stiffness rho0 c0^2 / gamma
     double c_solid;       // solid sound speed
+    int gamma_odd;        // gamma when it is an odd integer in [1, 15] (powers by products), else 0
 };
+
+// s^k for 0 <= k < 16 by repeated squaring (k is uniform across the launch).
+__device__ inline double ipow(double s, int k)
+{
+    double r = 1.0, b = s;
+    for (; k > 0; k >>= 1) {
+        if (k & 1) r *= b;
+        b *= b;
+    }
+    return r;
+}
+
+// Tait EOS factors s^gamma and s^((gamma - 1) / 2), s = rho / rho0.  The
+// FP32-split form (real = float) takes products for an odd integer gamma:
+// within a few ulp of pow in FP64, invisible once stored as float, and far
+// cheaper.  The FP64 form keeps pow, the plain definition, so that its
+// near-zero differences (p = B (s^gamma - 1) with s close to 1) round as
+// the oracle's do.
+template <typename real>
+__device__ inline void tait_powers(const Params &P, double s, double &sg, double &sh)
+{
+    if (sizeof(real) == 4 && P.gamma_odd) {
+        sh = ipow(s, (P.gamma_odd - 1) / 2);
+        sg = sh * sh * s;
+    } else {
+        sg = pow(s, P.gamma);
+        sh = pow(s, 0.5 * (P.gamma - 1.0));
+    }
+}
 
 // Particle array with typed pointers.  real = float (FP32 split) or double.
 template <typename real>

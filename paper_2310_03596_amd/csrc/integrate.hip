@@ -13,12 +13,14 @@ namespace sph {
 
 namespace {
 
+template <typename real>
 __device__ inline void eos(const Params &P, double rho, double &p, double &c)
 {
     if (P.material == SPH_FLUID_TAIT) {
-        double s = rho / P.rho0;
-        p = P.B * (pow(s, P.gamma) - 1.0);
-        c = P.c0 * pow(s, 0.5 * (P.gamma - 1.0));
+        double sg, sh;
+        tait_powers<real>(P, rho / P.rho0, sg, sh);
+        p = P.B * (sg - 1.0);
+        c = P.c0 * sh;
     } else {
         p = P.K * (rho / P.rho0 - 1.0);
         c = P.c_solid;
@@ -58,7 +60,7 @@ __device__ inline void finish(const Params &P, const PV<real> &s, uint32_t i, do
 {
     double rho = m / w;
     double p, c;
-    eos(P, rho, p, c);
+    eos<real>(P, rho, p, c);
     double v2 = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
     s.rho[i] = (real)rho;
     s.p[i] = (real)p;
