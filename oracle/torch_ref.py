@@ -100,6 +100,29 @@ def gradient(wl, c0, dt, nsteps):
     return float(J.detach()), gv.numpy(), float(gc)
 
 
+def z_displacement_after(x0, v0, m0, w0, e0, P, c0, dt, nsteps, tag):
+    """J = mean over the tagged rows of (z after nsteps - z0)."""
+    x, v, m, w = x0, v0, m0, w0
+    E = e0 + 0.5 * (v0 * v0).sum(1)
+    for _ in range(nsteps):
+        x, v, m, w, E = step(x, v, m, w, E, P, c0, dt)
+    return (x[tag, 2] - x0[tag, 2]).mean()
+
+
+def gradient_z_displacement(wl, c0, dt, nsteps, tag):
+    """(J, dJ/dv0 (n,3), dJ/dc0) of the tagged mean z-displacement, float64."""
+    x0 = torch.tensor(wl.x, dtype=torch.float64)
+    v0 = torch.tensor(wl.v, dtype=torch.float64, requires_grad=True)
+    m0 = torch.tensor(wl.m, dtype=torch.float64)
+    w0 = torch.tensor(wl.omega, dtype=torch.float64)
+    e0 = torch.tensor(wl.E - 0.5 * (wl.v * wl.v).sum(1), dtype=torch.float64)
+    c = torch.tensor(float(c0), dtype=torch.float64, requires_grad=True)
+    t = torch.as_tensor(tag, dtype=torch.int64)
+    J = z_displacement_after(x0, v0, m0, w0, e0, wl.params, c, dt, nsteps, t)
+    gv, gc = torch.autograd.grad(J, (v0, c))
+    return float(J.detach()), gv.numpy(), float(gc)
+
+
 def final_state(wl, c0, dt, nsteps):
     """State after nsteps (id order) as numpy arrays."""
     with torch.no_grad():

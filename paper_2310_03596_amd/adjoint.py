@@ -1,9 +1,13 @@
 """Checkpointed hand adjoint of a fluid rollout, behind torch.autograd.
 
-Objective: the kinetic energy J = sum m |v|^2 / 2 after `nsteps` fixed-dt
-steps of the fluid path (hash + sort + FORCE pass + update; free boundaries,
-no gravity).  Differentiable inputs: the initial velocities (at fixed
-specific internal energy, so E0 = e0 + |v0|^2 / 2) and the sound speed c0.
+Objectives, after `nsteps` fixed-dt steps of the fluid path (hash + sort +
+FORCE pass + update; free boundaries, no gravity): the kinetic energy
+J = sum m |v|^2 / 2, or the mean displacement along z of a tagged set of
+particles (`tag_ids`), J = mean_{i in tag} (z_i(T) - z_i(0)).  Differentiable
+inputs: the initial velocities (at fixed specific internal energy, so
+E0 = e0 + |v0|^2 / 2) and the sound speed c0.  The objective's value and its
+seed cotangent are the caller's side and use plain tensor operations; every
+step of the path, forward and reverse, runs in libsph.
 
 Forward keeps a copy of the whole particle state every `ckpt` steps.
 Backward walks the segments in reverse: it restores a segment's checkpoint,
@@ -71,10 +75,11 @@ class Cotangent:
 class KineticEnergyRollout:
     """Forward rollout with checkpoints, and its reverse pass."""
 
-    def __init__(self, wl, prec: int, nsteps: int, ckpt: int, dt: float, device="cuda"):
+    def __init__(self, wl, prec: int, nsteps: int, ckpt: int, dt: float, device="cuda", tag_ids=None):
         self.wl, self.prec, self.nsteps, self.ckpt, self.dt = wl, prec, nsteps, max(1, ckpt), dt
         self.device = device
         self.e0 = wl.E - 0.5 * np.einsum("ij,ij->i", wl.v, wl.v)   # specific internal energy, held fixed
+        self.tag = None if tag_ids is None else np.unique(np.asarray(tag_ids, dtype=np.int64))
 
     def _workload(self, v0: np.ndarray, c0: float):
         w = copy.copy(self.wl)
@@ -93,7 +98,14 @@ class KineticEnergyRollout:
             sim.step()
         torch.cuda.synchronize()
         self.final = sim.A
-        return float(sim.diagnostics()[6])
+        if self.tag is None:
+            return float(sim.diagnostics()[6])
+        # mean z-displacement of the tagged particles (by id)
+        ids = sim.A.id.cpu().numpy().astype(np.int64)
+        z = sim.A.x[2].cpu().numpy()
+        zt = z[np.isin(ids, self.tag)]
+        z0 = self.wl.x[np.isin(np.asarray(self.wl.id, dtype=np.int64), self.tag), 2]
+        return float(zt.mean() - z0.mean())
 
     def backward(self, gJ: float):
         sim = self.sim
@@ -103,9 +115,15 @@ class KineticEnergyRollout:
         bar = Cotangent(n, prec, dev)
         tmp = Cotangent(n, prec, dev)
         # dJ/d(final state): J = sum m |v|^2 / 2
-        v = self.final.v.double()
-        bar.v.copy_((gJ * self.final.m.double() * v).to(real))
-        bar.m.copy_((gJ * 0.5 * (v * v).sum(0)).to(real))
+        if self.tag is None:
+            v = self.final.v.double()
+            bar.v.copy_((gJ * self.final.m.double() * v).to(real))
+            bar.m.copy_((gJ * 0.5 * (v * v).sum(0)).to(real))
+        else:
+            ids = self.final.id.to(torch.int64)
+            tag = torch.as_tensor(self.tag, device=ids.device)
+            hit = torch.isin(ids, tag)
+            bar.x[2].copy_((hit.to(torch.float64) * (gJ / float(self.tag.size))).to(real))
         c0bar = torch.zeros(1, dtype=torch.float64, device=dev)
         rbar = Rates(n, prec, False, dev)
         ws_adj_bytes = L.sph_workspace_size(sim.grid, n, prec, L.SPH_SOLID_J2)

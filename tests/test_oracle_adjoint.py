@@ -52,3 +52,31 @@ def test_reverse_mode_matches_central_differences():
     fdc = (Jof(w.v, c0 + eps) - Jof(w.v, c0 - eps)) / (2 * eps)
     assert fdc == pytest.approx(gc, rel=1e-6)
     assert gc != 0.0
+
+
+def test_displacement_gradient_matches_central_differences():
+    w = small_box(n_side=5, seed=73)
+    dt, nsteps, c0 = 1.4e-5, 4, 50.0
+    tag = np.flatnonzero(np.linalg.norm(w.x - w.x.mean(0), axis=1) < 3.0e-3)
+    J, gv, gc = torch_ref.gradient_z_displacement(w, c0, dt, nsteps, tag)
+    x0, m0, w0 = torch.tensor(w.x), torch.tensor(w.m), torch.tensor(w.omega)
+    e0 = torch.tensor(w.E - 0.5 * (w.v * w.v).sum(1))
+    t = torch.as_tensor(tag)
+
+    def Jof(v, c):
+        with torch.no_grad():
+            return float(torch_ref.z_displacement_after(x0, torch.tensor(v), m0, w0, e0, w.params, c, dt, nsteps, t))
+
+    assert abs(J - Jof(w.v, c0)) < 1e-18
+    rng = np.random.default_rng(74)
+    for _ in range(3):
+        d = rng.normal(size=w.v.shape)
+        eps = 1e-5
+        fd = (Jof(w.v + eps * d, c0) - Jof(w.v - eps * d, c0)) / (2 * eps)
+        assert fd == pytest.approx(float((gv * d).sum()), rel=1e-7)
+    # displacement of a tagged set grows with its own initial z-velocity:
+    # dJ/dv0_z is positive on the tag (about nsteps dt / n_tag) and small elsewhere
+    assert gv[tag, 2].min() > 0.5 * nsteps * dt / tag.size
+    eps = 1e-4 * c0
+    fdc = (Jof(w.v, c0 + eps) - Jof(w.v, c0 - eps)) / (2 * eps)
+    assert fdc == pytest.approx(gc, rel=1e-5, abs=1e-14)
