@@ -121,6 +121,35 @@ def time_form(wl, prec, steps, warmup):
     }
 
 
+def other_workloads_leg():
+    """Step throughput of the 8,000-particle cube (10 steps) and the
+    3,987,920-particle elastic-plastic cylinder (two interaction loops per
+    step: GRADIENT, stress stage, FORCE; 20 steps) in both forms."""
+    import torch
+
+    import sph_synth as S
+    from paper_2310_03596_amd.sim import Sim
+
+    out = {}
+    for name, wl, steps in (("cube_8000", S.c1_cube(), 10), ("cylinder_3987920", S.c3_cylinder(), 20)):
+        out[name] = {}
+        for prec, tag in ((1, "fp32_split"), (0, "fp64")):
+            sim = Sim(wl, prec)
+            for _ in range(2):
+                sim.step()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                sim.step()
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            out[name][tag] = {"steps": steps, "ms_per_step": 1e3 * wall / steps,
+                              "particle_updates_per_s": wl.n * steps / wall}
+            del sim
+        torch.cuda.empty_cache()
+    return out
+
+
 def adjoint_leg(prec, reps=2):
     """Adjoint/forward time ratio on the 250,047-particle box: 50 fixed-dt
     steps with checkpoints every 10 (forward), then the reverse pass
@@ -322,6 +351,8 @@ def main():
                             "force_tflops": res[0]["force_tflops"],
                             "frac_of_fp64_peak": res[0]["force_tflops"] / PEAK_TFLOPS[0]}
         out["fp32_over_fp64"] = res[1]["value"] / res[0]["value"]
+    if not args.no_share:
+        out["other_workloads"] = other_workloads_leg()
     if not args.no_adjoint:
         out["adjoint"] = {"fp32_split": adjoint_leg(1), "fp64": adjoint_leg(0)}
         out["adjoint_forward_ratio"] = out["adjoint"]["fp32_split"]["adjoint_over_forward"]

@@ -43,17 +43,21 @@ __device__ inline void block_sum4(double r[kCg], double *out)
     }
 }
 
+constexpr uint32_t kCgBlocks = 1024;   // fixed partial count: the sum order depends on n only
+
+// Each thread sums the particles i = t, t + T, t + 2T, ... (T = grid threads)
+// in that order, then the block folds its threads in a fixed order.
 template <typename real>
 __global__ __launch_bounds__(kBlock) void k_cg_partial(PV<real> s, double *__restrict__ partials)
 {
-    const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
     double r[kCg] = {0.0, 0.0, 0.0, 0.0};
-    if (i < s.n) {
+    const uint32_t stride = gridDim.x * kBlock;
+    for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < s.n; i += stride) {
         const double m = (double)s.m[i];
-        r[0] = m * s.x[0][i];
-        r[1] = m * s.x[1][i];
-        r[2] = m * s.x[2][i];
-        r[3] = m;
+        r[0] += m * s.x[0][i];
+        r[1] += m * s.x[1][i];
+        r[2] += m * s.x[2][i];
+        r[3] += m;
     }
     block_sum4(r, partials + (size_t)blockIdx.x * kDiagPartial);
 }
@@ -213,7 +217,8 @@ __global__ __launch_bounds__(kBlock) void k_swap(PV<real> a, const uint32_t *__r
 
 hipError_t launch_centroid(int prec, const sph_particles &p, double *cg, const Workspace &ws, hipStream_t s)
 {
-    const uint32_t blocks = div_up(p.n > 0 ? p.n : 1, kBlock);
+    uint32_t blocks = div_up(p.n > 0 ? p.n : 1, kBlock);
+    blocks = blocks < kCgBlocks ? blocks : kCgBlocks;   // the workspace holds one record per kBlock particles
     if (prec == SPH_FP64)
         k_cg_partial<double><<<blocks, kBlock, 0, s>>>(view<double>(p), ws.partials);
     else

@@ -137,12 +137,27 @@ __global__ __launch_bounds__(kBlock) void k_eos(Params P, PV<real> s, double *__
 __global__ __launch_bounds__(kBlock) void k_diag_final(const double *__restrict__ partials, uint32_t nblocks,
                                                        double cfl_h, double *__restrict__ diag)
 {
-    double rec[kDiag] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    for (uint32_t b = threadIdx.x; b < nblocks; b += kBlock) {
-        const double *q = partials + (size_t)b * kDiagPartial;
-        rec[0] = fmax(rec[0], q[0]);
+    // four independent chains per thread (records b, b + kBlock, ...), so
+    // their loads overlap; folded in a fixed order
+    double acc[4][kDiag] = {};
+    for (uint32_t b0 = threadIdx.x; b0 < nblocks; b0 += 4 * kBlock) {
 #pragma unroll
-        for (int k = 1; k < kDiag; ++k) rec[k] += q[k];
+        for (int u = 0; u < 4; ++u) {
+            const uint32_t b = b0 + (uint32_t)u * kBlock;
+            if (b < nblocks) {
+                const double *q = partials + (size_t)b * kDiagPartial;
+                acc[u][0] = fmax(acc[u][0], q[0]);
+#pragma unroll
+                for (int k = 1; k < kDiag; ++k) acc[u][k] += q[k];
+            }
+        }
+    }
+    double rec[kDiag];
+#pragma unroll
+    for (int k = 0; k < kDiag; ++k) {
+        rec[k] = acc[0][k];
+#pragma unroll
+        for (int u = 1; u < 4; ++u) rec[k] = k == 0 ? fmax(rec[k], acc[u][k]) : rec[k] + acc[u][k];
     }
     __shared__ double out[kDiagPartial];
     block_reduce_record(rec, out);
