@@ -220,9 +220,14 @@ void k_pairs(Params P, Grid g, PV<real> tg, const uint32_t *__restrict__ tidx, c
     // at the end of that page's hits
     __shared__ uint16_t marks[kMaxWin][kWaves / 2][kWave][2];
     __shared__ v4 stage[kWaves][kPage + kSub];    // a page, then far sentinels
-    __shared__ uint32_t wbase[kWaves][kMaxWin];   // first source index of each staged page
-    __shared__ real wdy[kWaves][kMaxWin];         // (c_j - c_i) L in y and z of the page's row
-    __shared__ real wdz[kWaves][kMaxWin];
+    // per staged page: its first source index and (c_j - c_i) L in y and z of
+    // its row (split form; the FP64 form works on absolute positions), side by
+    // side so that one address serves the three reads
+    struct alignas(16) Win {
+        uint32_t base;
+        float dy, dz, pad;
+    };
+    __shared__ Win win[kWaves][kMaxWin];
 
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
     const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);   // neighbouring tiles share sources
@@ -237,11 +242,7 @@ void k_pairs(Params P, Grid g, PV<real> tg, const uint32_t *__restrict__ tidx, c
     const bool valid = t < nt;
     const uint32_t i = valid ? (tidx ? tidx[t] : t) : 0u;
 
-    PairK<real> K;
-    K.hinv = (real)P.hinv;
-    K.Fc = (real)P.Fc;
-    K.beta = (real)P.beta;
-    K.half_beta = (real)(0.5 * P.beta);
+    const PairK<real> K = make_pair_k<real>(P);
     const real R2 = (real)P.R2;
 
     const uint32_t h = valid ? tg.hash[i] : 0u;
@@ -306,9 +307,10 @@ void k_pairs(Params P, Grid g, PV<real> tg, const uint32_t *__restrict__ tidx, c
         const uint32_t m = marks[mk][wave >> 1][lane][wave & 1];
         nb = (int)(m & 0xFFu);
         const uint32_t slot = m >> 8;
-        const uint32_t jj = wbase[wave][slot] + (uint32_t)hits[s][lane][wave];
-        q.qy = wdy[wave][slot];
-        q.qz = wdz[wave][slot];
+        const Win &wn = win[wave][slot];
+        const uint32_t jj = wn.base + (uint32_t)hits[s][lane][wave];
+        q.qy = SPLIT ? (real)wn.dy : real(0);
+        q.qz = SPLIT ? (real)wn.dz : real(0);
         // a 32-bit byte offset from each array's base (sources are fewer than
         // 2^28 FP32 / 2^27 FP64 records), so the loads take the scalar-base form
         const uint32_t ob = jj * (uint32_t)sizeof(v4);
@@ -478,9 +480,7 @@ void k_pairs(Params P, Grid g, PV<real> tg, const uint32_t *__restrict__ tidx, c
                 }
                 int slot = nwin++;
                 if (lane == 0) {
-                    wbase[wave][slot] = pb;
-                    wdy[wave][slot] = ddy;
-                    wdz[wave][slot] = ddz;
+                    win[wave][slot] = Win{pb, (float)ddy, (float)ddz, 0.0f};
                 }
                 wave_lds_sync();   // earlier reads of the stage are done
                 // the page in the group's filter frame, then far sentinels up to
@@ -530,9 +530,7 @@ void k_pairs(Params P, Grid g, PV<real> tg, const uint32_t *__restrict__ tidx, c
                         close_page(slot);
                         flush();
                         if (lane == 0) {
-                            wbase[wave][0] = pb;
-                            wdy[wave][0] = ddy;
-                            wdz[wave][0] = ddz;
+                            win[wave][0] = Win{pb, (float)ddy, (float)ddz, 0.0f};
                         }
                         slot = 0;
                         nwin = 1;

@@ -36,14 +36,16 @@ __device__ inline double rcp<double>(double x)
 }
 
 // 1 / sqrt(r2) and sqrt(r2); r2 = 0 (a particle with itself, or a
-// coincident pair) gives r = 0 and rinv = 0, so n = 0 and, with F(0) = 0,
-// every pair term is exactly zero.
+// coincident pair) gives r = 0, so n = 0 and, with F(0) = 0, every pair term
+// is exactly zero.  In FP32 the argument is r2 + 2^-126, which equals r2 for
+// every r2 above 2^-101 and makes rinv = 2^63 at r2 = 0, a finite factor that
+// every term then multiplies by an exact zero.
 template <typename real>
 __device__ inline void inv_len(real r2, real &r, real &rinv);
 template <>
 __device__ inline void inv_len<float>(float r2, float &r, float &rinv)
 {
-    rinv = r2 > 0.0f ? __builtin_amdgcn_rsqf(r2) : 0.0f;
+    rinv = __builtin_amdgcn_rsqf(r2 + 0x1p-126f);
     r = r2 * rinv;
 }
 template <>
@@ -75,20 +77,51 @@ struct Sum<double> {
     __device__ inline void add(double x) { s += x; }
 };
 
-// Kernel and Riemann constants in the form's precision.
+// Kernel and Riemann constants in the form's precision: F3, F225 and F075
+// are Fc times the cubic spline's coefficients 3, 9/4 and 3/4; hb4 = 2 beta
+// and hbq = beta / 8 are the Riemann factor beta / 2 times 4 and 1 / 4 (powers
+// of two: exact).
 template <typename real>
 struct PairK {
     real hinv, Fc, beta, half_beta;
+    real F3, F225, F075;
+    real hb4, hbq;
 };
 
 template <typename real>
+__device__ inline PairK<real> make_pair_k(const Params &P)
+{
+    PairK<real> K;
+    K.hinv = (real)P.hinv;
+    K.Fc = (real)P.Fc;
+    K.beta = (real)P.beta;
+    K.half_beta = (real)(0.5 * P.beta);
+    K.F3 = (real)(3.0 * P.Fc);
+    K.F225 = (real)(2.25 * P.Fc);
+    K.F075 = (real)(0.75 * P.Fc);
+    K.hb4 = (real)(2.0 * P.beta);
+    K.hbq = (real)(0.125 * P.beta);
+    return K;
+}
+
+// F(r) for r < 2h (the callers have applied the neighbour predicate; at the
+// support's edge F and dF/dr vanish, so a q that rounds to just above 2 gives
+// F of the order of the rounding squared).
+template <typename real>
 __device__ inline real kernel_F(real r, const PairK<real> &K)
 {
-    real q = r * K.hinv;
-    real t = max(real(2) - q, real(0));      // zero beyond the support
-    real fin = q * (real(3) - real(2.25) * q);
-    real fout = real(0.75) * t * t;
-    return K.Fc * (q < real(1) ? fin : fout);
+    const real q = r * K.hinv;
+    const real t = real(2) - q;
+    if constexpr (sizeof(real) == 4) {
+        const real fin = q * (K.F3 - K.F225 * q);
+        const real fout = (K.F075 * t) * t;
+        return q < real(1) ? fin : fout;
+    } else {
+        // fewer live constants: the FP64 pass is short of registers
+        const real fin = q * (real(3) - real(2.25) * q);
+        const real fout = real(0.75) * t * t;
+        return K.Fc * (q < real(1) ? fin : fout);
+    }
 }
 
 // Per-particle quantities the FORCE pair terms read.
@@ -147,9 +180,8 @@ __device__ inline void pair_force(const real d[3], real r2, const Part<real, SOL
     const real s1 = dv[0] * d[0] + dv[1] * d[1] + dv[2] * d[2];
     const real s2 = sv[0] * d[0] + sv[1] * d[1] + sv[2] * d[2];
     const real rb = real(0.5) * (I.rho + J.rho);
-    const real cb = real(0.5) * (I.c + J.c);
     const real pb = real(0.5) * (I.p + J.p);
-    const real Z = rb * cb;
+    const real Z4 = (I.rho + J.rho) * (I.c + J.c);   // 4 Z
     real Pi = I.p, Pj = J.p;
     real Sd[3] = {real(0), real(0), real(0)};   // (S_i + S_j) d
     if constexpr (SOLID) {
@@ -162,8 +194,17 @@ __device__ inline void pair_force(const real d[3], real r2, const Part<real, SOL
 #pragma unroll
         for (int a = 0; a < 3; ++a) Sd[a] = si[a] + sj[a];
     }
-    const real du = K.half_beta * (Pi - Pj) * rcp<real>(Z);
-    const real ps = pb - (K.half_beta * Z * s1) * rinv;
+    // du = (beta / 2) (P_i - P_j) / Z and p* = mean(p) - (beta / 2) Z s1 / r
+    real du, ps;
+    if constexpr (sizeof(real) == 4) {
+        du = K.hb4 * (Pi - Pj) * rcp<real>(Z4);
+        ps = pb - (K.hbq * Z4 * s1) * rinv;
+    } else {
+        // fewer live constants: the FP64 pass is short of registers
+        const real Z = real(0.25) * Z4;
+        du = K.half_beta * (Pi - Pj) * rcp<real>(Z);
+        ps = pb - (K.half_beta * Z * s1) * rinv;
+    }
     const real A = real(2) * I.w * J.w;
     const real Phi = rb * du * F;
     const real mA = -A;
@@ -180,7 +221,7 @@ __device__ inline void pair_force(const real d[3], real r2, const Part<real, SOL
     }
     const real sv2 = sv[0] * sv[0] + sv[1] * sv[1] + sv[2] * sv[2];
     const real vs2 = real(0.25) * sv2 + du * (s2 * rinv + du);
-    const real Es = real(0.5) * (I.e + J.e) + real(0.5) * vs2;
+    const real Es2 = (I.e + J.e) + vs2;                        // 2 E*
     const real vsd = real(0.5) * s2 + du * r;                  // v* . d
     real tv = psG * vsd;                                       // t . v* (fluid part)
     if constexpr (SOLID) {
@@ -189,7 +230,7 @@ __device__ inline void pair_force(const real d[3], real r2, const Part<real, SOL
         const real sdd = Sd[0] * d[0] + Sd[1] * d[1] + Sd[2] * d[2];
         tv -= real(0.5) * G * (real(0.5) * sdsv + du * rinv * sdd);
     }
-    out[4] = mA * (Phi * Es + tv);
+    out[4] = ca * Es2 - A * tv;                                // -A (Phi E* + t . v*)
     out[5] = real(0.5) * A * G * s1;
 }
 
