@@ -217,20 +217,28 @@ def share_leg(reps=5):
     return out
 
 
-def balance_leg(reps=3):
+def balance_leg(reps=3, types=False):
     """One round of the swap heuristic (Section III.A) between an 8M and a 2M
     particle set (the mixed share and its partner), FP32 split: both centres,
     both balancing hashes, both selections, the swap.  Fresh sets each
-    repetition (a round changes them); the first round is the warm-up."""
+    repetition (a round changes them); the first round is the warm-up.  With
+    types: two particle types (a bead of type 1 in type 0), each balanced
+    towards its biased centres (Section III.B)."""
+    import numpy as np
     import torch
 
     import sph_synth as S
-    from paper_2310_03596_amd.balance import BalancePair
+    from paper_2310_03596_amd.balance import BalancePair, BalanceTypesPair
 
     a, b = S.c4_share("mixed")
+    if types:
+        lo = np.asarray(a.grid["origin"], dtype=np.float64)
+        hi = lo + np.asarray(a.grid["dims"]) * a.grid["cell"]
+        c, r = lo + 0.7 * (hi - lo), 0.25 * float((hi - lo).min())
+        ta, tb = S.particle_types(a.x, c, r), S.particle_types(b.x, c, r)
     times, ks = [], []
     for r in range(reps + 1):
-        bp = BalancePair(a, b, 1)
+        bp = BalanceTypesPair(a, b, ta, tb, 2, 1) if types else BalancePair(a, b, 1)
         torch.cuda.synchronize()
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
         ev[0].record()
@@ -245,12 +253,16 @@ def balance_leg(reps=3):
         torch.cuda.synchronize()
         if r > 0:
             times.append([ev[q].elapsed_time(ev[q + 1]) for q in range(4)])
-            ks.append(int(bp.k.cpu()[0]))
+            ks.append(bp.k[0].cpu().tolist() if types else int(bp.k.cpu()[0]))
         del bp
     t = [sum(x[q] for x in times) / len(times) for q in range(4)]
     tot = sum(t)
-    return {"particles": a.n + b.n, "k_swapped": ks[0], "round_ms": tot, "centroids_ms": t[0], "hashes_ms": t[1],
-            "selections_ms": t[2], "swap_ms": t[3], "particles_per_s": (a.n + b.n) / (tot * 1e-3)}
+    out = {"particles": a.n + b.n, "k_swapped": ks[0], "round_ms": tot, "centroids_ms": t[0], "hashes_ms": t[1],
+           "selections_ms": t[2], "swap_ms": t[3], "particles_per_s": (a.n + b.n) / (tot * 1e-3)}
+    if types:
+        out["types"] = 2
+        out["particles_of_type_1"] = int(ta.sum() + tb.sum())
+    return out
 
 
 def cpu_leg(wl, budget_s):
@@ -359,6 +371,7 @@ def main():
     if not args.no_share:
         out["share_pass"] = share_leg()
         out["balance_round"] = balance_leg()
+        out["balance_types_round"] = balance_leg(types=True)
     if args.calib_copy_mb > 0:
         nbytes = args.calib_copy_mb << 20
         src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")

@@ -56,6 +56,9 @@ enum sph_material { SPH_FLUID_TAIT = 0, SPH_SOLID_J2 = 1 };
 enum sph_pass { SPH_PASS_FORCE = 0, SPH_PASS_GRADIENT = 1 };
 enum sph_stage { SPH_STAGE_MOTION = 0, SPH_STAGE_STRESS = 1, SPH_STAGE_EOS = 2 };
 
+/* Particle types that the per-type balancing calls (Section III.B) accept. */
+#define SPH_MAX_TYPES 8
+
 /* Bucket grid (Section I).  Buckets are cubes of side `cell` >= 2h; bucket
  * (cx, cy, cz) covers origin + [c, c+1) * cell and has hash
  * cx + dims[0] * (cy + dims[1] * cz).  Particles outside the grid are
@@ -313,6 +316,57 @@ int sph_balance_select(uint32_t n, const uint32_t *bhash, uint32_t hmax, const u
  * missing lists). */
 int sph_swap(sph_particles *a, const uint32_t *sel_a, sph_particles *b, const uint32_t *sel_b,
              const uint32_t *k_dev, uint32_t k_max, void *stream);
+
+/* ---------------------------------------------------------------------
+ * Balancing with several particle types (Section III.B).  Every type is
+ * balanced on its own with the rule of Section III.A, and the centres that
+ * rule uses are biased towards the centre of all the particles:
+ *   Cg'_t = alpha Cg_all + (1 - alpha) Cg_t   (the paper takes alpha = 0.1),
+ * so that the decompositions of the types do not drift apart.  A type label
+ * per particle (type_dev, u8, n entries on the device) names its type;
+ * labels of ntypes or more take no part (in no centre, hash 0, never
+ * selected).  1 <= ntypes <= SPH_MAX_TYPES.  One round between GPUs A and B:
+ * sph_centroid_types on each, sph_balance_hash_types on each towards the
+ * other's centres, sph_balance_select_types on each, then sph_swap with the
+ * two selections and k_dev pointing at sel_offset_dev[ntypes] (their total);
+ * the selections of a type sit at the same offsets on both sides, so every
+ * particle changes GPU against one of its own type and both GPUs keep their
+ * count of every type.
+ * --------------------------------------------------------------------- */
+
+/* Mass-weighted centres of p by type.  cg_dev receives ntypes + 1 records of
+ * four doubles: record t < ntypes holds Cg'_t (above; zeros when type t has
+ * no mass in p) and the type's mass, record ntypes holds Cg_all (over the
+ * particles of every valid type) and their mass.  0 <= alpha <= 1.  FP64 sums
+ * in a fixed order, so repeated calls give identical results.  Reads x, m and
+ * type_dev.  The workspace is sized by sph_workspace_size for p->n.  Errors:
+ * SPH_ERR_ARG, SPH_ERR_WORKSPACE. */
+int sph_centroid_types(const sph_particles *p, const uint8_t *type_dev, uint32_t ntypes, double alpha,
+                       double *cg_dev, void *ws, size_t ws_bytes, void *stream);
+
+/* Balancing hash of every particle towards its type's centres: the rule of
+ * sph_balance_hash with own = record t of cg_own_dev and other = record t of
+ * cg_other_dev (records of four doubles as sph_centroid_types writes them;
+ * the fourth is not read).  n_positive_dev[t] receives the number of positive
+ * hashes of type t.  1 <= hmax < 2^20.  The workspace is sized by
+ * sph_workspace_size for p->n.  Errors: SPH_ERR_ARG, SPH_ERR_WORKSPACE. */
+int sph_balance_hash_types(const sph_particles *p, const uint8_t *type_dev, uint32_t ntypes,
+                           const double *cg_own_dev, const double *cg_other_dev, uint32_t hmax,
+                           uint32_t *bhash_out, uint32_t *n_positive_dev, void *ws, size_t ws_bytes,
+                           void *stream);
+
+/* Per-type selection: for every type t, k_t = min(n_positive_own_dev[t],
+ * n_positive_other_dev[t], number of particles of type t) goes to k_dev[t],
+ * and sel_out[sel_offset_dev[t] + q], q < k_t, receives the indices of the
+ * k_t particles of type t of largest balancing hash, ties in ascending index
+ * (one stable sort by type and descending hash).  sel_offset_dev (ntypes + 1
+ * entries) receives the exclusive offsets, sel_offset_dev[ntypes] their
+ * total.  sel_out has room for n entries.  The workspace is sized by
+ * sph_workspace_size for n.  Errors: SPH_ERR_ARG, SPH_ERR_WORKSPACE. */
+int sph_balance_select_types(uint32_t n, const uint8_t *type_dev, uint32_t ntypes, const uint32_t *bhash,
+                             uint32_t hmax, const uint32_t *n_positive_own_dev,
+                             const uint32_t *n_positive_other_dev, uint32_t *sel_out, uint32_t *k_dev,
+                             uint32_t *sel_offset_dev, void *ws, size_t ws_bytes, void *stream);
 
 #ifdef __cplusplus
 }

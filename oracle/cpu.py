@@ -395,6 +395,74 @@ def balance_select(bhash: np.ndarray, k: int, hmax: int = HMAX) -> np.ndarray:
     return sel[:k]
 
 
+# ------------------------------------------- several particle types (III.B)
+# Every type is balanced on its own with the rule of Section III.A, towards
+# centres biased to the centre of all the particles:
+#   Cg'_t = alpha Cg_all + (1 - alpha) Cg_t,  alpha = 0.1.
+# Labels of ntypes or more take no part.  These functions apply the
+# single-type steps above to each type's particles in turn.
+
+ALPHA = 0.1   # Section III.B
+
+
+def _part(s: State, mask: np.ndarray) -> State:
+    """The particles of s selected by mask (positions and masses)."""
+    o = State(int(mask.sum()))
+    o.x[:] = s.x[mask]
+    o.m[:] = s.m[mask]
+    return o
+
+
+def centroid_types(s: State, types: np.ndarray, ntypes: int, alpha: float = ALPHA) -> np.ndarray:
+    """(ntypes + 1, 4) records: row t < ntypes holds Cg'_t and the mass of
+    type t (zeros for a type without mass), row ntypes holds Cg_all over the
+    particles of every valid type and their mass (Section III.B)."""
+    types = np.asarray(types)
+    out = np.zeros((ntypes + 1, 4))
+    call, mall = centroid(_part(s, types < ntypes))
+    out[ntypes, :3], out[ntypes, 3] = call, mall
+    for t in range(ntypes):
+        ct, mt = centroid(_part(s, types == t))
+        if mt > 0:
+            out[t, :3] = alpha * call + (1.0 - alpha) * ct
+        out[t, 3] = mt
+    return out
+
+
+def balance_hash_types(s: State, types: np.ndarray, ntypes: int, cg_own, cg_other, hmax: int = HMAX):
+    """Balancing hash of every particle towards its own type's centres (rows
+    of cg_own, cg_other), and the number of positive hashes per type."""
+    types = np.asarray(types)
+    h = np.zeros(s.n, dtype=np.uint32)
+    npos = np.zeros(ntypes, dtype=np.int64)
+    for t in range(ntypes):
+        m = types == t
+        ht, nt = balance_hash(_part(s, m), np.asarray(cg_own)[t, :3], np.asarray(cg_other)[t, :3], hmax)
+        h[m] = ht
+        npos[t] = nt
+    return h, npos
+
+
+def balance_select_types(bhash: np.ndarray, types: np.ndarray, ntypes: int, npos_own, npos_other,
+                         hmax: int = HMAX):
+    """Per type t, k_t = min(npos_own[t], npos_other[t], count of type t) and
+    the indices of its k_t largest hashes (ties in ascending index), one type
+    after another.  Returns (sel, k, offsets) with offsets[ntypes] = len(sel)."""
+    types = np.asarray(types)
+    bhash = np.asarray(bhash, dtype=np.uint32)
+    parts = []
+    k = np.zeros(ntypes, dtype=np.int64)
+    off = np.zeros(ntypes + 1, dtype=np.int64)
+    for t in range(ntypes):
+        idx = np.nonzero(types == t)[0]
+        kt = min(int(npos_own[t]), int(npos_other[t]), idx.size)
+        parts.append(idx[balance_select(bhash[idx], kt, hmax)].astype(np.uint32))
+        k[t] = kt
+        off[t + 1] = off[t] + kt
+    sel = np.concatenate(parts) if parts else np.zeros(0, dtype=np.uint32)
+    return sel, k, off
+
+
 def swap(a: State, sel_a: np.ndarray, b: State, sel_b: np.ndarray):
     """Exchange the selected particles of a and b pairwise (in place)."""
     k = len(sel_a)

@@ -17,6 +17,7 @@ SPH_FP64, SPH_FP32_SPLIT = 0, 1
 SPH_FLUID_TAIT, SPH_SOLID_J2 = 0, 1
 SPH_PASS_FORCE, SPH_PASS_GRADIENT = 0, 1
 SPH_STAGE_MOTION, SPH_STAGE_STRESS, SPH_STAGE_EOS = 0, 1, 2
+SPH_MAX_TYPES = 8   # particle types of the per-type balancing calls
 
 _vp = C.c_void_p
 
@@ -56,7 +57,8 @@ class SphAdjoint(C.Structure):
 EXPORTS = ("sph_version", "sph_last_error", "sph_workspace_size", "sph_build_cells", "sph_mark_boundary",
            "sph_pack_boundary", "sph_interact", "sph_count_pairs", "sph_integrate", "sph_interact_adjoint",
            "sph_integrate_adjoint", "sph_permute_adjoint", "sph_centroid", "sph_balance_hash",
-           "sph_balance_select", "sph_swap")
+           "sph_balance_select", "sph_swap", "sph_centroid_types", "sph_balance_hash_types",
+           "sph_balance_select_types")
 
 _lib = None
 
@@ -101,6 +103,11 @@ def load():
     L.sph_balance_hash.argtypes = [P(SphParticles), _vp, _vp, C.c_uint32, _vp, _vp, _vp, C.c_size_t, _vp]
     L.sph_balance_select.argtypes = [C.c_uint32, _vp, C.c_uint32, _vp, _vp, _vp, _vp, _vp, C.c_size_t, _vp]
     L.sph_swap.argtypes = [P(SphParticles), _vp, P(SphParticles), _vp, _vp, C.c_uint32, _vp]
+    L.sph_centroid_types.argtypes = [P(SphParticles), _vp, C.c_uint32, C.c_double, _vp, _vp, C.c_size_t, _vp]
+    L.sph_balance_hash_types.argtypes = [P(SphParticles), _vp, C.c_uint32, _vp, _vp, C.c_uint32, _vp, _vp, _vp,
+                                         C.c_size_t, _vp]
+    L.sph_balance_select_types.argtypes = [C.c_uint32, _vp, C.c_uint32, _vp, C.c_uint32, _vp, _vp, _vp, _vp, _vp,
+                                           _vp, C.c_size_t, _vp]
     for name in EXPORTS[3:]:
         getattr(L, name).restype = C.c_int
     _lib = L
@@ -196,3 +203,22 @@ def sph_balance_select(n, bhash_ptr, hmax, npos_own_ptr, npos_other_ptr, sel_ptr
 
 def sph_swap(a, sel_a_ptr, b, sel_b_ptr, k_ptr, k_max, stream):
     return check("sph_swap", load().sph_swap(C.byref(a), sel_a_ptr, C.byref(b), sel_b_ptr, k_ptr, k_max, stream))
+
+
+def sph_centroid_types(p, type_ptr, ntypes, alpha, cg_ptr, ws_ptr, ws_bytes, stream):
+    return check("sph_centroid_types", load().sph_centroid_types(C.byref(p), type_ptr, ntypes, alpha, cg_ptr,
+                                                                 ws_ptr, ws_bytes, stream))
+
+
+def sph_balance_hash_types(p, type_ptr, ntypes, cg_own_ptr, cg_other_ptr, hmax, bhash_ptr, npos_ptr, ws_ptr,
+                           ws_bytes, stream):
+    return check("sph_balance_hash_types",
+                 load().sph_balance_hash_types(C.byref(p), type_ptr, ntypes, cg_own_ptr, cg_other_ptr, hmax,
+                                               bhash_ptr, npos_ptr, ws_ptr, ws_bytes, stream))
+
+
+def sph_balance_select_types(n, type_ptr, ntypes, bhash_ptr, hmax, npos_own_ptr, npos_other_ptr, sel_ptr, k_ptr,
+                             off_ptr, ws_ptr, ws_bytes, stream):
+    return check("sph_balance_select_types",
+                 load().sph_balance_select_types(n, type_ptr, ntypes, bhash_ptr, hmax, npos_own_ptr, npos_other_ptr,
+                                                 sel_ptr, k_ptr, off_ptr, ws_ptr, ws_bytes, stream))

@@ -444,4 +444,55 @@ int sph_swap(sph_particles *a, const uint32_t *sel_a, sph_particles *b, const ui
     return hip_status(launch_swap(a->prec, *a, sel_a, *b, sel_b, k_dev, k_max, (hipStream_t)stream), "sph_swap");
 }
 
+int sph_centroid_types(const sph_particles *p, const uint8_t *type_dev, uint32_t ntypes, double alpha, double *cg_dev,
+                       void *ws, size_t ws_bytes, void *stream)
+{
+    if (!p) return fail(SPH_ERR_ARG, "p is NULL");
+    if (p->prec != SPH_FP64 && p->prec != SPH_FP32_SPLIT) return fail(SPH_ERR_ARG, "unknown precision %d", p->prec);
+    if (ntypes < 1 || ntypes > SPH_MAX_TYPES) return fail(SPH_ERR_ARG, "ntypes = %u must be in [1, %d]", ntypes, SPH_MAX_TYPES);
+    if (!(alpha >= 0.0 && alpha <= 1.0)) return fail(SPH_ERR_ARG, "alpha = %g must be in [0, 1]", alpha);
+    if (!cg_dev) return fail(SPH_ERR_ARG, "cg_dev is NULL");
+    if (p->n > 0 && (!p->x[0] || !p->x[1] || !p->x[2] || !p->m || !type_dev))
+        return fail(SPH_ERR_ARG, "x, m or type_dev is NULL");
+    Workspace w;
+    if (!check_ws(ws, ws_bytes, p->n, w)) return SPH_ERR_WORKSPACE;
+    return hip_status(launch_centroid_types(p->prec, *p, type_dev, ntypes, alpha, cg_dev, w, (hipStream_t)stream),
+                      "sph_centroid_types");
+}
+
+int sph_balance_hash_types(const sph_particles *p, const uint8_t *type_dev, uint32_t ntypes, const double *cg_own_dev,
+                           const double *cg_other_dev, uint32_t hmax, uint32_t *bhash_out, uint32_t *n_positive_dev,
+                           void *ws, size_t ws_bytes, void *stream)
+{
+    if (!p) return fail(SPH_ERR_ARG, "p is NULL");
+    if (ntypes < 1 || ntypes > SPH_MAX_TYPES) return fail(SPH_ERR_ARG, "ntypes = %u must be in [1, %d]", ntypes, SPH_MAX_TYPES);
+    if (!cg_own_dev || !cg_other_dev || !n_positive_dev) return fail(SPH_ERR_ARG, "a centre or the counts are NULL");
+    if (hmax < 1 || hmax >= (1u << 20)) return fail(SPH_ERR_ARG, "hmax = %u must be in [1, 2^20)", hmax);
+    if (p->n > 0 && (!p->x[0] || !p->x[1] || !p->x[2] || !bhash_out || !type_dev))
+        return fail(SPH_ERR_ARG, "x, type_dev or bhash_out is NULL");
+    Workspace w;
+    if (!check_ws(ws, ws_bytes, p->n, w)) return SPH_ERR_WORKSPACE;
+    return hip_status(launch_balance_hash_types(*p, type_dev, ntypes, cg_own_dev, cg_other_dev, hmax, bhash_out,
+                                                n_positive_dev, w, (hipStream_t)stream),
+                      "sph_balance_hash_types");
+}
+
+int sph_balance_select_types(uint32_t n, const uint8_t *type_dev, uint32_t ntypes, const uint32_t *bhash, uint32_t hmax,
+                             const uint32_t *n_positive_own_dev, const uint32_t *n_positive_other_dev,
+                             uint32_t *sel_out, uint32_t *k_dev, uint32_t *sel_offset_dev, void *ws, size_t ws_bytes,
+                             void *stream)
+{
+    if (ntypes < 1 || ntypes > SPH_MAX_TYPES) return fail(SPH_ERR_ARG, "ntypes = %u must be in [1, %d]", ntypes, SPH_MAX_TYPES);
+    if (!n_positive_own_dev || !n_positive_other_dev || !k_dev || !sel_offset_dev)
+        return fail(SPH_ERR_ARG, "a count, k_dev or sel_offset_dev is NULL");
+    if (hmax < 1 || hmax >= (1u << 20)) return fail(SPH_ERR_ARG, "hmax = %u must be in [1, 2^20)", hmax);
+    if (n > 0 && (!bhash || !sel_out || !type_dev)) return fail(SPH_ERR_ARG, "bhash, type_dev or sel_out is NULL");
+    Workspace w;
+    if (!check_ws(ws, ws_bytes, n, w)) return SPH_ERR_WORKSPACE;
+    return hip_status(launch_balance_select_types(n, type_dev, ntypes, bhash, hmax, n_positive_own_dev,
+                                                  n_positive_other_dev, sel_out, k_dev, sel_offset_dev, w,
+                                                  (hipStream_t)stream),
+                      "sph_balance_select_types");
+}
+
 }  // extern "C"

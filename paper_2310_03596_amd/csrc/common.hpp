@@ -29,6 +29,7 @@ constexpr int kMaxRadixBits = 10;     // digits of 8 to 10 bits: keys up to 20 b
 constexpr int kMaxRadixBins = 1 << kMaxRadixBits;
 constexpr int kDiag = 7;             // integrate diagnostics
 constexpr int kDiagPartial = 8;      // per-block partial record (doubles)
+constexpr int kMaxTypes = SPH_MAX_TYPES;   // particle types balanced separately
 
 // Device view of the grid: origin, bucket side and its float copy.
 struct Grid {
@@ -290,6 +291,15 @@ hipError_t launch_balance_select(uint32_t n, const uint32_t *bhash, uint32_t hma
                                  hipStream_t s);
 hipError_t launch_swap(int prec, const sph_particles &a, const uint32_t *sel_a, const sph_particles &b,
                        const uint32_t *sel_b, const uint32_t *k_dev, uint32_t k_max, hipStream_t s);
+hipError_t launch_centroid_types(int prec, const sph_particles &p, const uint8_t *type, uint32_t ntypes, double alpha,
+                                 double *cg, const Workspace &ws, hipStream_t s);
+hipError_t launch_balance_hash_types(const sph_particles &p, const uint8_t *type, uint32_t ntypes,
+                                     const double *cg_own, const double *cg_other, uint32_t hmax, uint32_t *bhash,
+                                     uint32_t *npos, const Workspace &ws, hipStream_t s);
+hipError_t launch_balance_select_types(uint32_t n, const uint8_t *type, uint32_t ntypes, const uint32_t *bhash,
+                                       uint32_t hmax, const uint32_t *npos_own, const uint32_t *npos_other,
+                                       uint32_t *sel, uint32_t *k_out, uint32_t *off, const Workspace &ws,
+                                       hipStream_t s);
 hipError_t launch_permute_adjoint(int prec, uint32_t n, const uint32_t *perm, const sph_adjoint &in,
                                   const sph_adjoint &out, hipStream_t s);
 

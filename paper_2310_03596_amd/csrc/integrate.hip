@@ -134,38 +134,50 @@ __global__ __launch_bounds__(kBlock) void k_eos(Params P, PV<real> s, double *__
     block_reduce_record(rec, partials + (size_t)blockIdx.x * kDiagPartial);
 }
 
-__global__ __launch_bounds__(kBlock) void k_diag_final(const double *__restrict__ partials, uint32_t nblocks,
-                                                       double cfl_h, double *__restrict__ diag)
+// The final fold of the per-block records: one workgroup of 1024 threads;
+// every thread issues the loads of up to four records (b, b + 1024, ...)
+// before it folds them, so the records arrive in one round trip instead of
+// one per record.  Folded in a fixed order (within a thread, then a fixed
+// tree), so the diagnostics are deterministic.
+constexpr int kFinalBlock = 1024;
+__global__ __launch_bounds__(kFinalBlock) void k_diag_final(const double *__restrict__ partials, uint32_t nblocks,
+                                                            double cfl_h, double *__restrict__ diag)
 {
-    // four independent chains per thread (records b, b + kBlock, ...), so
-    // their loads overlap; folded in a fixed order
-    double acc[4][kDiag] = {};
-    for (uint32_t b0 = threadIdx.x; b0 < nblocks; b0 += 4 * kBlock) {
+    constexpr int kU = 4;
+    double acc[kDiag] = {};
+    for (uint32_t b0 = threadIdx.x; b0 < nblocks; b0 += kU * kFinalBlock) {
+        double q[kU][kDiag];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const uint32_t b = b0 + (uint32_t)u * kBlock;
-            if (b < nblocks) {
-                const double *q = partials + (size_t)b * kDiagPartial;
-                acc[u][0] = fmax(acc[u][0], q[0]);
+        for (int u = 0; u < kU; ++u) {
+            const uint32_t b = b0 + (uint32_t)u * kFinalBlock;
 #pragma unroll
-                for (int k = 1; k < kDiag; ++k) acc[u][k] += q[k];
-            }
+            for (int k = 0; k < kDiag; ++k) q[u][k] = b < nblocks ? partials[(size_t)b * kDiagPartial + k] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            acc[0] = fmax(acc[0], q[u][0]);
+#pragma unroll
+            for (int k = 1; k < kDiag; ++k) acc[k] += q[u][k];
         }
     }
-    double rec[kDiag];
+    __shared__ double sh[kDiag][kFinalBlock / kWave];
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
 #pragma unroll
     for (int k = 0; k < kDiag; ++k) {
-        rec[k] = acc[0][k];
+        double v = acc[k];
 #pragma unroll
-        for (int u = 1; u < 4; ++u) rec[k] = k == 0 ? fmax(rec[k], acc[u][k]) : rec[k] + acc[u][k];
+        for (int off = kWave / 2; off > 0; off >>= 1) {
+            const double o = __shfl_down(v, off, kWave);
+            v = (k == 0) ? fmax(v, o) : v + o;
+        }
+        if (lane == 0) sh[k][wave] = v;
     }
-    __shared__ double out[kDiagPartial];
-    block_reduce_record(rec, out);
     __syncthreads();
-    if (threadIdx.x == 0) {
-        diag[0] = out[0] > 0.0 ? cfl_h / out[0] : __builtin_huge_val();
-#pragma unroll
-        for (int k = 1; k < kDiag; ++k) diag[k] = out[k];
+    if (threadIdx.x < kDiag) {
+        const int k = threadIdx.x;
+        double v = sh[k][0];
+        for (int w = 1; w < kFinalBlock / kWave; ++w) v = (k == 0) ? fmax(v, sh[k][w]) : v + sh[k][w];
+        diag[k] = k == 0 ? (v > 0.0 ? cfl_h / v : __builtin_huge_val()) : v;
     }
 }
 
@@ -242,7 +254,7 @@ hipError_t go(const Params &P, int stage, const sph_particles &p, const sph_rate
         else
             k_eos<real><<<blocks, kBlock, 0, s>>>(P, view<real>(p), ws.partials);
     }
-    if (diag) k_diag_final<<<1, kBlock, 0, s>>>(ws.partials, blocks, P.cfl * P.h, diag);
+    if (diag) k_diag_final<<<1, kFinalBlock, 0, s>>>(ws.partials, blocks, P.cfl * P.h, diag);
     return hipGetLastError();
 }
 

@@ -38,8 +38,15 @@ namespace sph {
 
 namespace {
 
-constexpr int kPairBlock = 256;            // targets per workgroup
+#ifndef SPH_PAIR_BLOCK
+#define SPH_PAIR_BLOCK 256
+#endif
+constexpr int kPairBlock = SPH_PAIR_BLOCK;  // targets per workgroup
 constexpr int kWaves = kPairBlock / kWave;
+// wavefronts whose list entries share one dword (so that a wavefront's 64
+// lanes touch 64 different dwords)
+constexpr int kHitWaves = kWaves < 4 ? kWaves : 4;
+static_assert(kWaves % kHitWaves == 0 && kWaves % 2 == 0, "whole wavefront groups");
 #ifndef SPH_PAIR_SUB
 #define SPH_PAIR_SUB 4   // measured best of 4, 8, 16 on the 810k column (fewer live VGPRs)
 #endif
@@ -215,7 +222,7 @@ void k_pairs(Params P, Grid g, PV<real> tg, const uint32_t *__restrict__ tidx, c
     // List entries and marks are laid out so that the 64 lanes of a wavefront
     // always touch 64 different dwords (the wavefronts of the workgroup share
     // each dword), whatever each lane's fill: no LDS bank conflicts.
-    __shared__ uint8_t hits[kHitCap][kWave][kWaves];   // index inside the page
+    __shared__ uint8_t hits[kHitCap][kWaves / kHitWaves][kWave][kHitWaves];   // index inside the page
     // per lane, one mark per page in which it has hits: (slot << 8) | list fill
     // at the end of that page's hits
     __shared__ uint16_t marks[kMaxWin][kWaves / 2][kWave][2];
@@ -308,7 +315,7 @@ void k_pairs(Params P, Grid g, PV<real> tg, const uint32_t *__restrict__ tidx, c
         nb = (int)(m & 0xFFu);
         const uint32_t slot = m >> 8;
         const Win &wn = win[wave][slot];
-        const uint32_t jj = wn.base + (uint32_t)hits[s][lane][wave];
+        const uint32_t jj = wn.base + (uint32_t)hits[s][wave / kHitWaves][lane][wave % kHitWaves];
         q.qy = SPLIT ? (real)wn.dy : real(0);
         q.qz = SPLIT ? (real)wn.dz : real(0);
         // a 32-bit byte offset from each array's base (sources are fewer than
@@ -541,7 +548,7 @@ void k_pairs(Params P, Grid g, PV<real> tg, const uint32_t *__restrict__ tidx, c
                         const v4 q = stage[wave][base + m];
                         const real t = fma(-q.z, fo[2], fma(-q.y, fo[1], fma(-q.x, fo[0], q.w)));
                         // the entry is written always and kept only when it is a hit
-                        hits[cnt][lane][wave] = (uint8_t)(base + m);
+                        hits[cnt][wave / kHitWaves][lane][wave % kHitWaves] = (uint8_t)(base + m);
                         cnt += (t < Tl) ? 1 : 0;
                     }
                 }

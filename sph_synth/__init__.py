@@ -223,6 +223,19 @@ def c4_share(layout: str = "slab", seed: int = 4, nx: int = 250, ny: int = 200, 
     return local, remote
 
 
+def particle_types(x: np.ndarray, centre, radius: float, seed: int = 0, p_third: float = 0.0) -> np.ndarray:
+    """Type labels (u8) for the per-type balancing: 1 inside a sphere (a bead,
+    like the projectile of a hypervelocity impact), 0 outside; with
+    p_third > 0 a uniformly drawn fraction of all particles gets type 2.
+    Draw order: U(0,1) (n,)."""
+    x = np.asarray(x)
+    t = (np.linalg.norm(x - np.asarray(centre, dtype=np.float64), axis=1) < radius).astype(np.uint8)
+    if p_third > 0.0:
+        rng = np.random.default_rng(seed)
+        t[rng.uniform(0.0, 1.0, size=x.shape[0]) < p_third] = 2
+    return t
+
+
 def c5_box(seed: int = 5, n_side: int = 63, dx: float = 2e-3, margin_cells: int = 2) -> Workload:
     """Free fluid box for the adjoint: n_side^3 jittered lattice, v ~ N(0, 1).
 

@@ -208,3 +208,32 @@ def test_balancing_entry_points_reject_bad_arguments():
     assert lib.sph_swap(C.byref(p), FAKE, C.byref(q), FAKE, FAKE, 10, None) == ARG and "precision" in _last()
     assert lib.sph_swap(C.byref(p), None, C.byref(p), FAKE, FAKE, 10, None) == ARG
     assert lib.sph_swap(C.byref(p), None, C.byref(p), None, None, 0, None) == L.SPH_OK   # nothing to do
+
+
+def test_type_balancing_entry_points_reject_bad_arguments():
+    lib = L.load()
+    ARG, WS = L.SPH_ERR_ARG, L.SPH_ERR_WORKSPACE
+    p = _particles(10)
+    n_ws = L.sph_workspace_size(_grid(), 10, 0, 0)
+    for nt in (0, L.SPH_MAX_TYPES + 1):
+        assert lib.sph_centroid_types(C.byref(p), FAKE, nt, 0.1, FAKE, FAKE, n_ws, None) == ARG
+        assert "ntypes" in _last()
+        assert lib.sph_balance_hash_types(C.byref(p), FAKE, nt, FAKE, FAKE, 1000, FAKE, FAKE, FAKE, n_ws,
+                                          None) == ARG
+        assert lib.sph_balance_select_types(10, FAKE, nt, FAKE, 1000, FAKE, FAKE, FAKE, FAKE, FAKE, FAKE, n_ws,
+                                            None) == ARG
+    for alpha in (-0.1, 1.5, float("nan")):
+        assert lib.sph_centroid_types(C.byref(p), FAKE, 2, alpha, FAKE, FAKE, n_ws, None) == ARG
+        assert "alpha" in _last()
+    assert lib.sph_centroid_types(C.byref(p), None, 2, 0.1, FAKE, FAKE, n_ws, None) == ARG
+    assert lib.sph_centroid_types(C.byref(p), FAKE, 2, 0.1, None, FAKE, n_ws, None) == ARG
+    assert lib.sph_centroid_types(C.byref(p), FAKE, 2, 0.1, FAKE, FAKE, 64, None) == WS
+    assert lib.sph_balance_hash_types(C.byref(p), FAKE, 2, FAKE, FAKE, 0, FAKE, FAKE, FAKE, n_ws, None) == ARG
+    assert lib.sph_balance_hash_types(C.byref(p), None, 2, FAKE, FAKE, 1000, FAKE, FAKE, FAKE, n_ws, None) == ARG
+    assert lib.sph_balance_hash_types(C.byref(p), FAKE, 2, FAKE, None, 1000, FAKE, FAKE, FAKE, n_ws, None) == ARG
+    assert lib.sph_balance_select_types(10, FAKE, 2, FAKE, 1000, FAKE, FAKE, FAKE, FAKE, None, FAKE, n_ws,
+                                        None) == ARG
+    assert lib.sph_balance_select_types(10, None, 2, FAKE, 1000, FAKE, FAKE, FAKE, FAKE, FAKE, FAKE, n_ws,
+                                        None) == ARG
+    assert lib.sph_balance_select_types(10, FAKE, 2, FAKE, 1000, FAKE, FAKE, FAKE, FAKE, FAKE, None, n_ws,
+                                        None) == WS
