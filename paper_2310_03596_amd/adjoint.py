@@ -28,21 +28,6 @@ from .sim import Sim
 from .state import Particles, Rates, cells_struct, real_dtype, stream_handle
 
 
-def _clone_particles(p: Particles) -> Particles:
-    q = copy.copy(p)
-    for f in ("x", "off", "hash", "id", "v", "m", "w", "rho", "p", "c", "e", "E", "S", "ep"):
-        a = getattr(p, f)
-        setattr(q, f, None if a is None else a.clone())
-    return q
-
-
-def _copy_into(dst: Particles, src: Particles):
-    for f in ("x", "off", "hash", "id", "v", "m", "w", "rho", "p", "c", "e", "E"):
-        a = getattr(src, f)
-        if a is not None:
-            getattr(dst, f).copy_(a)
-
-
 class Cotangent:
     """Device buffers of a state cotangent (sph_adjoint), in the form's precision."""
 
@@ -94,7 +79,7 @@ class KineticEnergyRollout:
         self.ckpts = []
         for k in range(self.nsteps):
             if k % self.ckpt == 0:
-                self.ckpts.append(_clone_particles(sim.A))
+                self.ckpts.append(sim.A.clone())
             sim.step()
         torch.cuda.synchronize()
         self.final = sim.A
@@ -129,27 +114,26 @@ class KineticEnergyRollout:
         ws_adj_bytes = L.sph_workspace_size(sim.grid, n, prec, L.SPH_SOLID_J2)
         ws_adj = torch.zeros(ws_adj_bytes, dtype=torch.uint8, device=dev)
         fixed = sim.fixed.data_ptr()
+        # saved states of one segment, allocated once and reused by every segment:
+        # the sorted state before the update, its permutation, bucket table and rates
+        pool = [(Particles(n, prec, sim.solid, dev), torch.empty_like(sim.perm), torch.empty_like(sim.start),
+                 Rates(n, prec, False, dev)) for _ in range(min(self.ckpt, self.nsteps))]
         for seg in reversed(range(len(self.ckpts))):
             k0 = seg * self.ckpt
             k1 = min(k0 + self.ckpt, self.nsteps)
-            _copy_into(sim.A, self.ckpts[seg])
-            saved = []
-            for _ in range(k0, k1):
+            sim.A.copy_from(self.ckpts[seg])
+            saved = pool[:k1 - k0]
+            for srt, perm, start, rates in saved:
                 sim.build()
-                srt = _clone_particles(sim.A)
-                perm = sim.perm.clone()
-                start = sim.start.clone()
+                srt.copy_from(sim.A)
+                perm.copy_(sim.perm)
+                start.copy_(sim.start)
                 a = sim.A.struct()
-                r = sim.rates.struct()
+                r = rates.struct()
                 L.sph_interact(sim.params, sim.grid, L.SPH_PASS_FORCE, a, None, None, a, sim.cells, 1, r,
                                sim.ws.data_ptr(), sim.ws_bytes, st)
-                rates = Rates(n, prec, False, dev)
-                rates.hi.copy_(sim.rates.hi)
-                if rates.lo is not None:
-                    rates.lo.copy_(sim.rates.lo)
                 L.sph_integrate(sim.params, L.SPH_STAGE_MOTION, a, r, fixed, sim.diag[0].data_ptr(),
                                 sim.ws.data_ptr(), sim.ws_bytes, st)
-                saved.append((srt, perm, start, rates))
             for srt, perm, start, rates in reversed(saved):
                 ps = srt.struct()
                 L.sph_integrate_adjoint(sim.params, L.SPH_STAGE_MOTION, ps, rates.struct(), fixed, bar.struct(),

@@ -5,6 +5,8 @@ tensor here is raw device memory handed to libsph by pointer.
 """
 from __future__ import annotations
 
+import copy
+
 import numpy as np
 import torch
 
@@ -47,7 +49,54 @@ def _ptr(t):
     return None if t is None else t.data_ptr()
 
 
-class Particles:
+def _carve(buf: torch.Tensor, layout):
+    """Views of one flat byte buffer, one per (name, shape, dtype) of layout
+    (None where shape is None), each at a 256-byte aligned offset."""
+    out, off = {}, 0
+    for name, shape, dt in layout:
+        if shape is None:
+            out[name] = None
+            continue
+        nbytes = int(np.prod(shape)) * torch.empty((), dtype=dt).element_size()
+        out[name] = buf[off:off + nbytes].view(dt).view(shape)
+        off += (nbytes + 255) & ~255
+    return out
+
+
+def _carved_bytes(layout) -> int:
+    off = 0
+    for _, shape, dt in layout:
+        if shape is not None:
+            off += (int(np.prod(shape)) * torch.empty((), dtype=dt).element_size() + 255) & ~255
+    return max(off, 256)
+
+
+class _Flat:
+    """Fields that live in one device allocation, so that a copy of the whole
+    set (checkpoints, saved states of the reverse pass) is one copy."""
+
+    def _allocate(self, layout, device):
+        self._layout = layout
+        self._buf = torch.zeros(_carved_bytes(layout), dtype=torch.uint8, device=device)
+        self._bind()
+
+    def _bind(self):
+        for k, v in _carve(self._buf, self._layout).items():
+            setattr(self, k, v)
+
+    def clone(self):
+        """A copy with its own storage (one device copy)."""
+        q = copy.copy(self)
+        q._buf = self._buf.clone()
+        q._bind()
+        return q
+
+    def copy_from(self, other):
+        """Overwrite every field with other's (same sizes; one device copy)."""
+        self._buf.copy_(other._buf)
+
+
+class Particles(_Flat):
     """One particle array in SoA form on the device."""
 
     REAL = ("m", "w", "rho", "p", "c", "e")
@@ -55,20 +104,13 @@ class Particles:
     def __init__(self, n: int, prec: int, solid: bool, device="cuda"):
         real = real_dtype(prec)
         self.n, self.prec, self.solid, self.device = n, prec, solid, device
-
-        def z(shape, dt):
-            return torch.zeros(shape, dtype=dt, device=device)
-
-        self.x = z((3, n), torch.float64)
-        self.off = z((3, n), torch.float32) if prec == L.SPH_FP32_SPLIT else None
-        self.hash = z((n,), torch.int32)
-        self.id = z((n,), torch.int32)
-        self.v = z((3, n), real)
-        for f in self.REAL:
-            setattr(self, f, z((n,), real))
-        self.E = z((n,), torch.float64)
-        self.S = z((6, n), real) if solid else None
-        self.ep = z((n,), real) if solid else None
+        split = prec == L.SPH_FP32_SPLIT
+        layout = [("x", (3, n), torch.float64), ("off", (3, n) if split else None, torch.float32),
+                  ("hash", (n,), torch.int32), ("id", (n,), torch.int32), ("v", (3, n), real)]
+        layout += [(f, (n,), real) for f in self.REAL]
+        layout += [("E", (n,), torch.float64), ("S", (6, n) if solid else None, real),
+                   ("ep", (n,) if solid else None, real)]
+        self._allocate(layout, device)
 
     def struct(self) -> L.SphParticles:
         s = L.SphParticles()
@@ -123,16 +165,15 @@ class Particles:
         return out
 
 
-class Rates:
+class Rates(_Flat):
     """Pair-sum outputs: FORCE rates and, for solids, the velocity gradient."""
 
     def __init__(self, n: int, prec: int, gradient: bool, device="cuda"):
         real = real_dtype(prec)
         split = prec == L.SPH_FP32_SPLIT
-        self.hi = torch.zeros((6, n), dtype=real, device=device)
-        self.lo = torch.zeros((6, n), dtype=real, device=device) if split else None
-        self.Lhi = torch.zeros((9, n), dtype=real, device=device) if gradient else None
-        self.Llo = torch.zeros((9, n), dtype=real, device=device) if (gradient and split) else None
+        self._allocate([("hi", (6, n), real), ("lo", (6, n) if split else None, real),
+                        ("Lhi", (9, n) if gradient else None, real),
+                        ("Llo", (9, n) if (gradient and split) else None, real)], device)
 
     def struct(self) -> L.SphRates:
         r = L.SphRates()
