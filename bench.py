@@ -122,16 +122,20 @@ def time_form(wl, prec, steps, warmup):
 
 
 def other_workloads_leg():
-    """Step throughput of the 8,000-particle cube (10 steps) and the
+    """Step throughput of the 8,000-particle cube (10 steps), the
     3,987,920-particle elastic-plastic cylinder (two interaction loops per
-    step: GRADIENT, stress stage, FORCE; 20 steps) in both forms."""
+    step: GRADIENT, stress stage, FORCE; 20 steps) and the 6,668,204-particle
+    hypervelocity impact (same loops, Mie-Gruneisen EOS; 20 steps from the
+    first contact) in both forms."""
     import torch
 
     import sph_synth as S
     from paper_2310_03596_amd.sim import Sim
 
     out = {}
-    for name, wl, steps in (("cube_8000", S.c1_cube(), 10), ("cylinder_3987920", S.c3_cylinder(), 20)):
+    for name, make, steps in (("cube_8000", S.c1_cube, 10), ("cylinder_3987920", S.c3_cylinder, 20),
+                              ("hvi_6668204", S.c6_hvi, 20)):
+        wl = make()
         out[name] = {}
         for prec, tag in ((1, "fp32_split"), (0, "fp64")):
             sim = Sim(wl, prec)
@@ -146,6 +150,7 @@ def other_workloads_leg():
             out[name][tag] = {"steps": steps, "ms_per_step": 1e3 * wall / steps,
                               "particle_updates_per_s": wl.n * steps / wall}
             del sim
+        del wl
         torch.cuda.empty_cache()
     return out
 

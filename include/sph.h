@@ -72,20 +72,37 @@ typedef struct sph_grid {
     int32_t reserved;
 } sph_grid;
 
+/* Equation of state of a J2 solid (sph_params.eos). */
+enum sph_solid_eos { SPH_EOS_LINEAR = 0, SPH_EOS_MIE_GRUNEISEN = 1 };
+
 /* Physical constants.  Smoothing length h is one value for all particles
  * (Section II: equal particle counts balance the work only when h is
  * constant).  Tait fluid: p = rho0 c0^2 / gamma ((rho / rho0)^gamma - 1),
- * c = c0 (rho / rho0)^((gamma - 1) / 2).  J2 solid: p = K (rho / rho0 - 1),
- * c = sqrt((K + 4G/3) / rho0), yield Y0 + H eps_p.  beta scales the acoustic
- * Riemann solver's dissipation (1 = the linearised Riemann solution).  Walls:
- * bit 2d of wall_mask reflects at wall_lo[d], bit 2d+1 at wall_hi[d]. */
+ * c = c0 (rho / rho0)^((gamma - 1) / 2).  J2 solid: yield Y0 + H eps_p
+ * (H = 0: the elastic perfectly plastic limit of Johnson-Cook that Section
+ * IV.A uses), with eos = SPH_EOS_LINEAR: p = K (rho / rho0 - 1),
+ * c = sqrt((K + 4G/3) / rho0); or eos = SPH_EOS_MIE_GRUNEISEN (Section IV.A
+ * names a Mie-Gruneisen EOS with a cut-off pressure; the form is the linear
+ * shock-velocity one, Us = c0 + mg_s up, with Gamma rho = mg_gamma0 rho0):
+ * mu = rho / rho0 - 1, e the specific internal energy,
+ *   mu > 0: p = rho0 c0^2 mu (1 + (1 - mg_gamma0 / 2) mu) / D^2 + mg_gamma0 rho0 e,
+ *           D = max(1 - (mg_s - 1) mu, 1/16),
+ *   mu <= 0: p = rho0 c0^2 mu + mg_gamma0 rho0 e,
+ * then p = max(p, p_cut) (spall cut-off, p_cut <= 0); bulk sound speed
+ * cb^2 = c0^2 (1 + (2 - mg_gamma0 + mg_s - 1) mu) / D^3 (mu > 0; c0^2 else)
+ * + mg_gamma0 rho0 max(p_u, 0) / rho^2 with p_u the pressure before the
+ * cut-off, and c = sqrt(cb^2 + 4G / (3 rho)).  K is not read.  beta scales
+ * the acoustic Riemann solver's dissipation (1 = the linearised Riemann
+ * solution).  Walls: bit 2d of wall_mask reflects at wall_lo[d], bit 2d+1 at
+ * wall_hi[d]. */
 typedef struct sph_params {
     double h, rho0, c0, gamma, K, G, Y0, H, beta, cfl;
     double gravity[3], wall_lo[3], wall_hi[3];
     uint32_t wall_mask;
     int32_t material;      /* sph_material  */
     int32_t prec;          /* sph_precision */
-    int32_t reserved;
+    int32_t eos;           /* sph_solid_eos (solids; fluids ignore it) */
+    double mg_s, mg_gamma0, p_cut;   /* Mie-Gruneisen constants and cut-off */
 } sph_params;
 
 /* One particle array in structure-of-arrays form, n entries per field.

@@ -34,7 +34,9 @@ class OParams(C.Structure):
                 ("gamma", C.c_double), ("K", C.c_double), ("G", C.c_double),
                 ("Y0", C.c_double), ("H", C.c_double), ("beta", C.c_double),
                 ("cfl", C.c_double), ("g", C.c_double * 3), ("wlo", C.c_double * 3),
-                ("whi", C.c_double * 3), ("wall_mask", C.c_int32), ("material", C.c_int32)]
+                ("whi", C.c_double * 3), ("wall_mask", C.c_int32), ("material", C.c_int32),
+                ("eos", C.c_int32), ("pad", C.c_int32), ("mg_s", C.c_double), ("mg_gamma0", C.c_double),
+                ("p_cut", C.c_double)]
 
 
 _dp = C.POINTER(C.c_double)
@@ -60,7 +62,7 @@ def _declare(L):
     L.or_kernel_W.restype = C.c_double
     L.or_kernel_F.argtypes = [C.c_double, C.c_double]
     L.or_kernel_F.restype = C.c_double
-    L.or_eos.argtypes = [C.POINTER(OParams), C.c_double, _dp, _dp]
+    L.or_eos.argtypes = [C.POINTER(OParams), C.c_double, C.c_double, _dp, _dp]
     L.or_pair.argtypes = [C.POINTER(OParams), vp, vp, vp] + [C.c_double] * 10 + [vp, vp, vp]
     L.or_pair_grad.argtypes = [C.POINTER(OParams), vp, vp, vp, C.c_double, vp]
     L.or_interact.argtypes = [C.POINTER(OParams), C.POINTER(OGrid), C.c_int, C.POINTER(OState),
@@ -112,6 +114,9 @@ def params_struct(p: dict) -> OParams:
         s.whi[d] = p["wall_hi"][d]
     s.wall_mask = int(p["wall_mask"])
     s.material = int(p["material"])
+    s.eos = int(p.get("eos", 0))
+    for k in ("mg_s", "mg_gamma0", "p_cut"):
+        setattr(s, k, float(p.get(k, 0.0)))
     return s
 
 
@@ -250,10 +255,12 @@ def kernel_F(r: float, h: float) -> float:
     return lib().or_kernel_F(r, h)
 
 
-def eos(params: dict, rho: float):
+def eos(params: dict, rho: float, e: float = 0.0):
+    """(p, c) at density rho and specific internal energy e (e matters only
+    for the Mie-Gruneisen solid)."""
     p, c = C.c_double(), C.c_double()
     P = params_struct(params)
-    lib().or_eos(C.byref(P), rho, C.byref(p), C.byref(c))
+    lib().or_eos(C.byref(P), rho, e, C.byref(p), C.byref(c))
     return p.value, c.value
 
 

@@ -68,6 +68,8 @@ typedef struct {
     double h, rho0, c0, gamma, K, G, Y0, H, beta, cfl;
     double g[3], wlo[3], whi[3];
     int32_t wall_mask, material; /* material 0 = Tait fluid, 1 = J2 solid */
+    int32_t eos, pad;            /* solids: 0 = linear, 1 = Mie-Gruneisen */
+    double mg_s, mg_gamma0, p_cut;
 } op_t;
 
 typedef struct {
@@ -218,20 +220,54 @@ double or_kernel_F(double r, double h)
 
 /* --------------------------------------------------------------- EOS */
 
-static void eos(const op_t *P, double rho, double *p, double *c)
+/* Mie-Gruneisen (Section IV.A names it, with a cut-off pressure for
+ * spalling; the paper gives no formula).  Reference curve: the shock
+ * Hugoniot of a linear shock-velocity law Us = c0 + s up, which in
+ * mu = rho / rho0 - 1 reads pH = rho0 c0^2 mu (1 + mu) / (1 - (s - 1) mu)^2
+ * with specific energy eH = pH mu / (2 rho0 (1 + mu)); off the Hugoniot
+ * p = pH + Gamma0 rho0 (e - eH) (Gamma rho held at Gamma0 rho0), which
+ * simplifies to the form below.  In tension the linear branch rho0 c0^2 mu.
+ * The pole of the Hugoniot is kept away by D >= 1/16.  Sound speed:
+ * cb^2 = dp/drho at fixed e + (p / rho^2) dp/de, with dp/de = Gamma0 rho0,
+ * the thermal part taken on max(p, 0); the longitudinal speed adds 4G/(3 rho). */
+static void eos_mie_gruneisen(const op_t *P, double rho, double e, double *p, double *c)
+{
+    double mu = rho / P->rho0 - 1.0;
+    double dpde = P->mg_gamma0 * P->rho0;
+    double pu, dpdrho;
+    if (mu > 0.0) {
+        double b = P->mg_s - 1.0;
+        double D = 1.0 - b * mu;
+        if (D < 0.0625) D = 0.0625;
+        double a = 1.0 - 0.5 * P->mg_gamma0;
+        /* f(mu) = mu (1 + a mu) / D^2, f'(mu) = (1 + (2a + b) mu) / D^3 */
+        pu = P->rho0 * P->c0 * P->c0 * (mu * (1.0 + a * mu) / (D * D)) + dpde * e;
+        dpdrho = P->c0 * P->c0 * ((1.0 + (2.0 * a + b) * mu) / (D * D * D));
+    } else {
+        pu = P->rho0 * P->c0 * P->c0 * mu + dpde * e;
+        dpdrho = P->c0 * P->c0;
+    }
+    double cb2 = dpdrho + (pu > 0.0 ? pu : 0.0) * dpde / (rho * rho);
+    *p = pu > P->p_cut ? pu : P->p_cut;
+    *c = sqrt(cb2 + 4.0 * P->G / (3.0 * rho));
+}
+
+static void eos(const op_t *P, double rho, double e, double *p, double *c)
 {
     if (P->material == 0) {
         double B = P->rho0 * P->c0 * P->c0 / P->gamma;
         double s = rho / P->rho0;
         *p = B * (pow(s, P->gamma) - 1.0);
         *c = P->c0 * pow(s, 0.5 * (P->gamma - 1.0));
+    } else if (P->eos == 1) {
+        eos_mie_gruneisen(P, rho, e, p, c);
     } else {
         *p = P->K * (rho / P->rho0 - 1.0);
         *c = sqrt((P->K + 4.0 * P->G / 3.0) / P->rho0);
     }
 }
 
-void or_eos(const op_t *P, double rho, double *p, double *c) { eos(P, rho, p, c); }
+void or_eos(const op_t *P, double rho, double e, double *p, double *c) { eos(P, rho, e, p, c); }
 
 /* ---------------------------------------------------------- pair terms */
 
@@ -510,8 +546,9 @@ enum { OR_MOTION = 0, OR_STRESS = 1, OR_EOS = 2 };
 
 static void finish_particle(const op_t *P, const os_t *s, int64_t i)
 {
+    const double *v = s->v + 3 * i;
     s->rho[i] = s->m[i] / s->w[i];
-    eos(P, s->rho[i], &s->p[i], &s->c[i]);
+    eos(P, s->rho[i], s->E[i] - 0.5 * ((v[0] * v[0] + v[1] * v[1]) + v[2] * v[2]), &s->p[i], &s->c[i]);
 }
 
 /* diag: [0] dt_next = cfl h / max(c + |v|), [1] sum m, [2..4] sum m v,

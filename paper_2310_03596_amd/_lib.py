@@ -17,6 +17,7 @@ SPH_FP64, SPH_FP32_SPLIT = 0, 1
 SPH_FLUID_TAIT, SPH_SOLID_J2 = 0, 1
 SPH_PASS_FORCE, SPH_PASS_GRADIENT = 0, 1
 SPH_STAGE_MOTION, SPH_STAGE_STRESS, SPH_STAGE_EOS = 0, 1, 2
+SPH_EOS_LINEAR, SPH_EOS_MIE_GRUNEISEN = 0, 1
 SPH_MAX_TYPES = 8   # particle types of the per-type balancing calls
 
 _vp = C.c_void_p
@@ -32,7 +33,8 @@ class SphParams(C.Structure):
                 ("K", C.c_double), ("G", C.c_double), ("Y0", C.c_double), ("H", C.c_double),
                 ("beta", C.c_double), ("cfl", C.c_double), ("gravity", C.c_double * 3),
                 ("wall_lo", C.c_double * 3), ("wall_hi", C.c_double * 3), ("wall_mask", C.c_uint32),
-                ("material", C.c_int32), ("prec", C.c_int32), ("reserved", C.c_int32)]
+                ("material", C.c_int32), ("prec", C.c_int32), ("eos", C.c_int32), ("mg_s", C.c_double),
+                ("mg_gamma0", C.c_double), ("p_cut", C.c_double)]
 
 
 class SphParticles(C.Structure):

@@ -64,8 +64,16 @@ bool make_params(const sph_params *sp, const sph_grid *sg, Params &P)
     if (!(sp->rho0 > 0.0)) return fail(SPH_ERR_ARG, "rho0 must be > 0"), false;
     if (sp->material == SPH_FLUID_TAIT && !(sp->gamma > 0.0 && sp->c0 > 0.0))
         return fail(SPH_ERR_ARG, "Tait fluid needs gamma > 0 and c0 > 0"), false;
-    if (sp->material == SPH_SOLID_J2 && !(sp->K > 0.0 && sp->G > 0.0))
-        return fail(SPH_ERR_ARG, "J2 solid needs K > 0 and G > 0"), false;
+    if (sp->material == SPH_SOLID_J2) {
+        if (sp->eos != SPH_EOS_LINEAR && sp->eos != SPH_EOS_MIE_GRUNEISEN)
+            return fail(SPH_ERR_ARG, "unknown solid EOS %d", sp->eos), false;
+        if (sp->eos == SPH_EOS_LINEAR && !(sp->K > 0.0 && sp->G > 0.0))
+            return fail(SPH_ERR_ARG, "J2 solid needs K > 0 and G > 0"), false;
+        if (sp->eos == SPH_EOS_MIE_GRUNEISEN &&
+            !(sp->c0 > 0.0 && sp->G > 0.0 && sp->mg_s >= 1.0 && sp->mg_gamma0 >= 0.0 && sp->p_cut <= 0.0))
+            return fail(SPH_ERR_ARG, "Mie-Gruneisen solid needs c0 > 0, G > 0, mg_s >= 1, mg_gamma0 >= 0, p_cut <= 0"),
+                   false;
+    }
     double R = 2.0 * sp->h;
     if (sg && sg->cell < R)
         return fail(SPH_ERR_ARG, "bucket side %g is smaller than the support 2h = %g", sg->cell, R), false;
@@ -91,6 +99,10 @@ bool make_params(const sph_params *sp, const sph_grid *sg, Params &P)
     P.Fc = (1.0 / (M_PI * sp->h * sp->h * sp->h)) / sp->h;
     P.B = sp->material == SPH_FLUID_TAIT ? sp->rho0 * sp->c0 * sp->c0 / sp->gamma : 0.0;
     P.c_solid = sp->material == SPH_SOLID_J2 ? sqrt((sp->K + 4.0 * sp->G / 3.0) / sp->rho0) : 0.0;
+    P.eos = sp->material == SPH_SOLID_J2 ? sp->eos : SPH_EOS_LINEAR;
+    P.mg_s = sp->mg_s;
+    P.mg_gamma0 = sp->mg_gamma0;
+    P.p_cut = sp->p_cut;
     P.gamma_odd = 0;
     for (int k = 1; k < 16; k += 2)
         if (sp->gamma == (double)k) P.gamma_odd = k;

@@ -50,7 +50,9 @@ struct Params {
     double hinv;          // 1 / h
     double Fc;            // 1 / (pi h^4): F = Fc f(q)
     double B;             // Tait stiffness rho0 c0^2 / gamma
-    double c_solid;       // solid sound speed
+    double c_solid;       // solid sound speed (linear EOS)
+    int eos;              // sph_solid_eos
+    double mg_s, mg_gamma0, p_cut;
     int gamma_odd;        // gamma when it is an odd integer in [1, 15] (powers by products), else 0
 };
 

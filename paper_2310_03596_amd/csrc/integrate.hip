@@ -13,14 +13,41 @@ namespace sph {
 
 namespace {
 
+// Mie-Gruneisen EOS of a solid with the linear shock-velocity Hugoniot
+// (Us = c0 + s up) as reference and Gamma rho = Gamma0 rho0, a spall cut-off
+// and the longitudinal sound speed (bulk plus shear).  Section IV.A names the
+// EOS and the cut-off; the form is the usual one for metals.
+__device__ inline void eos_mie_gruneisen(const Params &P, double rho, double e, double &p, double &c)
+{
+#pragma clang fp contract(off)
+    const double mu = rho / P.rho0 - 1.0;
+    const double k0 = P.rho0 * P.c0 * P.c0;
+    const double th = P.mg_gamma0 * P.rho0 * e;
+    double pu, cb2;
+    if (mu > 0.0) {
+        const double b = P.mg_s - 1.0;
+        const double D = fmax(1.0 - b * mu, 0.0625);
+        pu = k0 * mu * (1.0 + (1.0 - 0.5 * P.mg_gamma0) * mu) / (D * D) + th;
+        cb2 = P.c0 * P.c0 * (1.0 + (2.0 - P.mg_gamma0 + b) * mu) / (D * D * D);
+    } else {
+        pu = k0 * mu + th;
+        cb2 = P.c0 * P.c0;
+    }
+    cb2 += P.mg_gamma0 * P.rho0 * fmax(pu, 0.0) / (rho * rho);
+    p = fmax(pu, P.p_cut);
+    c = sqrt(cb2 + 4.0 * P.G / (3.0 * rho));
+}
+
 template <typename real>
-__device__ inline void eos(const Params &P, double rho, double &p, double &c)
+__device__ inline void eos(const Params &P, double rho, double e, double &p, double &c)
 {
     if (P.material == SPH_FLUID_TAIT) {
         double sg, sh;
         tait_powers<real>(P, rho / P.rho0, sg, sh);
         p = P.B * (sg - 1.0);
         c = P.c0 * sh;
+    } else if (P.eos == SPH_EOS_MIE_GRUNEISEN) {
+        eos_mie_gruneisen(P, rho, e, p, c);
     } else {
         p = P.K * (rho / P.rho0 - 1.0);
         c = P.c_solid;
@@ -59,13 +86,14 @@ __device__ inline void finish(const Params &P, const PV<real> &s, uint32_t i, do
                               double E, double rec[kDiag])
 {
     double rho = m / w;
-    double p, c;
-    eos<real>(P, rho, p, c);
     double v2 = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+    const double e = E - 0.5 * v2;
+    double p, c;
+    eos<real>(P, rho, e, p, c);
     s.rho[i] = (real)rho;
     s.p[i] = (real)p;
     s.c[i] = (real)c;
-    s.e[i] = (real)(E - 0.5 * v2);
+    s.e[i] = (real)e;
     rec[0] = c + sqrt(v2);
     rec[1] = m;
     rec[2] = m * v[0];

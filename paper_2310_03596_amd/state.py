@@ -42,6 +42,9 @@ def params_struct(p: dict, prec: int) -> L.SphParams:
     s.wall_mask = int(p["wall_mask"])
     s.material = int(p["material"])
     s.prec = int(prec)
+    s.eos = int(p.get("eos", L.SPH_EOS_LINEAR))
+    for k in ("mg_s", "mg_gamma0", "p_cut"):
+        setattr(s, k, float(p.get(k, 0.0)))
     return s
 
 

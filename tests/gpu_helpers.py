@@ -73,9 +73,11 @@ def assert_within(got, ref, bound, what=""):
 
 def pressure_scale(params: dict) -> float:
     """Scale of the terms whose difference is p: gamma B for Tait (p = B (s^gamma - 1)
-    cancels near s = 1), K for the linear solid EOS."""
+    cancels near s = 1), K for the linear solid EOS, rho0 c0^2 for Mie-Gruneisen."""
     if params["material"] == S.FLUID_TAIT:
         return params["gamma"] * params["rho0"] * params["c0"] ** 2 / params["gamma"]
+    if params.get("eos", S.EOS_LINEAR) == S.EOS_MIE_GRUNEISEN:
+        return params["rho0"] * params["c0"] ** 2
     return params["K"]
 
 
