@@ -162,50 +162,46 @@ __global__ __launch_bounds__(kBlock) void k_eos(Params P, PV<real> s, double *__
     block_reduce_record(rec, partials + (size_t)blockIdx.x * kDiagPartial);
 }
 
-// The final fold of the per-block records: one workgroup of 1024 threads;
-// every thread issues the loads of up to four records (b, b + 1024, ...)
-// before it folds them, so the records arrive in one round trip instead of
-// one per record.  Folded in a fixed order (within a thread, then a fixed
-// tree), so the diagnostics are deterministic.
+// The final fold of the per-block records: one workgroup of 1024 threads
+// reads the records as one flat array in coalesced order, so thread t folds
+// component t % kDiagPartial of every (1024 / kDiagPartial)-th record.  The
+// records were written on every XCD, so each read goes to memory: a thread
+// issues up to 16 reads before it folds them, and the fold takes one or two
+// round trips instead of one per read.  The values in order, then the lanes
+// holding the same component (a fixed butterfly), then the wavefronts (in
+// order) are combined, so the diagnostics are deterministic.  Slot 0 folds
+// by max, the others by sum.
 constexpr int kFinalBlock = 1024;
+static_assert(kFinalBlock % kDiagPartial == 0 && kWave % kDiagPartial == 0, "components stay on their lanes");
 __global__ __launch_bounds__(kFinalBlock) void k_diag_final(const double *__restrict__ partials, uint32_t nblocks,
                                                             double cfl_h, double *__restrict__ diag)
 {
-    constexpr int kU = 4;
-    double acc[kDiag] = {};
-    for (uint32_t b0 = threadIdx.x; b0 < nblocks; b0 += kU * kFinalBlock) {
-        double q[kU][kDiag];
+    const uint32_t t = threadIdx.x;
+    const bool is_max = t % kDiagPartial == 0;
+    const uint32_t total = nblocks * kDiagPartial;
+    auto fold = [&](double a, double b) { return is_max ? fmax(a, b) : a + b; };
+    constexpr int kU = 16;
+    double a = 0.0;
+    for (uint32_t f0 = t; f0 < total; f0 += kU * kFinalBlock) {
+        double q[kU];
 #pragma unroll
         for (int u = 0; u < kU; ++u) {
-            const uint32_t b = b0 + (uint32_t)u * kFinalBlock;
-#pragma unroll
-            for (int k = 0; k < kDiag; ++k) q[u][k] = b < nblocks ? partials[(size_t)b * kDiagPartial + k] : 0.0;
+            const uint32_t f = f0 + (uint32_t)u * kFinalBlock;
+            q[u] = f < total ? partials[f] : 0.0;
         }
 #pragma unroll
-        for (int u = 0; u < kU; ++u) {
-            acc[0] = fmax(acc[0], q[u][0]);
-#pragma unroll
-            for (int k = 1; k < kDiag; ++k) acc[k] += q[u][k];
-        }
+        for (int u = 0; u < kU; ++u) a = fold(a, q[u]);
     }
-    __shared__ double sh[kDiag][kFinalBlock / kWave];
-    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
 #pragma unroll
-    for (int k = 0; k < kDiag; ++k) {
-        double v = acc[k];
-#pragma unroll
-        for (int off = kWave / 2; off > 0; off >>= 1) {
-            const double o = __shfl_down(v, off, kWave);
-            v = (k == 0) ? fmax(v, o) : v + o;
-        }
-        if (lane == 0) sh[k][wave] = v;
-    }
+    for (int off = kDiagPartial; off < kWave; off <<= 1) a = fold(a, __shfl_xor(a, off, kWave));
+    __shared__ double sh[kFinalBlock / kWave][kDiagPartial];
+    const int lane = t & (kWave - 1), wave = t / kWave;
+    if (lane < kDiagPartial) sh[wave][lane] = a;
     __syncthreads();
-    if (threadIdx.x < kDiag) {
-        const int k = threadIdx.x;
-        double v = sh[k][0];
-        for (int w = 1; w < kFinalBlock / kWave; ++w) v = (k == 0) ? fmax(v, sh[k][w]) : v + sh[k][w];
-        diag[k] = k == 0 ? (v > 0.0 ? cfl_h / v : __builtin_huge_val()) : v;
+    if (t < kDiag) {
+        double v = sh[0][t];
+        for (int w = 1; w < kFinalBlock / kWave; ++w) v = t == 0 ? fmax(v, sh[w][t]) : v + sh[w][t];
+        diag[t] = t == 0 ? (v > 0.0 ? cfl_h / v : __builtin_huge_val()) : v;
     }
 }
 

@@ -64,7 +64,7 @@ constexpr int kMaxWin = 12;                // staged pages whose hits a list can
 // the cases on the column workload.
 template <typename real>
 struct Tune {
-    static constexpr int page = sizeof(real) == 4 ? 160 : 80;
+    static constexpr int page = 160;
     static constexpr int cap = 88;
 };
 static_assert(Tune<float>::page + kSub <= 256 && Tune<double>::page + kSub <= 256, "page index must fit a u8 entry");
@@ -112,6 +112,16 @@ __device__ inline void wave_lds_sync()
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// A wave-uniform double held in scalar registers (it is an operand of
+// vector instructions, so it takes no vector registers of its own).
+__device__ inline double uniform_double(double v)
+{
+    const uint64_t b = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)b);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(b >> 32));
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
 }
 
 __device__ inline int wave_min(int v)
@@ -226,7 +236,7 @@ void k_pairs(Params P, Grid g, PV<real> tg, const uint32_t *__restrict__ tidx, c
     // per lane, one mark per page in which it has hits: (slot << 8) | list fill
     // at the end of that page's hits
     __shared__ uint16_t marks[kMaxWin][kWaves / 2][kWave][2];
-    __shared__ v4 stage[kWaves][kPage + kSub];    // a page, then far sentinels
+    __shared__ float4 stage[kWaves][kPage + kSub];   // a page, then far sentinels
     // per staged page: its first source index and (c_j - c_i) L in y and z of
     // its row (split form; the FP64 form works on absolute positions), side by
     // side so that one address serves the three reads
@@ -430,7 +440,7 @@ void k_pairs(Params P, Grid g, PV<real> tg, const uint32_t *__restrict__ tidx, c
         npg = 0;
     };
 
-    const real kFar = SPLIT ? real(1e30f) : real(1e300);
+    const float kFar = 1e30f;
 
     uint64_t pending = __ballot(valid);
     while (pending) {
@@ -441,32 +451,42 @@ void k_pairs(Params P, Grid g, PV<real> tg, const uint32_t *__restrict__ tidx, c
         pending &= ~__ballot(in);
         const int gx0 = wave_min(in ? x0 : 0x7FFFFFFF);
         const int gx1 = wave_max(in ? x1 : -1);
-        const int gy = (int)(key % (uint32_t)g.ny), gz = (int)(key / (uint32_t)g.ny);
-        // Filter frame.  Split form: positions relative to the corner of bucket
-        // (gx0, gy, gz), ((c - gx0) L + off) in x and (dy L + off) in y, z;
-        // FP64: absolute positions.  The test is the expanded form
+        // Filter frame, in FP32 in both forms: positions relative to the
+        // corner of bucket (gx0, gy, gz); split form ((c - gx0) L + off) in x
+        // and (dy L + off) in y, z; FP64 form (x - corner) in FP64, rounded
+        // once to float.  The test is the expanded form
         // |q|^2 - 2 q.f < R2 - |f|^2, with (2q, |q|^2) staged for each record,
-        // so a candidate costs three FMAs and a compare.  For a candidate within 2h
-        // of the target (|q| <= |f| + 2h) its rounding, with that of the
-        // frame, stays below 2^-18 (|f| + 2h)^2 in FP32 and 2^-46 (...)^2 in
-        // FP64; the bound is widened by four times that, so the shortlist
-        // keeps every neighbour.  The pair body applies the neighbour
-        // predicate itself, on the exact, odd d.
-        real fo[3];
-        const real gx0f = (real)gx0;
+        // so a candidate costs three FMAs and a compare.  For a candidate
+        // within 2h of the target (|q| <= |f| + 2h) its rounding, with that of
+        // the frame, stays below 2^-18 (|f| + 2h)^2; the bound is widened by
+        // four times that, and in FP64 also by 2^-46 X (|f| + 2h) with
+        // X = |corner|_1 + |f| + 2h, over ten times the rounding of the FP64
+        // differences.  So the shortlist keeps every neighbour, and the FP64
+        // form's sums are those an FP64 filter would give.  The pair body
+        // applies the neighbour predicate itself, on the exact, odd d.
+        float fo[3];
+        const int gy = (int)(key % (uint32_t)g.ny), gz = (int)(key / (uint32_t)g.ny);
+        const float gx0f = (float)gx0;
+        double corner[3] = {0.0, 0.0, 0.0};
         if constexpr (SPLIT) {
             fo[0] = (T.cxf - gx0f) * T.Lf + T.o[0];
             fo[1] = T.o[1];
             fo[2] = T.o[2];
         } else {
-            fo[0] = T.x[0];
-            fo[1] = T.x[1];
-            fo[2] = T.x[2];
+            corner[0] = uniform_double(g.o[0] + (double)gx0 * g.L);
+            corner[1] = uniform_double(g.o[1] + (double)gy * g.L);
+            corner[2] = uniform_double(g.o[2] + (double)gz * g.L);
+#pragma unroll
+            for (int d = 0; d < 3; ++d) fo[d] = (float)(T.x[d] - corner[d]);
         }
-        const real f2 = fo[0] * fo[0] + fo[1] * fo[1] + fo[2] * fo[2];
-        const real fl = sqrt(f2) + (real)(2.0 * P.h);
-        const real margin = (SPLIT ? real(0x1p-16) : real(0x1p-44)) * fl * fl;
-        const real Tl = in ? (R2 - f2) + margin : -kFar;
+        const float f2 = fo[0] * fo[0] + fo[1] * fo[1] + fo[2] * fo[2];
+        const float fl = sqrtf(f2) + (float)(2.0 * P.h);
+        float margin = 0x1p-16f * fl * fl;
+        if constexpr (!SPLIT) {
+            const float X = (float)(fabs(corner[0]) + fabs(corner[1]) + fabs(corner[2])) + fl;
+            margin += 0x1p-46f * X * fl;
+        }
+        const float Tl = in ? ((float)R2 - f2) + margin : -kFar;
         int nwin = 0;
         for (int r = 0; r < 9; ++r) {
             const int dz = r / 3 - 1, dy = r % 3 - 1;
@@ -494,20 +514,24 @@ void k_pairs(Params P, Grid g, PV<real> tg, const uint32_t *__restrict__ tidx, c
                 // kPage + kSub so that every read below stays in the array and
                 // nothing past the page can pass a test
                 for (uint32_t u = (uint32_t)lane; u < (uint32_t)(kPage + kSub); u += kWave) {
-                    v4 rec;
+                    float4 rec;
                     if (u < len) {
-                        rec = src.pos[pb + u];
+                        const v4 sp = src.pos[pb + u];
                         if constexpr (SPLIT) {
-                            rec.x = (rec.w - gx0f) * T.Lf + rec.x;
-                            rec.y = ddy + rec.y;
-                            rec.z = ddz + rec.z;
+                            rec.x = (sp.w - gx0f) * T.Lf + sp.x;
+                            rec.y = ddy + sp.y;
+                            rec.z = ddz + sp.z;
+                        } else {
+                            rec.x = (float)(sp.x - corner[0]);
+                            rec.y = (float)(sp.y - corner[1]);
+                            rec.z = (float)(sp.z - corner[2]);
                         }
                         rec.w = rec.x * rec.x + rec.y * rec.y + rec.z * rec.z;
-                        rec.x *= real(2);   // staged as (2q, |q|^2)
-                        rec.y *= real(2);
-                        rec.z *= real(2);
+                        rec.x *= 2.0f;   // staged as (2q, |q|^2)
+                        rec.y *= 2.0f;
+                        rec.z *= 2.0f;
                     } else {
-                        rec.x = rec.y = rec.z = real(0);
+                        rec.x = rec.y = rec.z = 0.0f;
                         rec.w = kFar;
                     }
                     stage[wave][u] = rec;
@@ -545,8 +569,8 @@ void k_pairs(Params P, Grid g, PV<real> tg, const uint32_t *__restrict__ tidx, c
                     const int base = a + k0;
 #pragma unroll
                     for (int m = 0; m < kSub; ++m) {
-                        const v4 q = stage[wave][base + m];
-                        const real t = fma(-q.z, fo[2], fma(-q.y, fo[1], fma(-q.x, fo[0], q.w)));
+                        const float4 q = stage[wave][base + m];
+                        const float t = fmaf(-q.z, fo[2], fmaf(-q.y, fo[1], fmaf(-q.x, fo[0], q.w)));
                         // the entry is written always and kept only when it is a hit
                         hits[cnt][wave / kHitWaves][lane][wave % kHitWaves] = (uint8_t)(base + m);
                         cnt += (t < Tl) ? 1 : 0;
