@@ -46,29 +46,47 @@ __global__ __launch_bounds__(kBlock) void k_gather(Grid g, PV<real> in, PV<real>
 {
     uint32_t k = blockIdx.x * kBlock + threadIdx.x;
     if (k >= in.n) return;
-    uint32_t s = vals[k];
-    uint32_t h = keys[k];
-    perm[k] = s;
-    out.hash[k] = h;
-    out.id[k] = in.id[s];
+    const uint32_t s = vals[k];
+    const uint32_t h = keys[k];
+    // every read is issued before the first write: the writes could alias
+    // the reads as far as the compiler knows, and a read issued after a write
+    // would wait for the write's round trip
+    const uint32_t id = in.id[s];
     double x[3];
+    real v[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
         x[d] = in.x[d][s];
-        out.x[d][k] = x[d];
-        out.v[d][k] = in.v[d][s];
+        v[d] = in.v[d][s];
     }
-    out.m[k] = in.m[s];
-    out.w[k] = in.w[s];
-    out.rho[k] = in.rho[s];
-    out.p[k] = in.p[s];
-    out.c[k] = in.c[s];
-    out.e[k] = in.e[s];
-    out.E[k] = in.E[s];
-    if (in.S[0]) {
+    const real m = in.m[s], w = in.w[s], rho = in.rho[s], p = in.p[s], c = in.c[s], e = in.e[s];
+    const double E = in.E[s];
+    const bool solid = in.S[0] != nullptr;
+    real S[6] = {}, ep = 0;
+    if (solid) {
 #pragma unroll
-        for (int q = 0; q < 6; ++q) out.S[q][k] = in.S[q][s];
-        out.ep[k] = in.ep[s];
+        for (int q = 0; q < 6; ++q) S[q] = in.S[q][s];
+        ep = in.ep[s];
+    }
+    perm[k] = s;
+    out.hash[k] = h;
+    out.id[k] = id;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        out.x[d][k] = x[d];
+        out.v[d][k] = v[d];
+    }
+    out.m[k] = m;
+    out.w[k] = w;
+    out.rho[k] = rho;
+    out.p[k] = p;
+    out.c[k] = c;
+    out.e[k] = e;
+    out.E[k] = E;
+    if (solid) {
+#pragma unroll
+        for (int q = 0; q < 6; ++q) out.S[q][k] = S[q];
+        out.ep[k] = ep;
     }
     if (split) {
         uint32_t cx = h % (uint32_t)g.nx;

@@ -116,16 +116,21 @@ __global__ __launch_bounds__(kBlock) void k_motion(Params P, PV<real> s, RV<real
         for (int k = 0; k < 6; ++k) r[k] = (double)R.hi[k][i] + (SPLIT ? (double)R.lo[k][i] : 0.0);
         double m = (double)s.m[i];
         double v[3] = {(double)s.v[0][i], (double)s.v[1][i], (double)s.v[2][i]};
+        // every input is read before the first store: the stores below could
+        // alias them as far as the compiler knows, and reads issued after a
+        // store would each wait a full memory round trip
+        const double x0[3] = {s.x[0][i], s.x[1][i], s.x[2][i]};
+        const double E0 = s.E[i], w0 = (double)s.w[i];
         double mn = m + dt * r[0];
         double gv = P.g[0] * v[0] + P.g[1] * v[1] + P.g[2] * v[2];
         double vn[3];
 #pragma unroll
         for (int a = 0; a < 3; ++a) vn[a] = (m * v[a] + dt * (r[1 + a] + m * P.g[a])) / mn;
-        double En = (m * s.E[i] + dt * (r[4] + m * gv)) / mn;
-        double wn = (double)s.w[i] + dt * r[5];
+        double En = (m * E0 + dt * (r[4] + m * gv)) / mn;
+        double wn = w0 + dt * r[5];
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            double xn = s.x[a][i] + dt * vn[a];
+            double xn = x0[a] + dt * vn[a];
             if ((P.wall_mask >> (2 * a)) & 1u)
                 if (xn < P.wlo[a]) {
                     xn = 2.0 * P.wlo[a] - xn;
