@@ -117,6 +117,7 @@ def time_form(wl, prec, steps, warmup):
         "flops_per_launch": flops,
         "force_tflops": flops / (force_ms * 1e-3) / 1e12,
         "pair_evals_per_s": pairs / (force_ms * 1e-3),
+        "candidates_per_s": cand / (force_ms * 1e-3),
         "diag": sim.diagnostics().tolist(),
     }
 
@@ -292,6 +293,15 @@ def cpu_leg(wl, budget_s):
     dts_all = np.concatenate([dts1, dts2])
     t_total = t1 + tm
     ref = st.by_id()
+    # the same oracle on one host thread, a few steps from the initial state
+    threads = cpu.num_threads()
+    cpu.set_threads(1)
+    s1 = cpu.State.from_workload(wl)
+    n1 = max(1, min(3, int(budget_s / 3 / max(t1 * threads, 1e-3))))
+    t0 = time.perf_counter()
+    cpu.run(wl.params, wl.grid, s1, n1)
+    t_one = time.perf_counter() - t0
+    cpu.set_threads(threads)
     errs = {}
     for name, prec in (("fp32_split", 1), ("fp64", 0)):
         sim = Sim(wl, prec)
@@ -309,11 +319,13 @@ def cpu_leg(wl, budget_s):
     return {
         "value": wl.n * nsteps / t_total,
         "unit": "particle-updates/s",
-        "cores": cpu.num_threads(),
+        "cores": threads,
         "kind": "oracle",
         "sample": f"first {nsteps} steps of the same 810448-particle column from its initial state "
                   f"(FP64 C oracle, OpenMP over targets), {t_total:.1f} s",
         "steps": nsteps,
+        "value_1_thread": wl.n * n1 / t_one,
+        "sample_1_thread": f"first {n1} steps on one host thread, {t_one:.1f} s",
     }, {"steps": nsteps, "max_abs_err_over_max_abs_ref": errs}
 
 
@@ -361,6 +373,7 @@ def main():
                      "avg_launch_ms": r["force_ms"], "flops_per_launch": r["flops_per_launch"],
                      "units_per_launch": {"candidates": r["candidates"], "pairs_within_2h": r["pairs"]}},
         "pair_evals_per_s": r["pair_evals_per_s"],
+        "candidates_per_s": r["candidates_per_s"],
     })
     if 0 in res and 1 in res:
         out["fp64_form"] = {"value": res[0]["value"], "ms_per_step": res[0]["ms_per_step"],

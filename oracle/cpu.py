@@ -78,6 +78,7 @@ def _declare(L):
                          C.c_double, vp, vp, vp]
     L.or_run.restype = C.c_int
     L.or_num_threads.restype = C.c_int
+    L.or_set_threads.argtypes = [C.c_int]
     L.or_centroid.argtypes = [C.POINTER(OState), vp]
     L.or_balance_hash.argtypes = [C.POINTER(OState), vp, vp, C.c_uint32, vp]
     L.or_balance_hash.restype = C.c_int64
@@ -89,6 +90,11 @@ def _declare(L):
 def num_threads() -> int:
     """OpenMP threads the oracle's parallel loops use."""
     return int(lib().or_num_threads())
+
+
+def set_threads(n: int):
+    """Threads of the oracle's following parallel loops."""
+    lib().or_set_threads(int(n))
 
 
 def _ptr(a):

@@ -48,6 +48,16 @@
 #define M_PI 3.14159265358979323846
 #endif
 
+/* Sets the threads of the following OpenMP loops (no effect without OpenMP). */
+void or_set_threads(int n)
+{
+#ifdef _OPENMP
+    omp_set_num_threads(n > 0 ? n : 1);
+#else
+    (void)n;
+#endif
+}
+
 /* Threads the OpenMP loops use (1 without OpenMP). */
 int or_num_threads(void)
 {

@@ -23,7 +23,10 @@ __device__ inline uint32_t xcd_tile(uint32_t b, uint32_t n)
     const uint32_t q = n / kXcds, r = n % kXcds;
     return x * q + (x < r ? x : r) + k;
 }
-constexpr int kSortItems = 8;        // keys per thread in a radix-sort tile
+#ifndef SPH_SORT_ITEMS
+#define SPH_SORT_ITEMS 8
+#endif
+constexpr int kSortItems = SPH_SORT_ITEMS;   // keys per thread in a radix-sort tile
 constexpr int kSortTile = kBlock * kSortItems;
 constexpr int kMaxRadixBits = 10;     // digits of 8 to 10 bits: keys up to 20 bits sort in two passes
 constexpr int kMaxRadixBins = 1 << kMaxRadixBits;
