@@ -53,11 +53,28 @@ __global__ __launch_bounds__(kBlock) void k_upsweep(const uint32_t *__restrict__
     __shared__ uint32_t h[BINS];
     for (int b = threadIdx.x; b < BINS; b += kBlock) h[b] = 0;
     __syncthreads();
-    uint32_t base = blockIdx.x * kSortTile;
+    // Runs of equal digits in consecutive lanes add their length once (the
+    // keys arrive nearly sorted, step after step, so runs are long and the
+    // LDS atomics do not serialise on one address).
+    const int lane = threadIdx.x & (kWave - 1);
+    const uint32_t base = blockIdx.x * kSortTile;
+    uint32_t keyv[kSortItems];
 #pragma unroll
     for (int it = 0; it < kSortItems; ++it) {
-        uint32_t e = base + it * kBlock + threadIdx.x;
-        if (e < n) atomicAdd(&h[(keys[e] >> shift) & (BINS - 1)], 1u);
+        const uint32_t e = base + it * kBlock + threadIdx.x;
+        keyv[it] = e < n ? keys[e] : 0u;
+    }
+#pragma unroll
+    for (int it = 0; it < kSortItems; ++it) {
+        const uint32_t e = base + it * kBlock + threadIdx.x;
+        const bool valid = e < n;
+        const uint32_t d = valid ? (keyv[it] >> shift) & (BINS - 1) : (uint32_t)BINS;
+        const uint32_t prev = __shfl_up(d, 1, kWave);
+        const bool head = lane == 0 || d != prev;
+        const uint64_t heads = __ballot(head);
+        const uint64_t above = heads & ~((2ull << lane) - 1ull);   // heads past this lane (2 << 63 wraps to 0)
+        const int next = above ? __ffsll((unsigned long long)above) - 1 : kWave;
+        if (valid && head) atomicAdd(&h[d], (uint32_t)(next - lane));
     }
     __syncthreads();
     for (int b = threadIdx.x; b < BINS; b += kBlock) hist[(size_t)b * tiles + blockIdx.x] = h[b];
@@ -96,6 +113,17 @@ __global__ __launch_bounds__(kBlock) void k_downsweep(const uint32_t *__restrict
     __shared__ uint32_t run[BINS];
     __shared__ uint32_t cnt[NW][BINS];
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+    // the tile's keys and values are read first: their loads overlap the
+    // digit-base bookkeeping below and each other (a load issued inside the
+    // loop would wait out a full round trip behind every barrier)
+    const uint32_t base = blockIdx.x * kSortTile;
+    uint32_t keyv[kSortItems], valv[kSortItems];
+#pragma unroll
+    for (int it = 0; it < kSortItems; ++it) {
+        const uint32_t e = base + it * kBlock + tid;
+        keyv[it] = e < n ? kin[e] : 0u;
+        valv[it] = e < n ? vin[e] : 0u;
+    }
     // digit bases of this tile: exclusive scan of the digit totals (each
     // thread holds PT consecutive digits) plus the tile's offset in its digit
     uint32_t loc[PT];
@@ -117,23 +145,45 @@ __global__ __launch_bounds__(kBlock) void k_downsweep(const uint32_t *__restrict
     }
     __syncthreads();
     const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    const uint32_t base = blockIdx.x * kSortTile;
-    for (int it = 0; it < kSortItems; ++it) {
-        uint32_t e = base + it * kBlock + tid;
-        bool valid = e < n;
-        uint32_t key = valid ? kin[e] : 0u;
-        uint32_t val = valid ? vin[e] : 0u;
-        uint32_t d = (key >> shift) & (BINS - 1);
-        uint64_t mask = __ballot(valid);
 #pragma unroll
-        for (int b = 0; b < D; ++b) {
-            bool bit = (d >> b) & 1u;
-            uint64_t bm = __ballot(bit);
-            mask &= bit ? bm : ~bm;
+    for (int it = 0; it < kSortItems; ++it) {
+        const uint32_t e = base + it * kBlock + tid;
+        const bool valid = e < n;
+        const uint32_t key = keyv[it];
+        const uint32_t val = valv[it];
+        uint32_t d = (key >> shift) & (BINS - 1);
+        // Rank among the lanes of this wavefront with the same digit.  When the
+        // valid lanes' digits do not decrease (the usual case: the keys arrive
+        // nearly sorted), each digit is one run of lanes and the rank is the
+        // distance from the run's first lane; otherwise one ballot per digit
+        // bit gives each lane the mask of lanes holding its digit.
+        const uint32_t prev = __shfl_up(d, 1, kWave);
+        const uint64_t vmask = __ballot(valid);
+        uint32_t rank, count;
+        bool leader;
+        if (__ballot(valid && lane > 0 && d < prev) == 0ull) {
+            const bool head = valid && (lane == 0 || d != prev);
+            const uint64_t heads = __ballot(head) | ~vmask;   // invalid lanes end the last run
+            const uint64_t upto = heads & (lane == kWave - 1 ? ~0ull : ((2ull << lane) - 1ull));
+            const int start = 63 - __clzll((long long)upto);
+            const uint64_t above = heads & ~(lane == kWave - 1 ? ~0ull : ((2ull << lane) - 1ull));
+            const int next = above ? __ffsll((unsigned long long)above) - 1 : kWave;
+            rank = (uint32_t)(lane - start);
+            count = (uint32_t)(next - start);
+            leader = valid && next == lane + 1;
+        } else {
+            uint64_t mask = vmask;
+#pragma unroll
+            for (int b = 0; b < D; ++b) {
+                bool bit = (d >> b) & 1u;
+                uint64_t bm = __ballot(bit);
+                mask &= bit ? bm : ~bm;
+            }
+            rank = (uint32_t)__popcll(mask & below);
+            count = (uint32_t)__popcll(mask);
+            leader = valid && ((mask >> lane) == 1ull);
         }
-        uint32_t rank = (uint32_t)__popcll(mask & below);
-        bool leader = valid && ((mask >> lane) == 1ull);
-        if (leader) cnt[wave][d] = (uint32_t)__popcll(mask);
+        if (leader) cnt[wave][d] = count;
         __syncthreads();
         if (valid) {
             uint32_t pre = run[d];
