@@ -94,22 +94,28 @@ __device__ inline void finish(const Params &P, const PV<real> &s, uint32_t i, do
     s.p[i] = (real)p;
     s.c[i] = (real)c;
     s.e[i] = (real)e;
-    rec[0] = c + sqrt(v2);
-    rec[1] = m;
-    rec[2] = m * v[0];
-    rec[3] = m * v[1];
-    rec[4] = m * v[2];
-    rec[5] = m * E;
-    rec[6] = 0.5 * m * v2;
+    rec[0] = fmax(rec[0], c + sqrt(v2));
+    rec[1] += m;
+    rec[2] += m * v[0];
+    rec[3] += m * v[1];
+    rec[4] += m * v[2];
+    rec[5] += m * E;
+    rec[6] += 0.5 * m * v2;
 }
+
+// The update and EOS kernels run on at most kDiagBlocks workgroups, each
+// thread taking particles i, i + T, ... (T the grid's threads), so the final
+// fold of the per-workgroup records reads at most kDiagBlocks records in one
+// round trip; the records depend on n only, so the totals stay deterministic.
+constexpr uint32_t kDiagBlocks = 2048;
 
 template <typename real, bool SPLIT>
 __global__ __launch_bounds__(kBlock) void k_motion(Params P, PV<real> s, RV<real> R, const double *__restrict__ dtp,
                                                    double *__restrict__ partials)
 {
-    uint32_t i = blockIdx.x * kBlock + threadIdx.x;
     double rec[kDiag] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    if (i < s.n) {
+    const uint32_t stride = gridDim.x * kBlock;
+    for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < s.n; i += stride) {
         const double dt = *dtp;
         double r[6];
 #pragma unroll
@@ -158,9 +164,9 @@ __global__ __launch_bounds__(kBlock) void k_motion(Params P, PV<real> s, RV<real
 template <typename real>
 __global__ __launch_bounds__(kBlock) void k_eos(Params P, PV<real> s, double *__restrict__ partials)
 {
-    uint32_t i = blockIdx.x * kBlock + threadIdx.x;
     double rec[kDiag] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    if (i < s.n) {
+    const uint32_t stride = gridDim.x * kBlock;
+    for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < s.n; i += stride) {
         double v[3] = {(double)s.v[0][i], (double)s.v[1][i], (double)s.v[2][i]};
         finish<real>(P, s, i, (double)s.m[i], (double)s.w[i], v, s.E[i], rec);
     }
@@ -171,11 +177,11 @@ __global__ __launch_bounds__(kBlock) void k_eos(Params P, PV<real> s, double *__
 // reads the records as one flat array in coalesced order, so thread t folds
 // component t % kDiagPartial of every (1024 / kDiagPartial)-th record.  The
 // records were written on every XCD, so each read goes to memory: a thread
-// issues up to 16 reads before it folds them, and the fold takes one or two
-// round trips instead of one per read.  The values in order, then the lanes
-// holding the same component (a fixed butterfly), then the wavefronts (in
-// order) are combined, so the diagnostics are deterministic.  Slot 0 folds
-// by max, the others by sum.
+// issues up to 16 reads before it folds them, and the fold of at most
+// kDiagBlocks records takes one round trip instead of one per read.  The
+// values in order, then the lanes holding the same component (a fixed
+// butterfly), then the wavefronts (in order) are combined, so the
+// diagnostics are deterministic.  Slot 0 folds by max, the others by sum.
 constexpr int kFinalBlock = 1024;
 static_assert(kFinalBlock % kDiagPartial == 0 && kWave % kDiagPartial == 0, "components stay on their lanes");
 __global__ __launch_bounds__(kFinalBlock) void k_diag_final(const double *__restrict__ partials, uint32_t nblocks,
@@ -277,13 +283,14 @@ hipError_t go(const Params &P, int stage, const sph_particles &p, const sph_rate
         if (blocks) k_stress<real, SPLIT><<<blocks, kBlock, 0, s>>>(P, view<real>(p), view<real>(r), dt);
         return hipGetLastError();
     }
-    if (blocks) {
+    const uint32_t rblocks = blocks < kDiagBlocks ? blocks : kDiagBlocks;   // records: at most one per kBlock particles
+    if (rblocks) {
         if (stage == SPH_STAGE_MOTION)
-            k_motion<real, SPLIT><<<blocks, kBlock, 0, s>>>(P, view<real>(p), view<real>(r), dt, ws.partials);
+            k_motion<real, SPLIT><<<rblocks, kBlock, 0, s>>>(P, view<real>(p), view<real>(r), dt, ws.partials);
         else
-            k_eos<real><<<blocks, kBlock, 0, s>>>(P, view<real>(p), ws.partials);
+            k_eos<real><<<rblocks, kBlock, 0, s>>>(P, view<real>(p), ws.partials);
     }
-    if (diag) k_diag_final<<<1, kFinalBlock, 0, s>>>(ws.partials, blocks, P.cfl * P.h, diag);
+    if (diag) k_diag_final<<<1, kFinalBlock, 0, s>>>(ws.partials, rblocks, P.cfl * P.h, diag);
     return hipGetLastError();
 }
 
