@@ -837,14 +837,14 @@ int64_t or_balance_hash(const os_t *s, const double cg_own[3], const double cg_o
  * index: a stable counting sort by hmax - hash, first k entries. */
 int or_balance_select(int64_t n, const uint32_t *bhash, uint32_t hmax, int64_t k, uint32_t *sel)
 {
-    uint32_t *key = malloc(sizeof(uint32_t) * (n > 0 ? n : 1));
-    uint32_t *perm = malloc(sizeof(uint32_t) * (n > 0 ? n : 1));
+    uint32_t *key = calloc((size_t)(n > 0 ? n : 1), sizeof(uint32_t));
+    uint32_t *perm = calloc((size_t)(n > 0 ? n : 1), sizeof(uint32_t));
     if (!key || !perm) {
         free(key);
         free(perm);
         return -1;
     }
-    for (int64_t i = 0; i < n; ++i) key[i] = hmax - bhash[i];
+    for (int64_t i = 0; i < n; ++i) key[i] = hmax - (bhash[i] < hmax ? bhash[i] : hmax);
     or_sort_perm(n, key, hmax + 1, perm);
     for (int64_t t = 0; t < k && t < n; ++t) sel[t] = perm[t];
     free(key);
