@@ -69,6 +69,19 @@ def _faces():
     return w
 
 
+def _far_origin():
+    """A lattice 2 km from the coordinate origin (the grid moves with it): the
+    FP64 form's filter works on FP64 differences rounded to float, with a
+    margin that grows with the frame's distance from the origin."""
+    w = S.jittered_lattice(10, seed=57, rho_sigma=0.01)
+    shift = np.array([1000.0, -2000.0, 500.0])
+    w.x = w.x + shift
+    g = dict(w.grid)
+    g["origin"] = [float(o + d) for o, d in zip(g["origin"], shift)]
+    w.grid = g
+    return w
+
+
 CASES = {
     "one": lambda: S.random_cloud(1, seed=50, h=0.05),
     "cloud2049": lambda: S.random_cloud(2049, seed=53, h=0.04, rho_sigma=0.01),
@@ -77,6 +90,7 @@ CASES = {
     "clamped": _clamped_cloud,
     "dense": lambda: dense_cell_cloud(1500, seed=54),
     "lattice12": lambda: S.jittered_lattice(12, seed=55, rho_sigma=0.01),
+    "far_origin": _far_origin,
 }
 
 
@@ -109,7 +123,8 @@ def test_build_cells_bit_exact(case, prec):
 
 
 @pytest.mark.parametrize("prec", PRECS)
-@pytest.mark.parametrize("case", ["one", "cloud2049", "cube8000", "faces", "clamped", "dense", "lattice12"])
+@pytest.mark.parametrize("case", ["one", "cloud2049", "cube8000", "faces", "clamped", "dense", "lattice12",
+                                  "far_origin"])
 def test_force_pass_matches_oracle(case, prec):
     wl = CASES[case]()
     print(f"[force] case={case} prec={prec} n={wl.n}", flush=True)
