@@ -96,7 +96,6 @@ class KineticEnergyRollout:
         sim = self.sim
         n, prec, dev = sim.n, self.prec, self.device
         real = real_dtype(prec)
-        st = stream_handle()
         bar = Cotangent(n, prec, dev)
         tmp = Cotangent(n, prec, dev)
         # dJ/d(final state): J = sum m |v|^2 / 2
@@ -114,15 +113,30 @@ class KineticEnergyRollout:
         ws_adj_bytes = L.sph_workspace_size(sim.grid, n, prec, L.SPH_SOLID_J2)
         ws_adj = torch.zeros(ws_adj_bytes, dtype=torch.uint8, device=dev)
         fixed = sim.fixed.data_ptr()
-        # saved states of one segment, allocated once and reused by every segment:
-        # the sorted state before the update, its permutation, bucket table and rates
-        pool = [(Particles(n, prec, sim.solid, dev), torch.empty_like(sim.perm), torch.empty_like(sim.start),
-                 Rates(n, prec, False, dev)) for _ in range(min(self.ckpt, self.nsteps))]
-        for seg in reversed(range(len(self.ckpts))):
+        # The recompute of a segment (forward steps from its checkpoint, saving
+        # each step's sorted state, permutation, bucket table and rates) and the
+        # reverse sweep over the segment after it are independent, so they run
+        # on two streams and overlap: the recompute on the current stream, the
+        # reverse sweep on a second one (default priority).  Two pools of saved
+        # states alternate; a recompute waits until the reverse sweep that read
+        # its pool two segments earlier is done, and a reverse sweep waits for
+        # its segment's recompute.  The reverse sweep has its own workspace.
+        sa = torch.cuda.current_stream()
+        sb = torch.cuda.Stream(device=dev)
+        sb.wait_stream(sa)   # the cotangents were initialised on sa
+        st_a = stream_handle()
+        npool = min(self.ckpt, self.nsteps)
+        pools = [[(Particles(n, prec, sim.solid, dev), torch.empty_like(sim.perm), torch.empty_like(sim.start),
+                   Rates(n, prec, False, dev)) for _ in range(npool)] for _ in range(2)]
+        freed = [None, None]
+        for idx, seg in enumerate(reversed(range(len(self.ckpts)))):
+            q = idx % 2
+            if freed[q] is not None:
+                sa.wait_event(freed[q])
             k0 = seg * self.ckpt
             k1 = min(k0 + self.ckpt, self.nsteps)
             sim.A.copy_from(self.ckpts[seg])
-            saved = pool[:k1 - k0]
+            saved = pools[q][:k1 - k0]
             for srt, perm, start, rates in saved:
                 sim.build()
                 srt.copy_from(sim.A)
@@ -131,19 +145,28 @@ class KineticEnergyRollout:
                 a = sim.A.struct()
                 r = rates.struct()
                 L.sph_interact(sim.params, sim.grid, L.SPH_PASS_FORCE, a, None, None, a, sim.cells, 1, r,
-                               sim.ws.data_ptr(), sim.ws_bytes, st)
+                               sim.ws.data_ptr(), sim.ws_bytes, st_a)
                 L.sph_integrate(sim.params, L.SPH_STAGE_MOTION, a, r, fixed, sim.diag[0].data_ptr(),
-                                sim.ws.data_ptr(), sim.ws_bytes, st)
-            for srt, perm, start, rates in reversed(saved):
-                ps = srt.struct()
-                L.sph_integrate_adjoint(sim.params, L.SPH_STAGE_MOTION, ps, rates.struct(), fixed, bar.struct(),
-                                        rbar.struct(), None, None, 0, st)
-                L.sph_interact_adjoint(sim.params, sim.grid, ps, cells_struct(start, sim.nc), rbar.struct(),
-                                       bar.struct(), ws_adj.data_ptr(), ws_adj_bytes, st)
-                L.sph_integrate_adjoint(sim.params, L.SPH_STAGE_EOS, ps, None, None, bar.struct(), None,
-                                        c0bar.data_ptr(), sim.ws.data_ptr(), sim.ws_bytes, st)
-                L.sph_permute_adjoint(prec, n, perm.data_ptr(), bar.state_struct(), tmp.state_struct(), st)
-                bar, tmp = tmp, bar
+                                sim.ws.data_ptr(), sim.ws_bytes, st_a)
+            ready = torch.cuda.Event()
+            ready.record(sa)
+            sb.wait_event(ready)
+            with torch.cuda.stream(sb):
+                st_b = stream_handle()
+                for srt, perm, start, rates in reversed(saved):
+                    ps = srt.struct()
+                    L.sph_integrate_adjoint(sim.params, L.SPH_STAGE_MOTION, ps, rates.struct(), fixed,
+                                            bar.struct(), rbar.struct(), None, None, 0, st_b)
+                    L.sph_interact_adjoint(sim.params, sim.grid, ps, cells_struct(start, sim.nc), rbar.struct(),
+                                           bar.struct(), ws_adj.data_ptr(), ws_adj_bytes, st_b)
+                    L.sph_integrate_adjoint(sim.params, L.SPH_STAGE_EOS, ps, None, None, bar.struct(), None,
+                                            c0bar.data_ptr(), ws_adj.data_ptr(), ws_adj_bytes, st_b)
+                    L.sph_permute_adjoint(prec, n, perm.data_ptr(), bar.state_struct(), tmp.state_struct(), st_b)
+                    bar, tmp = tmp, bar
+                done = torch.cuda.Event()
+                done.record(sb)
+            freed[q] = done
+        sa.wait_stream(sb)
         torch.cuda.synchronize()
         # the initial state is in id order; E0 = e0 + |v0|^2 / 2 adds dJ/dE0 v0 to dJ/dv0
         v0 = self.ckpts[0].v.double()
