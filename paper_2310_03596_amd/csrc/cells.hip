@@ -125,25 +125,31 @@ __global__ __launch_bounds__(kBlock) void k_mark(Grid g, uint32_t n, const uint3
     uint32_t i = blockIdx.x * kBlock + threadIdx.x;
     bool flag = false;
     if (i < n) {
-        uint32_t h = hash[i];
-        int cx = (int)(h % (uint32_t)g.nx);
-        int cy = (int)((h / (uint32_t)g.nx) % (uint32_t)g.ny);
-        int cz = (int)(h / ((uint32_t)g.nx * (uint32_t)g.ny));
-        int x0 = cx > 0 ? cx - 1 : 0, x1 = cx + 1 < g.nx ? cx + 1 : g.nx - 1;
-        for (int dz = -1; dz <= 1 && !flag; ++dz) {
-            int z = cz + dz;
-            if (z < 0 || z >= g.nz) continue;
-            for (int dy = -1; dy <= 1; ++dy) {
-                int y = cy + dy;
-                if (y < 0 || y >= g.ny) continue;
-                uint32_t row = (uint32_t)g.nx * ((uint32_t)y + (uint32_t)g.ny * (uint32_t)z);
-                // a row of up to three adjacent buckets is occupied iff its range is non-empty
-                if (rstart[row + x1 + 1] > rstart[row + x0]) {
-                    flag = true;
-                    break;
-                }
-            }
+        const uint32_t h = hash[i];
+        const uint32_t nx = (uint32_t)g.nx, nxy = nx * (uint32_t)g.ny;
+        const uint32_t cz = h / nxy, rz = h - cz * nxy;
+        const uint32_t cy = rz / nx, cx = rz - cy * nx;
+        // Row (dy, dz) of the target's 27 buckets spans the source range
+        // [start[h + dy nx + dz nxy - (cx > 0)], start[h + dy nx + dz nxy + 1
+        // + (cx + 1 < nx)]) (up to three adjacent buckets); it is occupied iff
+        // that range is non-empty.  The bounds of all nine rows are loaded
+        // before any is tested, so the test costs one memory round trip; a row
+        // outside the grid reads start[0] instead and is ignored.
+        const uint32_t a = h - (cx > 0 ? 1u : 0u), b = h + 1u + (cx + 1u < nx ? 1u : 0u);
+        const bool yin[3] = {cy > 0, true, cy + 1u < (uint32_t)g.ny};
+        const bool zin[3] = {cz > 0 && cz <= (uint32_t)g.nz, cz < (uint32_t)g.nz, cz + 1u < (uint32_t)g.nz};
+        uint32_t lo[9], hi[9];
+        bool inside[9];
+#pragma unroll
+        for (int r = 0; r < 9; ++r) {
+            const int dz = r / 3 - 1, dy = r % 3 - 1;
+            inside[r] = zin[dz + 1] && yin[dy + 1];
+            const uint32_t off = (uint32_t)dy * nx + (uint32_t)dz * nxy;   // modular: dy, dz may be -1
+            lo[r] = rstart[inside[r] ? a + off : 0u];
+            hi[r] = rstart[inside[r] ? b + off : 0u];
         }
+#pragma unroll
+        for (int r = 0; r < 9; ++r) flag = flag || (inside[r] && hi[r] > lo[r]);
         comm[i] = flag ? h : g.ncells;
     }
     uint64_t m = __ballot(flag);
@@ -157,19 +163,12 @@ __global__ __launch_bounds__(kBlock) void k_mark(Grid g, uint32_t n, const uint3
 }
 
 // Single workgroup: exclusive scan of block counts, total to *nb.
-__global__ __launch_bounds__(kBlock) void k_scan_counts(uint32_t *__restrict__ counts, uint32_t nblocks,
-                                                        uint32_t *__restrict__ nb)
+constexpr int kScanBlock = 1024;
+__global__ __launch_bounds__(kScanBlock) void k_scan_counts(uint32_t *__restrict__ counts, uint32_t nblocks,
+                                                            uint32_t *__restrict__ nb)
 {
-    uint32_t run = 0;
-    for (uint32_t b0 = 0; b0 < nblocks; b0 += kBlock) {
-        uint32_t b = b0 + threadIdx.x;
-        uint32_t v = b < nblocks ? counts[b] : 0u;
-        uint32_t tot;
-        uint32_t ex = block_excl_scan(v, tot);
-        if (b < nblocks) counts[b] = run + ex;
-        run += tot;
-    }
-    if (threadIdx.x == 0) *nb = run;
+    const uint32_t tot = block_scan_row<kScanBlock, 8>(counts, nblocks);
+    if (threadIdx.x == 0) *nb = tot;
 }
 
 __global__ __launch_bounds__(kBlock) void k_compact(uint32_t n, uint32_t G, const uint32_t *__restrict__ comm,
@@ -250,7 +249,7 @@ hipError_t launch_mark_boundary(const Grid &g, const sph_particles &local, const
     uint32_t n = local.n;
     uint32_t blocks = div_up(n > 0 ? n : 1, kBlock);
     k_mark<<<blocks, kBlock, 0, s>>>(g, n, local.hash, rstart, comm, ws.counts);
-    k_scan_counts<<<1, kBlock, 0, s>>>(ws.counts, blocks, nb);
+    k_scan_counts<<<1, kScanBlock, 0, s>>>(ws.counts, blocks, nb);
     k_compact<<<blocks, kBlock, 0, s>>>(n, g.ncells, comm, ws.counts, bidx, cap);
     return hipGetLastError();
 }

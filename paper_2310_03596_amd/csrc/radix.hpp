@@ -25,17 +25,18 @@ __device__ inline uint32_t wave_incl_scan(uint32_t v)
     return v;
 }
 
-// Exclusive scan over the 256 threads of a block; every thread gets `total`.
+// Exclusive scan over the NT threads of a block; every thread gets `total`.
+template <int NT = kBlock>
 __device__ inline uint32_t block_excl_scan(uint32_t v, uint32_t &total)
 {
-    __shared__ uint32_t wsum[kBlock / kWave];
+    __shared__ uint32_t wsum[NT / kWave];
     int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
     uint32_t inc = wave_incl_scan(v);
     if (lane == kWave - 1) wsum[wave] = inc;
     __syncthreads();
     uint32_t before = 0, tot = 0;
 #pragma unroll
-    for (int w = 0; w < kBlock / kWave; ++w) {
+    for (int w = 0; w < NT / kWave; ++w) {
         uint32_t s = wsum[w];
         before += (w < wave) ? s : 0u;
         tot += s;
@@ -43,6 +44,60 @@ __device__ inline uint32_t block_excl_scan(uint32_t v, uint32_t &total)
     __syncthreads();
     total = tot;
     return before + inc - v;
+}
+
+// In-place exclusive scan of row[0, len) by one block of NT threads; returns
+// the row's total.  The row is taken in tiles of NT * B entries: a tile is
+// loaded with coalesced reads (all in flight at once) into LDS, each thread
+// then scans B consecutive entries of it (entry e sits at e + e / B, so the
+// threads' strided LDS reads hit distinct banks), one block scan gives every
+// thread its offset, and the tile is written back coalesced.  A tile costs
+// one memory round trip and one block scan, where a scan 256 entries at a
+// time costs one of each per 256 entries.
+template <int NT, int B>
+__device__ inline uint32_t block_scan_row(uint32_t *__restrict__ row, uint32_t len)
+{
+    constexpr uint32_t T = (uint32_t)NT * B;
+    __shared__ uint32_t sh[T + T / B];
+    const uint32_t tid = threadIdx.x;
+    uint32_t carry = 0;
+    for (uint32_t base = 0; base < len; base += T) {
+        uint32_t q[B];
+#pragma unroll
+        for (int k = 0; k < B; ++k) {
+            const uint32_t e = (uint32_t)k * NT + tid;
+            q[k] = base + e < len ? row[base + e] : 0u;
+        }
+#pragma unroll
+        for (int k = 0; k < B; ++k) {
+            const uint32_t e = (uint32_t)k * NT + tid;
+            sh[e + e / B] = q[k];
+        }
+        __syncthreads();
+        uint32_t v[B];
+        uint32_t sum = 0;
+#pragma unroll
+        for (int u = 0; u < B; ++u) {
+            v[u] = sh[tid * (B + 1) + u];
+            sum += v[u];
+        }
+        uint32_t tot;
+        uint32_t run = carry + block_excl_scan<NT>(sum, tot);
+#pragma unroll
+        for (int u = 0; u < B; ++u) {
+            sh[tid * (B + 1) + u] = run;
+            run += v[u];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < B; ++k) {
+            const uint32_t e = (uint32_t)k * NT + tid;
+            if (base + e < len) row[base + e] = sh[e + e / B];
+        }
+        carry += tot;
+        __syncthreads();   // the next tile overwrites the LDS copy
+    }
+    return carry;
 }
 
 template <int D>
@@ -84,17 +139,8 @@ __global__ __launch_bounds__(kBlock) void k_upsweep(const uint32_t *__restrict__
 __global__ __launch_bounds__(kBlock) void k_scan_digit(uint32_t *__restrict__ hist, uint32_t tiles,
                                                        uint32_t *__restrict__ totals)
 {
-    uint32_t *row = hist + (size_t)blockIdx.x * tiles;
-    uint32_t run = 0;
-    for (uint32_t b0 = 0; b0 < tiles; b0 += kBlock) {
-        uint32_t b = b0 + threadIdx.x;
-        uint32_t v = b < tiles ? row[b] : 0u;
-        uint32_t tot;
-        uint32_t ex = block_excl_scan(v, tot);
-        if (b < tiles) row[b] = run + ex;
-        run += tot;
-    }
-    if (threadIdx.x == 0) totals[blockIdx.x] = run;
+    const uint32_t tot = block_scan_row<kBlock, 16>(hist + (size_t)blockIdx.x * tiles, tiles);
+    if (threadIdx.x == 0) totals[blockIdx.x] = tot;
 }
 
 template <int D>
