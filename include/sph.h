@@ -213,8 +213,7 @@ int sph_pack_boundary(const sph_particles *local, const uint32_t *boundary_idx,
  * hash-sorted on `grid`.  The workspace receives a packed copy of the
  * sources' pair inputs (sized by sph_workspace_size for sources->n).
  * Errors: SPH_ERR_ARG (precision or material mismatch, missing field,
- * sources->n at or above 2^28 in SPH_FP32_SPLIT or 2^27 in SPH_FP64),
- * SPH_ERR_WORKSPACE. */
+ * sources->n at or above 2^27 = 134,217,728), SPH_ERR_WORKSPACE. */
 int sph_interact(const sph_params *params, const sph_grid *grid, int pass,
                  const sph_particles *targets, const uint32_t *target_idx,
                  const uint32_t *n_targets_dev, const sph_particles *sources, sph_cells source_cells,
@@ -252,8 +251,7 @@ int sph_count_pairs(const sph_params *params, const sph_grid *grid, const sph_pa
  * atomics.  The workspace (sph_workspace_size with SPH_SOLID_J2, which has
  * room for the extra staged records) receives packed copies of the
  * particles and their rate cotangents.  Errors: SPH_ERR_ARG (also p->n at
- * or above 2^28 in SPH_FP32_SPLIT or 2^27 in SPH_FP64), SPH_ERR_WORKSPACE,
- * SPH_ERR_UNSUPPORTED (solids). */
+ * or above 2^27), SPH_ERR_WORKSPACE, SPH_ERR_UNSUPPORTED (solids). */
 int sph_interact_adjoint(const sph_params *params, const sph_grid *grid, const sph_particles *p,
                          sph_cells cells, const sph_rates *rates_bar, const sph_adjoint *bar,
                          void *ws, size_t ws_bytes, void *stream);

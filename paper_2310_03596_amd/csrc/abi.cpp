@@ -259,10 +259,9 @@ int sph_interact(const sph_params *params, const sph_grid *grid, int pass, const
         return fail(SPH_ERR_ARG, "source bucket table missing or not on this grid");
     if (!check_rates(rates, pass, params->prec)) return SPH_ERR_ARG;
     if (targets->n == 0) return SPH_OK;
-    // hit records are addressed with 32-bit byte offsets (16- or 32-byte records)
-    const uint32_t src_max = params->prec == SPH_FP64 ? (1u << 27) : (1u << 28);
-    if (sources->n >= src_max)
-        return fail(SPH_ERR_ARG, "sources.n = %u must be below %u for this precision", sources->n, src_max);
+    // hit records are addressed with 32-bit byte offsets (at most 32 bytes per source and array)
+    const uint32_t src_max = 1u << 27;
+    if (sources->n >= src_max) return fail(SPH_ERR_ARG, "sources.n = %u must be below %u", sources->n, src_max);
     Workspace w;
     int staged_material = pass == SPH_PASS_FORCE ? params->material : SPH_FLUID_TAIT;
     if (!check_ws(ws, ws_bytes, sources->n, w, stage_bytes(params->prec, staged_material))) return SPH_ERR_WORKSPACE;
@@ -341,8 +340,8 @@ int sph_interact_adjoint(const sph_params *params, const sph_grid *grid, const s
     if (!bar->omega || !bar->rho || !bar->p || !bar->c || !bar->e)
         return fail(SPH_ERR_ARG, "bar.omega/rho/p/c/e is NULL");
     if (p->n == 0) return SPH_OK;
-    const uint32_t src_max = params->prec == SPH_FP64 ? (1u << 27) : (1u << 28);
-    if (p->n >= src_max) return fail(SPH_ERR_ARG, "n = %u must be below %u for this precision", p->n, src_max);
+    const uint32_t src_max = 1u << 27;   // as in sph_interact
+    if (p->n >= src_max) return fail(SPH_ERR_ARG, "n = %u must be below %u", p->n, src_max);
     Workspace w;
     if (!check_ws(ws, ws_bytes, p->n, w, stage_bytes(params->prec, SPH_SOLID_J2))) return SPH_ERR_WORKSPACE;
     return hip_status(launch_interact_adjoint(P, g, params->prec, *p, cells.start, *rates_bar, *bar, w,

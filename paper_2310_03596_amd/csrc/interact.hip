@@ -168,8 +168,8 @@ __global__ __launch_bounds__(kBlock) void k_stage(Grid g, PV<real> s, Stage<real
     b.y = s.p[j];
     b.z = s.c[j];
     b.w = s.e[j];
-    st.va[j] = a;
-    st.vb[j] = b;
+    st.va[rec_stride<real> * j] = a;
+    st.vb[rec_stride<real> * j] = b;
     if constexpr (SOLID) {
         v4 c0, c1;
         c0.x = s.S[0][j];
@@ -180,8 +180,8 @@ __global__ __launch_bounds__(kBlock) void k_stage(Grid g, PV<real> s, Stage<real
         c1.y = s.S[5][j];
         c1.z = 0;
         c1.w = 0;
-        st.s0[j] = c0;
-        st.s1[j] = c1;
+        st.s0[rec_stride<real> * j] = c0;
+        st.s1[rec_stride<real> * j] = c1;
     }
 }
 
@@ -329,15 +329,17 @@ void k_pairs(Params P, Grid g, PV<real> tg, const uint32_t *__restrict__ tidx, c
         q.qy = SPLIT ? (real)wn.dy : real(0);
         q.qz = SPLIT ? (real)wn.dz : real(0);
         // a 32-bit byte offset from each array's base (sources are fewer than
-        // 2^28 FP32 / 2^27 FP64 records), so the loads take the scalar-base form
+        // 2^27, and a source's records span at most 32 bytes per array), so
+        // the loads take the scalar-base form
         const uint32_t ob = jj * (uint32_t)sizeof(v4);
-        auto at = [&](const v4 *base) { return *reinterpret_cast<const v4 *>(reinterpret_cast<const char *>(base) + ob); };
-        q.p = at(src.pos);
-        q.a = at(src.va);
-        if constexpr (PASS == SPH_PASS_FORCE || ADJ) q.b = at(src.vb);
+        auto at = [&](const v4 *base, uint32_t o) { return *reinterpret_cast<const v4 *>(reinterpret_cast<const char *>(base) + o); };
+        q.p = at(src.pos, ob);
+        const uint32_t ob2 = ob * rec_stride<real>;
+        q.a = at(src.va, ob2);
+        if constexpr (PASS == SPH_PASS_FORCE || ADJ) q.b = at(src.vb, ob2);
         if constexpr ((PASS == SPH_PASS_FORCE && SOLID) || ADJ) {
-            q.s0 = at(src.s0);
-            q.s1 = at(src.s1);
+            q.s0 = at(src.s0, ob2);
+            q.s1 = at(src.s1, ob2);
         }
         return q;
     };
@@ -614,8 +616,8 @@ __global__ __launch_bounds__(kBlock) void k_stage_rbar(uint32_t n, RV<real> rb, 
     b.y = rb.hi[5][j];
     b.z = 0;
     b.w = 0;
-    st.s0[j] = a;
-    st.s1[j] = b;
+    st.s0[rec_stride<real> * j] = a;
+    st.s1[rec_stride<real> * j] = b;
 }
 
 // Candidates and hits of one pass, with the predicate of the pair kernel.
