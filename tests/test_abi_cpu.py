@@ -141,6 +141,15 @@ def test_interact_rejects_bad_arguments():
     assert lib.sph_interact(C.byref(ps), C.byref(g), 0, C.byref(p), None, None, C.byref(p), cells, 1, C.byref(r),
                             FAKE, 1 << 30, None) == L.SPH_ERR_ARG
     assert "S[0]" in _last()
+    # pair records are addressed with 32-bit byte offsets: fewer than 2^27 sources, in both forms
+    for prec in (L.SPH_FP64, L.SPH_FP32_SPLIT):
+        t, big = _particles(10, prec), _particles(1 << 27, prec)
+        if prec == L.SPH_FP32_SPLIT:
+            for k in range(6):
+                r.lo[k] = FAKE
+        assert lib.sph_interact(C.byref(_params(prec=prec)), C.byref(g), 0, C.byref(t), None, None, C.byref(big),
+                                cells, 1, C.byref(r), FAKE, 1 << 62, None) == L.SPH_ERR_ARG
+        assert "must be below 134217728" in _last()
 
 
 def test_integrate_and_adjoint_reject_bad_arguments():
