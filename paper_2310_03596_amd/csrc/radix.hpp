@@ -14,6 +14,16 @@ namespace sph {
 
 namespace {
 
+#ifndef SPH_SORT_WIDE
+#define SPH_SORT_WIDE 1
+#endif
+// Keys per thread of a tile: 10-bit digits take tiles twice as long, so the
+// per-tile work that scales with the 1024 digits (clearing and writing the
+// tile's histogram, reading it back for the scatter) stays small next to the
+// keys.
+template <int D>
+constexpr int sort_items = (SPH_SORT_WIDE && D >= 10) ? 2 * kSortItems : kSortItems;
+
 __device__ inline uint32_t wave_incl_scan(uint32_t v)
 {
     int lane = threadIdx.x & (kWave - 1);
@@ -112,15 +122,16 @@ __global__ __launch_bounds__(kBlock) void k_upsweep(const uint32_t *__restrict__
     // keys arrive nearly sorted, step after step, so runs are long and the
     // LDS atomics do not serialise on one address).
     const int lane = threadIdx.x & (kWave - 1);
-    const uint32_t base = blockIdx.x * kSortTile;
-    uint32_t keyv[kSortItems];
+    constexpr int IT = sort_items<D>;
+    const uint32_t base = blockIdx.x * (kBlock * IT);
+    uint32_t keyv[IT];
 #pragma unroll
-    for (int it = 0; it < kSortItems; ++it) {
+    for (int it = 0; it < IT; ++it) {
         const uint32_t e = base + it * kBlock + threadIdx.x;
         keyv[it] = e < n ? keys[e] : 0u;
     }
 #pragma unroll
-    for (int it = 0; it < kSortItems; ++it) {
+    for (int it = 0; it < IT; ++it) {
         const uint32_t e = base + it * kBlock + threadIdx.x;
         const bool valid = e < n;
         const uint32_t d = valid ? (keyv[it] >> shift) & (BINS - 1) : (uint32_t)BINS;
@@ -162,10 +173,11 @@ __global__ __launch_bounds__(kBlock) void k_downsweep(const uint32_t *__restrict
     // the tile's keys and values are read first: their loads overlap the
     // digit-base bookkeeping below and each other (a load issued inside the
     // loop would wait out a full round trip behind every barrier)
-    const uint32_t base = blockIdx.x * kSortTile;
-    uint32_t keyv[kSortItems], valv[kSortItems];
+    constexpr int IT = sort_items<D>;
+    const uint32_t base = blockIdx.x * (kBlock * IT);
+    uint32_t keyv[IT], valv[IT];
 #pragma unroll
-    for (int it = 0; it < kSortItems; ++it) {
+    for (int it = 0; it < IT; ++it) {
         const uint32_t e = base + it * kBlock + tid;
         keyv[it] = e < n ? kin[e] : 0u;
         valv[it] = e < n ? vin[e] : 0u;
@@ -192,7 +204,7 @@ __global__ __launch_bounds__(kBlock) void k_downsweep(const uint32_t *__restrict
     __syncthreads();
     const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
 #pragma unroll
-    for (int it = 0; it < kSortItems; ++it) {
+    for (int it = 0; it < IT; ++it) {
         const uint32_t e = base + it * kBlock + tid;
         const bool valid = e < n;
         const uint32_t key = keyv[it];
@@ -256,8 +268,9 @@ __global__ __launch_bounds__(kBlock) void k_downsweep(const uint32_t *__restrict
 
 // One LSD pass with D-bit digits starting at bit `shift`.
 template <int D>
-void sort_pass(const Workspace &ws, uint32_t n, uint32_t tiles, int shift, int cur, hipStream_t s)
+void sort_pass(const Workspace &ws, uint32_t n, int shift, int cur, hipStream_t s)
 {
+    const uint32_t tiles = div_up(n, (uint64_t)kBlock * sort_items<D>);   // at most the workspace's tiles
     k_upsweep<D><<<tiles, kBlock, 0, s>>>(ws.keys[cur], n, shift, ws.hist, tiles);
     k_scan_digit<<<1u << D, kBlock, 0, s>>>(ws.hist, tiles, ws.totals);
     k_downsweep<D><<<tiles, kBlock, 0, s>>>(ws.keys[cur], ws.vals[cur], ws.keys[cur ^ 1], ws.vals[cur ^ 1], n,
@@ -280,16 +293,15 @@ inline int radix_sort(const Workspace &ws, uint32_t n, uint32_t nkeys, hipStream
     const int passes = bits > 0 ? (bits + kMaxRadixBits - 1) / kMaxRadixBits : 1;
     int dbits = (bits + passes - 1) / passes;
     dbits = dbits < 8 ? 8 : dbits;
-    const uint32_t tiles = div_up(n, kSortTile);
     int cur = 0;
     for (int ps = 0; ps < passes; ++ps) {
         const int shift = ps * dbits;
         if (dbits == 8)
-            sort_pass<8>(ws, n, tiles, shift, cur, s);
+            sort_pass<8>(ws, n, shift, cur, s);
         else if (dbits == 9)
-            sort_pass<9>(ws, n, tiles, shift, cur, s);
+            sort_pass<9>(ws, n, shift, cur, s);
         else
-            sort_pass<10>(ws, n, tiles, shift, cur, s);
+            sort_pass<10>(ws, n, shift, cur, s);
         cur ^= 1;
     }
     return cur;
