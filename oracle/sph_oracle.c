@@ -495,7 +495,7 @@ void or_interact(const op_t *P, const og_t *g, int pass, const os_t *tg, const u
 }
 
 /* Per-target sums of the magnitude bounds (pair_bound): the scale against
- * which round-off in a pair sum is judged. */
+ * which round-off in a pair sum is measured. */
 void or_interact_abs(const op_t *P, const og_t *g, int pass, const os_t *tg, const uint32_t *tidx,
                      int64_t nt, const os_t *sr, const uint32_t *sstart, int self, double *rates,
                      double *L)

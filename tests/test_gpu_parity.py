@@ -3,7 +3,7 @@
 Tolerances
   * Integer outputs (hash, permutation, bucket table, ids, communication
     hash, boundary list and count): bit-exact.
-  * Pair sums are judged against B, the per-target sum of the oracle's
+  * Pair sums are compared against B, the per-target sum of the oracle's
     magnitude bound of each term (every input in absolute value, every
     difference as a sum, |n_k| -> 1: forward error analysis bounds the
     rounding of a ~30-operation term by ~30 u B, and a relative perturbation
