@@ -69,6 +69,18 @@ def _faces():
     return w
 
 
+def _coincident():
+    """A fifth of the particles sit exactly on another one (different velocity
+    and density): such a pair has no direction and, with F(0) = 0, adds
+    nothing; the pair body must produce exact zeros there, not NaN."""
+    w = S.random_cloud(1200, seed=56, h=0.05, rho_sigma=0.01)
+    rng = np.random.default_rng(58)
+    src = rng.choice(w.n, size=240, replace=False)
+    dst = rng.choice(np.setdiff1d(np.arange(w.n), src), size=240, replace=False)
+    w.x[dst] = w.x[src]
+    return w
+
+
 def _far_origin():
     """A lattice 2 km from the coordinate origin (the grid moves with it): the
     FP64 form's filter works on FP64 differences rounded to float, with a
@@ -91,6 +103,7 @@ CASES = {
     "dense": lambda: dense_cell_cloud(1500, seed=54),
     "lattice12": lambda: S.jittered_lattice(12, seed=55, rho_sigma=0.01),
     "far_origin": _far_origin,
+    "coincident": _coincident,
 }
 
 
@@ -124,7 +137,7 @@ def test_build_cells_bit_exact(case, prec):
 
 @pytest.mark.parametrize("prec", PRECS)
 @pytest.mark.parametrize("case", ["one", "cloud2049", "cube8000", "faces", "clamped", "dense", "lattice12",
-                                  "far_origin"])
+                                  "far_origin", "coincident"])
 def test_force_pass_matches_oracle(case, prec):
     wl = CASES[case]()
     print(f"[force] case={case} prec={prec} n={wl.n}", flush=True)
