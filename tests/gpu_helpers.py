@@ -33,7 +33,7 @@ def assert_close_scaled(got, ref, scale, rtol, what=""):
     ref = np.asarray(ref, dtype=np.float64)
     err = np.abs(got - ref)
     bound = rtol * np.asarray(scale, dtype=np.float64) + 1e-300
-    bad = err > bound
+    bad = ~(err <= bound)   # a NaN on either side fails
     if bad.any():
         idx = np.argwhere(bad)[:5]
         ratio = (err / np.maximum(scale, 1e-300)).max()
@@ -63,7 +63,7 @@ def assert_within(got, ref, bound, what=""):
     got = np.asarray(got, dtype=np.float64)
     ref = np.asarray(ref, dtype=np.float64)
     err = np.abs(got - ref)
-    bad = err > bound + 1e-300
+    bad = ~(err <= bound + 1e-300)   # a NaN on either side fails
     if bad.any():
         idx = np.argwhere(bad)[:5]
         ratio = (err / np.maximum(bound, 1e-300)).max()

@@ -295,6 +295,17 @@ def test_share_pass_matches_oracle(layout, prec):
     bound += rate_bound(loc.params, loc.grid, cpu.FORCE, sl, sr, rstart, False, prec)
     got = sp.rates.force().T.cpu().numpy()
     assert_within(got, ref, bound, f"share {layout}")
+    # the decomposition loses no pair: LL + LR equal one pass over the union of
+    # the two arrays (Section II, steps e and f), matched by particle id
+    u = cpu.State(sl.n + sr.n)
+    for f in ("x", "v", "m", "w", "rho", "p", "c", "E", "id"):
+        getattr(u, f)[...] = np.concatenate([getattr(sl, f), getattr(sr, f)])
+    us, _, ustart = cpu.build_cells(loc.grid, u)
+    uref = cpu.interact(loc.params, loc.grid, cpu.FORCE, us, us, ustart, True)
+    ubound = rate_bound(loc.params, loc.grid, cpu.FORCE, us, us, ustart, True, prec)
+    row = {int(i): k for k, i in enumerate(us.id)}
+    sel = np.array([row[int(i)] for i in sl.id])
+    assert_within(got, uref[sel], ubound[sel], f"share {layout} vs union")
     # particles with no remote bucket nearby have no remote neighbour
     pi, pj = cpu.neighbors(loc.params, loc.grid, sl, sr, rstart, False)
     assert set(np.unique(pi).tolist()) <= set(bidx.tolist())
