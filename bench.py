@@ -156,7 +156,7 @@ def other_workloads_leg():
     return out
 
 
-def adjoint_leg(prec, reps=2):
+def adjoint_leg(prec, reps=5):
     """Adjoint/forward time ratio on the 250,047-particle box: 50 fixed-dt
     steps with checkpoints every 10 (forward), then the reverse pass
     (recompute of every segment + reverse kernels).  Best of `reps`."""
