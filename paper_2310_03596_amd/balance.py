@@ -22,13 +22,22 @@ class BalancePair:
     """Two particle sets A and B (e.g. the shares of two GPUs) on one device."""
 
     def __init__(self, wl_a, wl_b, prec: int, device="cuda", hmax: int = HMAX):
+        self._setup(Particles.upload(wl_a, prec, device), Particles.upload(wl_b, prec, device), wl_a.grid,
+                    prec, device, hmax)
+
+    @classmethod
+    def of(cls, A: Particles, B: Particles, grid: dict, prec: int, hmax: int = HMAX) -> "BalancePair":
+        """A pair over two existing particle arrays (swaps happen in place)."""
+        self = cls.__new__(cls)
+        self._setup(A, B, grid, prec, A.device, hmax)
+        return self
+
+    def _setup(self, A, B, grid, prec, device, hmax):
         self.prec, self.hmax = prec, hmax
-        self.A = Particles.upload(wl_a, prec, device)
-        self.B = Particles.upload(wl_b, prec, device)
+        self.A, self.B = A, B
         n = max(self.A.n, self.B.n, 1)
-        solid = wl_a.S is not None
-        self.ws_bytes = L.sph_workspace_size(grid_struct(wl_a.grid), n, prec,
-                                             L.SPH_SOLID_J2 if solid else L.SPH_FLUID_TAIT)
+        self.ws_bytes = L.sph_workspace_size(grid_struct(grid), n, prec,
+                                             L.SPH_SOLID_J2 if A.solid else L.SPH_FLUID_TAIT)
         self.ws = torch.zeros(self.ws_bytes, dtype=torch.uint8, device=device)
         i32 = dict(dtype=torch.int32, device=device)
         self.cg = torch.zeros((2, 4), dtype=torch.float64, device=device)
