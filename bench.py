@@ -223,6 +223,40 @@ def share_leg(reps=5):
     return out
 
 
+def decomposition_leg(steps=200, period=20):
+    """The column as two GPUs' shares on one device (FP32 split): steps a-g
+    for both sets with a balancing round every `period` steps.  Exchange-set
+    fraction (both sets' boundary particles over all particles) after each
+    round, for a random and a slab (median x) initial split; time per step
+    of both sets, balancing included."""
+    import numpy as np
+    import torch
+
+    import sph_synth as S
+    from paper_2310_03596_amd import SPH_FP32_SPLIT
+    from paper_2310_03596_amd.decomp import TwoSets
+
+    wl = S.c2_column()
+    out = {"particles": wl.n, "steps": steps, "balance_every": period}
+    splits = {"random": np.random.default_rng(93).random(wl.n) < 0.5,
+              "slab": wl.x[:, 0] > np.median(wl.x[:, 0])}
+    for name, owner in splits.items():
+        ts = TwoSets(wl, owner, SPH_FP32_SPLIT, period=period)
+        fr = []
+        for k in range(steps):
+            ts.step()
+            if k == 0 or (k + 1) % period == 0:
+                fr.append(round(ts.exchange_fraction(), 5))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            ts.step()
+        torch.cuda.synchronize()
+        out[name] = {"exchange_fraction_first_step_then_every_round": fr,
+                     "ms_per_step_both_sets": (time.perf_counter() - t0) * 1e3 / steps}
+    return out
+
+
 def balance_leg(reps=3, types=False):
     """One round of the swap heuristic (Section III.A) between an 8M and a 2M
     particle set (the mixed share and its partner), FP32 split: both centres,
@@ -390,6 +424,7 @@ def main():
         out["share_pass"] = share_leg()
         out["balance_round"] = balance_leg()
         out["balance_types_round"] = balance_leg(types=True)
+        out["decomposition"] = decomposition_leg()
     if args.calib_copy_mb > 0:
         nbytes = args.calib_copy_mb << 20
         src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
