@@ -217,11 +217,62 @@ struct Acc {
     __device__ inline void add(double x) { s += x; }
 };
 
+// Row-aligned wavefronts: the targets of one bucket row (cy, cz) are one
+// contiguous range of the sorted array, and a wavefront whose targets span
+// two rows walks the neighbour rows of each in turn with the other lanes
+// idle.  For a pass over every target of a sorted array, one workgroup of
+// kPlanBlock threads lists (first target, count) for wavefronts that each
+// take up to 64 targets of a single row, rows in order (on the column
+// workload: 13,183 row walks instead of 14,243).  plan holds at most
+// ceil(n / 64) + rows entries; *nplan receives their number.
+constexpr int kPlanBlock = 1024;
+__global__ __launch_bounds__(kPlanBlock) void k_wave_plan(Grid g, const uint32_t *__restrict__ start,
+                                                          uint2 *__restrict__ plan, uint32_t *__restrict__ nplan)
+{
+    __shared__ uint32_t wsum[kPlanBlock / kWave];
+    const uint32_t nx = (uint32_t)g.nx, nrows = (uint32_t)g.ny * (uint32_t)g.nz;
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    uint32_t carry = 0;
+    for (uint32_t r0 = 0; r0 < nrows; r0 += kPlanBlock) {
+        const uint32_t r = r0 + threadIdx.x;
+        uint32_t b = 0, len = 0;
+        if (r < nrows) {
+            b = start[(size_t)r * nx];
+            len = start[(size_t)(r + 1) * nx] - b;
+        }
+        const uint32_t w = (len + kWave - 1) / kWave;
+        // exclusive scan of w over the block (wavefront scan, then wavefront totals)
+        uint32_t inc = w;
+#pragma unroll
+        for (int off = 1; off < kWave; off <<= 1) {
+            const uint32_t v = __shfl_up(inc, off, kWave);
+            if (lane >= off) inc += v;
+        }
+        if (lane == kWave - 1) wsum[wave] = inc;
+        __syncthreads();
+        uint32_t before = 0, tot = 0;
+        for (int k = 0; k < kPlanBlock / kWave; ++k) {
+            const uint32_t s = wsum[k];
+            before += k < wave ? s : 0u;
+            tot += s;
+        }
+        __syncthreads();
+        const uint32_t first = carry + before + inc - w;
+        for (uint32_t k = 0; k < w; ++k) {
+            const uint32_t left = len - k * kWave;
+            plan[first + k] = make_uint2(b + k * kWave, left < (uint32_t)kWave ? left : (uint32_t)kWave);
+        }
+        carry += tot;
+    }
+    if (threadIdx.x == 0) *nplan = carry;
+}
+
 template <typename real, int PASS, bool SOLID, bool SELF>
 __global__ __launch_bounds__(kPairBlock)
 __attribute__((amdgpu_waves_per_eu(PairOccupancy<real, SOLID, PASS == kPassAdjoint>::value)))
 void k_pairs(Params P, Grid g, PV<real> tg, const uint32_t *__restrict__ tidx, const uint32_t *__restrict__ ntdev,
-             Stage<real> src, const uint32_t *__restrict__ sstart, int zero_first, RV<real> R, AV<real> B)
+             Stage<real> src, const uint32_t *__restrict__ sstart, int zero_first, RV<real> R, AV<real> B,
+             const uint2 *__restrict__ plan, const uint32_t *__restrict__ nplan)
 {
     using v4 = typename Vec4<real>::type;
     constexpr bool SPLIT = sizeof(real) == 4;
@@ -248,16 +299,28 @@ void k_pairs(Params P, Grid g, PV<real> tg, const uint32_t *__restrict__ tidx, c
 
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
     const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);   // neighbouring tiles share sources
-    const uint32_t t = tile * kPairBlock + tid;
-    uint32_t nt = tg.n;
-    if (tidx) {
-        uint32_t c = *ntdev;
-        nt = c < nt ? c : nt;
+    bool valid;
+    uint32_t i;
+    if (plan) {
+        // row-aligned wavefronts (k_wave_plan): whole wavefronts beyond the
+        // plan leave
+        const uint32_t wid = tile * kWaves + wave;
+        if (wid >= *nplan) return;
+        const uint2 d = plan[wid];
+        valid = (uint32_t)lane < d.y;
+        i = valid ? d.x + (uint32_t)lane : 0u;
+    } else {
+        const uint32_t t = tile * kPairBlock + tid;
+        uint32_t nt = tg.n;
+        if (tidx) {
+            uint32_t c = *ntdev;
+            nt = c < nt ? c : nt;
+        }
+        // whole wavefronts beyond the targets leave; partial ones keep idle lanes
+        if (tile * kPairBlock + wave * kWave >= nt) return;
+        valid = t < nt;
+        i = valid ? (tidx ? tidx[t] : t) : 0u;
     }
-    // whole wavefronts beyond the targets leave; partial ones keep idle lanes
-    if (tile * kPairBlock + wave * kWave >= nt) return;
-    const bool valid = t < nt;
-    const uint32_t i = valid ? (tidx ? tidx[t] : t) : 0u;
 
     const PairK<real> K = make_pair_k<real>(P);
     const real R2 = (real)P.R2;
@@ -709,12 +772,29 @@ hipError_t go(const Params &P, const Grid &g, const sph_particles &tg, const uin
         if constexpr (ADJ) k_stage_rbar<real><<<div_up(sr.n, kBlock), kBlock, 0, s>>>(sr.n, view<real>(r), st);
     }
     uint32_t blocks = div_up(tg.n, kPairBlock);
+    const uint2 *plan = nullptr;
+    const uint32_t *nplan = nullptr;
+    // A pass over every target of a sorted array (targets = sources, whose
+    // bucket table is at hand) takes row-aligned wavefronts; the plan lives in
+    // the sort's key buffers, free during a pass, when it fits there.
+    const uint64_t nrows = (uint64_t)g.ny * (uint64_t)g.nz;
+    const uint64_t pmax = div_up(tg.n, kWave) + nrows;
+    if (self && !tidx && pmax * sizeof(uint2) <= 4ull * tg.n) {
+        uint2 *pl = reinterpret_cast<uint2 *>(ws.keys[0]);
+        uint32_t *np = ws.keys[1];
+        k_wave_plan<<<1, kPlanBlock, 0, s>>>(g, sstart, pl, np);
+        plan = pl;
+        nplan = np;
+        blocks = div_up(pmax, kWaves);
+    }
     if (self)
         k_pairs<real, PASS, SOLID, true><<<blocks, kPairBlock, 0, s>>>(P, g, view<real>(tg), tidx, nt, st, sstart,
-                                                                     zero_first, view<real>(r), view<real>(bar));
+                                                                     zero_first, view<real>(r), view<real>(bar),
+                                                                     plan, nplan);
     else
         k_pairs<real, PASS, SOLID, false><<<blocks, kPairBlock, 0, s>>>(P, g, view<real>(tg), tidx, nt, st, sstart,
-                                                                      zero_first, view<real>(r), view<real>(bar));
+                                                                      zero_first, view<real>(r), view<real>(bar),
+                                                                      plan, nplan);
     return hipGetLastError();
 }
 
