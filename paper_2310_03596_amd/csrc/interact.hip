@@ -138,12 +138,68 @@ __device__ inline int wave_max(int v)
     return __builtin_amdgcn_readfirstlane(v);   // equal in every lane
 }
 
+// Row-aligned wavefronts: the targets of one bucket row (cy, cz) are one
+// contiguous range of the sorted array, and a wavefront whose targets span
+// two rows walks the neighbour rows of each in turn with the other lanes
+// idle.  For a pass over every target of a sorted array, one workgroup
+// lists (first target, count) for wavefronts that each take up to 64
+// targets of a single row, rows in order (on the column workload: 13,183 row
+// walks instead of 14,243).  plan holds at most ceil(n / 64) + rows entries;
+// *nplan receives their number.  The staging kernel runs this as its first
+// workgroup, so the plan's latency hides behind the staging.
+constexpr int kPlanBlock = kBlock;
+__device__ inline void wave_plan_block(const Grid &g, const uint32_t *__restrict__ start, uint2 *__restrict__ plan,
+                                       uint32_t *__restrict__ nplan)
+{
+    __shared__ uint32_t wsum[kPlanBlock / kWave];
+    const uint32_t nx = (uint32_t)g.nx, nrows = (uint32_t)g.ny * (uint32_t)g.nz;
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    uint32_t carry = 0;
+    for (uint32_t r0 = 0; r0 < nrows; r0 += kPlanBlock) {
+        const uint32_t r = r0 + threadIdx.x;
+        uint32_t b = 0, len = 0;
+        if (r < nrows) {
+            b = start[(size_t)r * nx];
+            len = start[(size_t)(r + 1) * nx] - b;
+        }
+        const uint32_t w = (len + kWave - 1) / kWave;
+        // exclusive scan of w over the block (wavefront scan, then wavefront totals)
+        uint32_t inc = w;
+#pragma unroll
+        for (int off = 1; off < kWave; off <<= 1) {
+            const uint32_t v = __shfl_up(inc, off, kWave);
+            if (lane >= off) inc += v;
+        }
+        if (lane == kWave - 1) wsum[wave] = inc;
+        __syncthreads();
+        uint32_t before = 0, tot = 0;
+        for (int k = 0; k < kPlanBlock / kWave; ++k) {
+            const uint32_t s = wsum[k];
+            before += k < wave ? s : 0u;
+            tot += s;
+        }
+        __syncthreads();
+        const uint32_t first = carry + before + inc - w;
+        for (uint32_t k = 0; k < w; ++k) {
+            const uint32_t left = len - k * kWave;
+            plan[first + k] = make_uint2(b + k * kWave, left < (uint32_t)kWave ? left : (uint32_t)kWave);
+        }
+        carry += tot;
+    }
+    if (threadIdx.x == 0) *nplan = carry;
+}
+
 // Packs the pair inputs of every source particle (see Stage).
 template <typename real, bool SOLID>
-__global__ __launch_bounds__(kBlock) void k_stage(Grid g, PV<real> s, Stage<real> st)
+__global__ __launch_bounds__(kBlock) void k_stage(Grid g, PV<real> s, Stage<real> st, const uint32_t *pstart,
+                                                  uint2 *plan, uint32_t *nplan)
 {
     constexpr bool SPLIT = sizeof(real) == 4;
-    uint32_t j = blockIdx.x * kBlock + threadIdx.x;
+    if (plan && blockIdx.x == 0) {
+        wave_plan_block(g, pstart, plan, nplan);
+        return;
+    }
+    uint32_t j = (blockIdx.x - (plan ? 1u : 0u)) * kBlock + threadIdx.x;
     if (j >= s.n) return;
     using v4 = typename Vec4<real>::type;
     v4 pos;
@@ -216,56 +272,6 @@ struct Acc {
     __device__ inline void add(float x) { s += (double)x; }
     __device__ inline void add(double x) { s += x; }
 };
-
-// Row-aligned wavefronts: the targets of one bucket row (cy, cz) are one
-// contiguous range of the sorted array, and a wavefront whose targets span
-// two rows walks the neighbour rows of each in turn with the other lanes
-// idle.  For a pass over every target of a sorted array, one workgroup of
-// kPlanBlock threads lists (first target, count) for wavefronts that each
-// take up to 64 targets of a single row, rows in order (on the column
-// workload: 13,183 row walks instead of 14,243).  plan holds at most
-// ceil(n / 64) + rows entries; *nplan receives their number.
-constexpr int kPlanBlock = 1024;
-__global__ __launch_bounds__(kPlanBlock) void k_wave_plan(Grid g, const uint32_t *__restrict__ start,
-                                                          uint2 *__restrict__ plan, uint32_t *__restrict__ nplan)
-{
-    __shared__ uint32_t wsum[kPlanBlock / kWave];
-    const uint32_t nx = (uint32_t)g.nx, nrows = (uint32_t)g.ny * (uint32_t)g.nz;
-    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
-    uint32_t carry = 0;
-    for (uint32_t r0 = 0; r0 < nrows; r0 += kPlanBlock) {
-        const uint32_t r = r0 + threadIdx.x;
-        uint32_t b = 0, len = 0;
-        if (r < nrows) {
-            b = start[(size_t)r * nx];
-            len = start[(size_t)(r + 1) * nx] - b;
-        }
-        const uint32_t w = (len + kWave - 1) / kWave;
-        // exclusive scan of w over the block (wavefront scan, then wavefront totals)
-        uint32_t inc = w;
-#pragma unroll
-        for (int off = 1; off < kWave; off <<= 1) {
-            const uint32_t v = __shfl_up(inc, off, kWave);
-            if (lane >= off) inc += v;
-        }
-        if (lane == kWave - 1) wsum[wave] = inc;
-        __syncthreads();
-        uint32_t before = 0, tot = 0;
-        for (int k = 0; k < kPlanBlock / kWave; ++k) {
-            const uint32_t s = wsum[k];
-            before += k < wave ? s : 0u;
-            tot += s;
-        }
-        __syncthreads();
-        const uint32_t first = carry + before + inc - w;
-        for (uint32_t k = 0; k < w; ++k) {
-            const uint32_t left = len - k * kWave;
-            plan[first + k] = make_uint2(b + k * kWave, left < (uint32_t)kWave ? left : (uint32_t)kWave);
-        }
-        carry += tot;
-    }
-    if (threadIdx.x == 0) *nplan = carry;
-}
 
 template <typename real, int PASS, bool SOLID, bool SELF>
 __global__ __launch_bounds__(kPairBlock)
@@ -767,13 +773,9 @@ hipError_t go(const Params &P, const Grid &g, const sph_particles &tg, const uin
     if (tg.n == 0) return hipSuccess;
     constexpr bool ADJ = PASS == kPassAdjoint;
     Stage<real> st = stage_view<real>(ws, sr.n, SOLID || ADJ);
-    if (sr.n > 0) {
-        k_stage<real, SOLID><<<div_up(sr.n, kBlock), kBlock, 0, s>>>(g, view<real>(sr), st);
-        if constexpr (ADJ) k_stage_rbar<real><<<div_up(sr.n, kBlock), kBlock, 0, s>>>(sr.n, view<real>(r), st);
-    }
     uint32_t blocks = div_up(tg.n, kPairBlock);
-    const uint2 *plan = nullptr;
-    const uint32_t *nplan = nullptr;
+    uint2 *plan = nullptr;
+    uint32_t *nplan = nullptr;
     // A fluid pass over every target of a sorted array (targets = sources,
     // whose bucket table is at hand) takes row-aligned wavefronts; the plan
     // lives in the sort's key buffers, free during a pass, when it fits there.
@@ -783,12 +785,15 @@ hipError_t go(const Params &P, const Grid &g, const sph_particles &tg, const uin
     const uint64_t nrows = (uint64_t)g.ny * (uint64_t)g.nz;
     const uint64_t pmax = div_up(tg.n, kWave) + nrows;
     if (!SOLID && PASS != SPH_PASS_GRADIENT && self && !tidx && pmax * sizeof(uint2) <= 4ull * tg.n) {
-        uint2 *pl = reinterpret_cast<uint2 *>(ws.keys[0]);
-        uint32_t *np = ws.keys[1];
-        k_wave_plan<<<1, kPlanBlock, 0, s>>>(g, sstart, pl, np);
-        plan = pl;
-        nplan = np;
+        plan = reinterpret_cast<uint2 *>(ws.keys[0]);
+        nplan = ws.keys[1];
         blocks = div_up(pmax, kWaves);
+    }
+    if (sr.n > 0) {
+        // one more workgroup (the first) builds the wavefront plan
+        k_stage<real, SOLID><<<div_up(sr.n, kBlock) + (plan ? 1 : 0), kBlock, 0, s>>>(g, view<real>(sr), st, sstart,
+                                                                                    plan, nplan);
+        if constexpr (ADJ) k_stage_rbar<real><<<div_up(sr.n, kBlock), kBlock, 0, s>>>(sr.n, view<real>(r), st);
     }
     if (self)
         k_pairs<real, PASS, SOLID, true><<<blocks, kPairBlock, 0, s>>>(P, g, view<real>(tg), tidx, nt, st, sstart,
