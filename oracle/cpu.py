@@ -5,6 +5,7 @@ lives in ``sph_oracle.c``.  Arrays are numpy, float64 unless stated.
 """
 from __future__ import annotations
 
+import contextlib
 import ctypes as C
 import os
 
@@ -23,6 +24,21 @@ def lib():
         _lib = C.CDLL(_build.LIB)
         _declare(_lib)
     return _lib
+
+
+@contextlib.contextmanager
+def use_library(path: str):
+    """Route every call of this module to another build of the oracle (the
+    tests use it to check that a deliberately mistaken copy fails its pins)."""
+    global _lib
+    saved = _lib
+    alt = C.CDLL(path)
+    _declare(alt)
+    _lib = alt
+    try:
+        yield alt
+    finally:
+        _lib = saved
 
 
 class OGrid(C.Structure):
