@@ -27,12 +27,22 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "particle-updates/s (FP32 vs FP64 form, stated error) + adjoint/forward ratio"
-# Algorithmic flops of the fluid FORCE pass, counted from the kernel source
-# (FMA = 2, add/mul/sqrt/rcp/rsq = 1): per candidate source (position
-# difference + squared distance) and per pair within 2h (pair terms +
-# compensated accumulation of 6 rates).
-FLOPS_CAND = {1: 12, 0: 8}
-FLOPS_PAIR = {1: 139, 0: 103}
+# Algorithmic flops of the fluid FORCE pass (FMA = 2; add, mul, div, sqrt = 1),
+# the same in both forms: the work of the plain definition of the pass, not
+# of the kernel's evaluation of it.  Per candidate source: the position
+# difference and the squared distance of the neighbour test.  Per pair within
+# 2h: the pair terms written plainly (r, q, F, n, g, the normal velocities,
+# the means, the acoustic Riemann solution, v*, E*, the six terms) and the
+# accumulation of the six rates.  tests/test_flop_count.py counts them by
+# evaluating that plain form with an operation-counting number type and checks
+# its values against the oracle's pair terms.
+FLOPS_CAND_ITEMS = {"x_j - x_i": 3, "|d|^2": 5}
+FLOPS_PAIR_ITEMS = {"r = sqrt(r2)": 1, "q and F(q)": 5, "n = d / r": 3, "g = F n": 3, "u_i, u_j": 10,
+                    "means of rho, c, p": 6, "Z": 1, "u* - ubar": 3, "p*": 4, "v*": 12, "E*": 9,
+                    "A = 2 w_i w_j": 2, "Phi": 2, "traction p* g": 3, "mdot": 1, "mvdot": 9, "mEdot": 8,
+                    "wdot": 10, "accumulate 6 rates": 6}
+FLOPS_CAND = {p: sum(FLOPS_CAND_ITEMS.values()) for p in (0, 1)}
+FLOPS_PAIR = {p: sum(FLOPS_PAIR_ITEMS.values()) for p in (0, 1)}
 PEAK_TFLOPS = {1: 157.3, 0: 78.6}      # MI355X vector FP32 (published) / FP64
 EVENT_EVERY = 10
 

@@ -29,7 +29,8 @@
  *     keeps positions x and total energy E in double and every other real
  *     field in float; its pair loops run in float on positions held as bucket
  *     index plus a float offset from the bucket corner (so x_j - x_i keeps
- *     its relative precision), and pair sums are compensated (hi, lo) pairs.
+ *     its relative precision); pair sums accumulate in double and are
+ *     stored as float (hi, lo) pairs whose sum carries the double result.
  *     Fields typed `void*` below are double in SPH_FP64 and float in
  *     SPH_FP32_SPLIT.
  */
@@ -208,7 +209,7 @@ int sph_pack_boundary(const sph_particles *local, const uint32_t *boundary_idx,
  * of mass, momentum, energy and volume from the acoustic Riemann solver
  * (solids: Cauchy stress -p I + S); SPH_PASS_GRADIENT: velocity gradient L.
  * zero_first = 1 overwrites the rate entries of the targets, 0 adds to them
- * (the local-remote pass, step f, continues the compensated sum of step e).
+ * (the local-remote pass, step f, continues the sums of step e from hi + lo).
  * Summation over j runs in ascending source index.  Both arrays must be
  * hash-sorted on `grid`.  The workspace receives a packed copy of the
  * sources' pair inputs (sized by sph_workspace_size for sources->n).
@@ -241,6 +242,30 @@ int sph_count_pairs(const sph_params *params, const sph_grid *grid, const sph_pa
                     const uint32_t *target_idx, const uint32_t *n_targets_dev,
                     const sph_particles *sources, sph_cells source_cells, uint64_t *counts_dev,
                     void *stream);
+
+/* Neighbour census of one interaction pass (Section I: a particle's
+ * neighbours lie in its own bucket or the 26 around it).  Takes the arguments
+ * of sph_interact without the rates and runs the same staging, wavefront
+ * mapping, candidate filter, hit lists and neighbour predicate as that pass
+ * would (pass and params->material choose which), but instead of the pair
+ * terms it writes, for every target i, count_out[i] = the number of sources
+ * j the pass evaluates (r_ij^2 < (2h)^2 on the position difference the pass
+ * rebuilds; j == i and coincident particles, whose terms are exactly zero,
+ * included) and checksum_out[i] = the sum modulo 2^64 of
+ * splitmix64(sources->id[j]) over them, with
+ *   splitmix64(k): z = k + 0x9E3779B97F4A7C15;
+ *                  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9;
+ *                  z = (z ^ (z >> 27)) * 0x94D049BB133111EB; return z ^ (z >> 31)
+ * (Steele, Lea and Flood 2014), so two neighbour sets are compared by id
+ * without listing them.  count_out (u32) and checksum_out (u64) are device
+ * arrays indexed like the target array; entries of targets not visited are
+ * left as they are.  Test and diagnostic use: it costs about a FORCE pass.
+ * Errors: as sph_interact. */
+int sph_neighbor_census(const sph_params *params, const sph_grid *grid, int pass,
+                        const sph_particles *targets, const uint32_t *target_idx,
+                        const uint32_t *n_targets_dev, const sph_particles *sources,
+                        sph_cells source_cells, uint32_t *count_out, uint64_t *checksum_out,
+                        void *ws, size_t ws_bytes, void *stream);
 
 /* Adjoint of the local-local FORCE pass (step e) of a fluid.  With rates_bar
  * the cotangents of the rates (hi only), accumulates into `bar` the

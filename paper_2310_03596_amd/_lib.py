@@ -57,7 +57,7 @@ class SphAdjoint(C.Structure):
 
 
 EXPORTS = ("sph_version", "sph_last_error", "sph_workspace_size", "sph_build_cells", "sph_mark_boundary",
-           "sph_pack_boundary", "sph_interact", "sph_count_pairs", "sph_integrate", "sph_interact_adjoint",
+           "sph_pack_boundary", "sph_interact", "sph_count_pairs", "sph_neighbor_census", "sph_integrate", "sph_interact_adjoint",
            "sph_integrate_adjoint", "sph_permute_adjoint", "sph_centroid", "sph_balance_hash",
            "sph_balance_select", "sph_swap", "sph_centroid_types", "sph_balance_hash_types",
            "sph_balance_select_types")
@@ -94,6 +94,8 @@ def load():
                                P(SphParticles), SphCells, C.c_int, P(SphRates), _vp, C.c_size_t, _vp]
     L.sph_count_pairs.argtypes = [P(SphParams), P(SphGrid), P(SphParticles), _vp, _vp, P(SphParticles),
                                   SphCells, _vp, _vp]
+    L.sph_neighbor_census.argtypes = [P(SphParams), P(SphGrid), C.c_int, P(SphParticles), _vp, _vp,
+                                      P(SphParticles), SphCells, _vp, _vp, _vp, C.c_size_t, _vp]
     L.sph_integrate.argtypes = [P(SphParams), C.c_int, P(SphParticles), P(SphRates), _vp, _vp, _vp,
                                 C.c_size_t, _vp]
     L.sph_interact_adjoint.argtypes = [P(SphParams), P(SphGrid), P(SphParticles), SphCells, P(SphRates),
@@ -164,6 +166,14 @@ def sph_count_pairs(params, grid, targets, tidx_ptr, nt_ptr, sources, source_cel
     return check("sph_count_pairs", load().sph_count_pairs(C.byref(params), C.byref(grid), C.byref(targets),
                                                            tidx_ptr, nt_ptr, C.byref(sources), source_cells,
                                                            counts_ptr, stream))
+
+
+def sph_neighbor_census(params, grid, pass_, targets, tidx_ptr, nt_ptr, sources, source_cells, count_ptr, sum_ptr,
+                        ws_ptr, ws_bytes, stream):
+    return check("sph_neighbor_census",
+                 load().sph_neighbor_census(C.byref(params), C.byref(grid), pass_, C.byref(targets), tidx_ptr, nt_ptr,
+                                            C.byref(sources), source_cells, count_ptr, sum_ptr, ws_ptr, ws_bytes,
+                                            stream))
 
 
 def sph_integrate(params, stage, p, rates, dt_ptr, diag_ptr, ws_ptr, ws_bytes, stream):

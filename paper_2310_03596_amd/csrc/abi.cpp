@@ -271,6 +271,38 @@ int sph_interact(const sph_params *params, const sph_grid *grid, int pass, const
                       "sph_interact");
 }
 
+int sph_neighbor_census(const sph_params *params, const sph_grid *grid, int pass, const sph_particles *targets,
+                        const uint32_t *target_idx, const uint32_t *n_targets_dev, const sph_particles *sources,
+                        sph_cells source_cells, uint32_t *count_out, uint64_t *checksum_out, void *ws,
+                        size_t ws_bytes, void *stream)
+{
+    Grid g;
+    Params P;
+    if (!make_grid(grid, g) || !make_params(params, grid, P)) return SPH_ERR_ARG;
+    if (pass != SPH_PASS_FORCE && pass != SPH_PASS_GRADIENT) return fail(SPH_ERR_ARG, "unknown pass %d", pass);
+    if (!targets || !sources) return fail(SPH_ERR_ARG, "targets/sources is NULL");
+    if (targets->prec != params->prec || sources->prec != params->prec)
+        return fail(SPH_ERR_ARG, "particle precision does not match params.prec");
+    bool solid_force = pass == SPH_PASS_FORCE && params->material == SPH_SOLID_J2;
+    if (!check_particles(targets, "targets", true, solid_force) ||
+        !check_particles(sources, "sources", true, solid_force))
+        return SPH_ERR_ARG;
+    if (target_idx && !n_targets_dev) return fail(SPH_ERR_ARG, "target_idx given without n_targets_dev");
+    if (!source_cells.start || source_cells.ncells != g.ncells)
+        return fail(SPH_ERR_ARG, "source bucket table missing or not on this grid");
+    if (targets->n == 0) return SPH_OK;
+    if (!count_out || !checksum_out) return fail(SPH_ERR_ARG, "count_out/checksum_out is NULL");
+    const uint32_t src_max = 1u << 27;   // as in sph_interact
+    if (sources->n >= src_max) return fail(SPH_ERR_ARG, "sources.n = %u must be below %u", sources->n, src_max);
+    Workspace w;
+    int staged_material = pass == SPH_PASS_FORCE ? params->material : SPH_FLUID_TAIT;
+    if (!check_ws(ws, ws_bytes, sources->n, w, stage_bytes(params->prec, staged_material))) return SPH_ERR_WORKSPACE;
+    bool self = targets->hash == sources->hash;
+    return hip_status(launch_census(P, g, params->prec, pass, *targets, target_idx, n_targets_dev, *sources,
+                                    source_cells.start, self, count_out, checksum_out, w, (hipStream_t)stream),
+                      "sph_neighbor_census");
+}
+
 int sph_count_pairs(const sph_params *params, const sph_grid *grid, const sph_particles *targets,
                     const uint32_t *target_idx, const uint32_t *n_targets_dev, const sph_particles *sources,
                     sph_cells source_cells, uint64_t *counts_dev, void *stream)

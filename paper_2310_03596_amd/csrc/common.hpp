@@ -283,6 +283,9 @@ hipError_t launch_interact(const Params &P, const Grid &g, int prec, int pass, c
                            const uint32_t *tidx, const uint32_t *nt, const sph_particles &sr,
                            const uint32_t *sstart, bool self, int zero_first, const sph_rates &r,
                            const Workspace &ws, hipStream_t s);
+hipError_t launch_census(const Params &P, const Grid &g, int prec, int pass, const sph_particles &tg,
+                         const uint32_t *tidx, const uint32_t *nt, const sph_particles &sr, const uint32_t *sstart,
+                         bool self, uint32_t *count, uint64_t *sum, const Workspace &ws, hipStream_t s);
 hipError_t launch_count_pairs(const Params &P, const Grid &g, int prec, const sph_particles &tg,
                               const uint32_t *tidx, const uint32_t *nt, const sph_particles &sr,
                               const uint32_t *sstart, bool self, uint64_t *counts, hipStream_t s);

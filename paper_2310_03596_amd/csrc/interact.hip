@@ -18,7 +18,8 @@
 //   * hits go to a per-lane list in LDS; when any lane's list is nearly full
 //     (and at the end of the group) every lane evaluates the pair terms of its
 //     listed hits.  Only ~1 candidate in 6 is a neighbour, so separating the
-//     cheap test from the ~140-flop pair body keeps the body dense.
+//     cheap test from the pair body (about a hundred operations) keeps the
+//     body dense.
 // A candidate outside a lane's own 3-bucket range is farther than one bucket
 // side >= 2h on some axis and fails the distance test, so the lanes that run
 // past the end of their range while the longest one finishes change no
@@ -71,6 +72,27 @@ static_assert(Tune<float>::page + kSub <= 256 && Tune<double>::page + kSub <= 25
 static_assert(Tune<float>::page % kSub == 0 && Tune<double>::page % kSub == 0, "reads stay below page + kSub");
 static_assert(Tune<float>::cap <= 255 && Tune<double>::cap <= 255 && kMaxWin <= 255, "marks hold a u8 fill and slot");
 constexpr int kPassAdjoint = 2;            // reverse mode of the FORCE pass (fluid)
+constexpr int kPassCensus = 3;             // neighbour census of a FORCE or GRADIENT pass
+
+// Census outputs: per target, the number of sources the pass evaluates
+// (r^2 < (2h)^2 on the rebuilt d, the pairs at r = 0 included) and the sum,
+// modulo 2^64, of mix64 of their ids; sid is the sources' id array.
+struct Census {
+    uint32_t *count;
+    unsigned long long *sum;
+    const uint32_t *sid;
+};
+
+// SplitMix64 output function (Steele, Lea and Flood, "Fast splittable
+// pseudorandom number generators", 2014): a bijection of 64-bit words whose
+// sums over two different id sets differ with overwhelming probability.
+__device__ inline unsigned long long mix64(uint32_t id)
+{
+    unsigned long long z = (unsigned long long)id + 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
 #ifndef SPH_PAIR_WAVES_PER_EU
 #define SPH_PAIR_WAVES_PER_EU 4
 #endif
@@ -278,12 +300,13 @@ __global__ __launch_bounds__(kPairBlock)
 __attribute__((amdgpu_waves_per_eu(PairOccupancy<real, SOLID, PASS == kPassAdjoint>::value)))
 void k_pairs(Params P, Grid g, PV<real> tg, const uint32_t *__restrict__ tidx, const uint32_t *__restrict__ ntdev,
              Stage<real> src, const uint32_t *__restrict__ sstart, int zero_first, RV<real> R, AV<real> B,
-             const uint2 *__restrict__ plan, const uint32_t *__restrict__ nplan)
+             const uint2 *__restrict__ plan, const uint32_t *__restrict__ nplan, Census cz)
 {
     using v4 = typename Vec4<real>::type;
     constexpr bool SPLIT = sizeof(real) == 4;
     constexpr bool ADJ = PASS == kPassAdjoint;
-    constexpr int NOUT = PASS == SPH_PASS_FORCE ? 6 : (ADJ ? 11 : 9);
+    constexpr bool CENSUS = PASS == kPassCensus;
+    constexpr int NOUT = PASS == SPH_PASS_FORCE ? 6 : (ADJ ? 11 : (CENSUS ? 1 : 9));
     constexpr int kPage = Tune<real>::page;
     constexpr int kHitCap = Tune<real>::cap;
     // List entries and marks are laid out so that the 64 lanes of a wavefront
@@ -326,6 +349,9 @@ void k_pairs(Params P, Grid g, PV<real> tg, const uint32_t *__restrict__ tidx, c
         if (tile * kPairBlock + wave * kWave >= nt) return;
         valid = t < nt;
         i = valid ? (tidx ? tidx[t] : t) : 0u;
+        // a listed index outside the target array names no target
+        valid = valid && i < tg.n;
+        i = valid ? i : 0u;
     }
 
     const PairK<real> K = make_pair_k<real>(P);
@@ -354,7 +380,7 @@ void k_pairs(Params P, Grid g, PV<real> tg, const uint32_t *__restrict__ tidx, c
     real rbi[6];   // adjoint: the target's rate cotangents
     if constexpr (PASS == SPH_PASS_FORCE || ADJ) {
         load_part<real, SOLID>(tg, i, I);
-    } else {
+    } else if constexpr (!CENSUS) {
 #pragma unroll
         for (int d = 0; d < 3; ++d) I.v[d] = tg.v[d][i];
     }
@@ -367,7 +393,7 @@ void k_pairs(Params P, Grid g, PV<real> tg, const uint32_t *__restrict__ tidx, c
 #pragma unroll
     for (int k = 0; k < NOUT; ++k) {
         double s0 = 0.0;
-        if constexpr (!ADJ) {
+        if constexpr (!ADJ && !CENSUS) {
             real *hi = PASS == SPH_PASS_FORCE ? R.hi[k] : R.Lhi[k];
             real *lo = PASS == SPH_PASS_FORCE ? R.lo[k] : R.Llo[k];
             if (!zero_first && valid) {
@@ -378,12 +404,15 @@ void k_pairs(Params P, Grid g, PV<real> tg, const uint32_t *__restrict__ tidx, c
         acc[k].s = s0;
     }
 
+    uint32_t ncen = 0;             // census: pairs evaluated
+    unsigned long long scen = 0;   // census: sum of mix64 of their ids
     int cnt = 0;   // entries in the lane's list
     // Records of one listed hit; the next hit's are loaded while the current
     // pair is evaluated (software pipelining hides the L2 latency).
     struct Rec {
         v4 p, a, b, s0, s1;
         real qy, qz;
+        uint32_t j;
     };
     // entry s of the lane's list; (mk, nb) walk the lane's marks as s ascends
     // (each mark covers at least one entry, so one step suffices)
@@ -403,6 +432,8 @@ void k_pairs(Params P, Grid g, PV<real> tg, const uint32_t *__restrict__ tidx, c
         const uint32_t ob = jj * (uint32_t)sizeof(v4);
         auto at = [&](const v4 *base, uint32_t o) { return *reinterpret_cast<const v4 *>(reinterpret_cast<const char *>(base) + o); };
         q.p = at(src.pos, ob);
+        q.j = jj;
+        if constexpr (CENSUS) return q;
         const uint32_t ob2 = ob * rec_stride<real>;
         q.a = at(src.va, ob2);
         if constexpr (PASS == SPH_PASS_FORCE || ADJ) q.b = at(src.vb, ob2);
@@ -417,18 +448,20 @@ void k_pairs(Params P, Grid g, PV<real> tg, const uint32_t *__restrict__ tidx, c
             real d[3];
             diff<real>(T, cur.p, cur.qy, cur.qz, d);
             const real r2 = r2_of<real>(d);
-            const v4 a = cur.a;
             // the neighbour predicate, on the exact and odd d (so a pair is in or
             // out for both of its particles); the filter's shortlist is wider
             if (!(r2 < R2)) {
                 // outside the support: nothing to add
+            } else if constexpr (CENSUS) {
+                ++ncen;
+                scen += mix64(cz.sid[cur.j]);
             } else if constexpr (PASS == SPH_PASS_FORCE) {
                 const v4 b = cur.b;
                 Part<real, SOLID> J;
-                J.v[0] = a.x;
-                J.v[1] = a.y;
-                J.v[2] = a.z;
-                J.w = a.w;
+                J.v[0] = cur.a.x;
+                J.v[1] = cur.a.y;
+                J.v[2] = cur.a.z;
+                J.w = cur.a.w;
                 J.rho = b.x;
                 J.p = b.y;
                 J.c = b.z;
@@ -447,10 +480,10 @@ void k_pairs(Params P, Grid g, PV<real> tg, const uint32_t *__restrict__ tidx, c
                 for (int k = 0; k < 6; ++k) acc[k].add(o[k]);
             } else if constexpr (ADJ) {
                 Part<real, false> J, Ii;
-                J.v[0] = a.x;
-                J.v[1] = a.y;
-                J.v[2] = a.z;
-                J.w = a.w;
+                J.v[0] = cur.a.x;
+                J.v[1] = cur.a.y;
+                J.v[2] = cur.a.z;
+                J.w = cur.a.w;
                 J.rho = cur.b.x;
                 J.p = cur.b.y;
                 J.c = cur.b.z;
@@ -474,9 +507,9 @@ void k_pairs(Params P, Grid g, PV<real> tg, const uint32_t *__restrict__ tidx, c
 #pragma unroll
                 for (int k = 0; k < 11; ++k) acc[k].add(o[k]);
             } else {
-                const real vj[3] = {a.x, a.y, a.z};
+                const real vj[3] = {cur.a.x, cur.a.y, cur.a.z};
                 real o[9];
-                pair_grad<real>(d, r2, I.v, vj, a.w, K, o);
+                pair_grad<real>(d, r2, I.v, vj, cur.a.w, K, o);
 #pragma unroll
                 for (int k = 0; k < 9; ++k) acc[k].add(o[k]);
             }
@@ -653,7 +686,10 @@ void k_pairs(Params P, Grid g, PV<real> tg, const uint32_t *__restrict__ tidx, c
         flush();
     }
     if (!valid) return;
-    if constexpr (ADJ) {
+    if constexpr (CENSUS) {
+        cz.count[i] = ncen;
+        cz.sum[i] = scen;
+    } else if constexpr (ADJ) {
         // accumulate the cotangents of x, v, omega, rho, p, c, e
         real *out[11] = {B.x[0], B.x[1], B.x[2], B.v[0], B.v[1], B.v[2], B.w, B.rho, B.p, B.c, B.e};
 #pragma unroll
@@ -765,10 +801,14 @@ __global__ __launch_bounds__(kBlock) void k_count(Params P, Grid g, PV<real> tg,
     }
 }
 
+// One pass.  The census (PASS = kPassCensus) runs the staging, wavefront
+// mapping, filter and lists of the FORCE pass of the same material (SOLID),
+// or of the GRADIENT pass when census_of_gradient is set.
 template <typename real, int PASS, bool SOLID>
 hipError_t go(const Params &P, const Grid &g, const sph_particles &tg, const uint32_t *tidx,
               const uint32_t *nt, const sph_particles &sr, const uint32_t *sstart, bool self, int zero_first,
-              const sph_rates &r, const sph_adjoint &bar, const Workspace &ws, hipStream_t s)
+              const sph_rates &r, const sph_adjoint &bar, const Workspace &ws, hipStream_t s,
+              const Census cz = Census{}, bool census_of_gradient = false)
 {
     if (tg.n == 0) return hipSuccess;
     constexpr bool ADJ = PASS == kPassAdjoint;
@@ -784,7 +824,8 @@ hipError_t go(const Params &P, const Grid &g, const sph_particles &tg, const uin
     // consecutive targets per wavefront.)
     const uint64_t nrows = (uint64_t)g.ny * (uint64_t)g.nz;
     const uint64_t pmax = div_up(tg.n, kWave) + nrows;
-    if (!SOLID && PASS != SPH_PASS_GRADIENT && self && !tidx && pmax * sizeof(uint2) <= 4ull * tg.n) {
+    if (!SOLID && PASS != SPH_PASS_GRADIENT && !census_of_gradient && self && !tidx &&
+        pmax * sizeof(uint2) <= 4ull * tg.n) {
         plan = reinterpret_cast<uint2 *>(ws.keys[0]);
         nplan = ws.keys[1];
         blocks = div_up(pmax, kWaves);
@@ -798,11 +839,11 @@ hipError_t go(const Params &P, const Grid &g, const sph_particles &tg, const uin
     if (self)
         k_pairs<real, PASS, SOLID, true><<<blocks, kPairBlock, 0, s>>>(P, g, view<real>(tg), tidx, nt, st, sstart,
                                                                      zero_first, view<real>(r), view<real>(bar),
-                                                                     plan, nplan);
+                                                                     plan, nplan, cz);
     else
         k_pairs<real, PASS, SOLID, false><<<blocks, kPairBlock, 0, s>>>(P, g, view<real>(tg), tidx, nt, st, sstart,
                                                                       zero_first, view<real>(r), view<real>(bar),
-                                                                      plan, nplan);
+                                                                      plan, nplan, cz);
     return hipGetLastError();
 }
 
@@ -844,6 +885,24 @@ hipError_t launch_count_pairs(const Params &P, const Grid &g, int prec, const sp
                                                             sstart, c);
     }
     return hipGetLastError();
+}
+
+hipError_t launch_census(const Params &P, const Grid &g, int prec, int pass, const sph_particles &tg,
+                         const uint32_t *tidx, const uint32_t *nt, const sph_particles &sr, const uint32_t *sstart,
+                         bool self, uint32_t *count, uint64_t *sum, const Workspace &ws, hipStream_t s)
+{
+    const sph_rates none{};
+    const sph_adjoint nobar{};
+    const Census cz{count, reinterpret_cast<unsigned long long *>(sum), sr.id};
+    const bool grad = pass == SPH_PASS_GRADIENT;
+    const bool solid = !grad && P.material == SPH_SOLID_J2;
+    if (prec == SPH_FP64) {
+        if (solid)
+            return go<double, kPassCensus, true>(P, g, tg, tidx, nt, sr, sstart, self, 1, none, nobar, ws, s, cz);
+        return go<double, kPassCensus, false>(P, g, tg, tidx, nt, sr, sstart, self, 1, none, nobar, ws, s, cz, grad);
+    }
+    if (solid) return go<float, kPassCensus, true>(P, g, tg, tidx, nt, sr, sstart, self, 1, none, nobar, ws, s, cz);
+    return go<float, kPassCensus, false>(P, g, tg, tidx, nt, sr, sstart, self, 1, none, nobar, ws, s, cz, grad);
 }
 
 hipError_t launch_interact_adjoint(const Params &P, const Grid &g, int prec, const sph_particles &p,

@@ -70,28 +70,6 @@ __device__ inline void inv_len<double>(double r2, double &r, double &rinv)
     r = r2 * y;
 }
 
-// Compensated (hi, lo) accumulator for float (TwoSum: the rounding error of
-// every addition is kept exactly in lo); plain sum for double.
-template <typename real>
-struct Sum;
-template <>
-struct Sum<float> {
-    float s, c;
-    __device__ inline void add(float x)
-    {
-        float t = s + x;
-        float bp = t - s;
-        float ap = t - bp;
-        c += (s - ap) + (x - bp);
-        s = t;
-    }
-};
-template <>
-struct Sum<double> {
-    double s, c;
-    __device__ inline void add(double x) { s += x; }
-};
-
 // Kernel and Riemann constants in the form's precision: F3, F225 and F075
 // are Fc times the cubic spline's coefficients 3, 9/4 and 3/4; hb4 = 2 beta
 // and hbq = beta / 8 are the Riemann factor beta / 2 times 4 and 1 / 4 (powers

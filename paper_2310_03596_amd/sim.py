@@ -108,6 +108,18 @@ class Sim:
         v = c.cpu().numpy()
         return int(v[0]), int(v[1])
 
+    def census(self, pass_=L.SPH_PASS_FORCE) -> tuple[np.ndarray, np.ndarray]:
+        """Per particle of the current (sorted) state: number of sources the
+        pass evaluates and the mixed-id checksum of their ids."""
+        dev = self.A.x.device
+        cnt = torch.zeros(self.n, dtype=torch.int32, device=dev)
+        chk = torch.zeros(self.n, dtype=torch.int64, device=dev)
+        a = self.A.struct()
+        L.sph_neighbor_census(self.params, self.grid, pass_, a, None, None, a, self.cells, cnt.data_ptr(),
+                              chk.data_ptr(), self.ws.data_ptr(), self.ws_bytes, stream_handle())
+        torch.cuda.synchronize()
+        return cnt.cpu().numpy().view(np.uint32), chk.cpu().numpy().view(np.uint64)
+
     def diagnostics(self) -> np.ndarray:
         return self.diag[self.cur, :7].cpu().numpy()
 
@@ -182,6 +194,27 @@ class SharePass:
         L.sph_interact(self.params, self.grid, L.SPH_PASS_FORCE, self.LB.struct(), self.bidx.data_ptr(),
                        self.nb.data_ptr(), self.RB.struct(), cells_struct(self.rstart, self.nc), 0,
                        self.rates.struct(), self.ws.data_ptr(), self.ws_bytes, stream_handle())
+
+    def census(self) -> tuple[np.ndarray, np.ndarray, np.ndarray, np.ndarray]:
+        """Neighbour census of the local-local pass (every local particle) and
+        of the local-remote pass (boundary list): counts and checksums, each
+        indexed like the sorted local array (entries of the local-remote
+        census outside the list stay 0)."""
+        dev = self.LB.x.device
+        out = []
+        for remote in (False, True):
+            cnt = torch.zeros(self.nl, dtype=torch.int32, device=dev)
+            chk = torch.zeros(self.nl, dtype=torch.int64, device=dev)
+            src = self.RB if remote else self.LB
+            start = self.rstart if remote else self.lstart
+            L.sph_neighbor_census(self.params, self.grid, L.SPH_PASS_FORCE, self.LB.struct(),
+                                  self.bidx.data_ptr() if remote else None, self.nb.data_ptr() if remote else None,
+                                  src.struct(), cells_struct(start, self.nc), cnt.data_ptr(), chk.data_ptr(),
+                                  self.ws.data_ptr(), self.ws_bytes, stream_handle())
+            out += [cnt, chk]
+        torch.cuda.synchronize()
+        return (out[0].cpu().numpy().view(np.uint32), out[1].cpu().numpy().view(np.uint64),
+                out[2].cpu().numpy().view(np.uint32), out[3].cpu().numpy().view(np.uint64))
 
     def run(self):
         self.build()

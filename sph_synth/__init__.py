@@ -342,10 +342,13 @@ def jittered_lattice(n_side: int, seed: int, dx: float = 1e-3, jitter: float = 0
 
 
 def solid_block(n_side: int, seed: int, dx: float = 1e-3, vz: float = -50.0,
-                s_sigma: float = 0.0) -> Workload:
+                s_sigma: float = 0.0, s_axial: float = 0.0, stretch_rate: float = 0.0) -> Workload:
     """Small jittered block of C3's material moving onto the z = 0 wall.
 
     Draws: jitter (n,3), velocity perturbation N(0, 1) (n,3), stress N(0, s_sigma) (n,6).
+    Optional, no draws: a uniaxial deviatoric stress s_axial diag(2/3, -1/3, -1/3)
+    (von Mises stress s_axial) added to S, and an isochoric stretch along x,
+    v += stretch_rate (x - xc, -(y - yc) / 2, -(z - zc) / 2), which raises it.
     """
     rng = np.random.default_rng(seed)
     x = _lattice(n_side, n_side, n_side, dx)
@@ -356,6 +359,11 @@ def solid_block(n_side: int, seed: int, dx: float = 1e-3, vz: float = -50.0,
     # deviatoric: remove the trace
     tr = (S[:, 0] + S[:, 1] + S[:, 2]) / 3.0
     S[:, :3] -= tr[:, None]
+    if s_axial:
+        S[:, :3] += s_axial * np.array([2.0 / 3.0, -1.0 / 3.0, -1.0 / 3.0])
+    if stretch_rate:
+        xc = x.mean(0)
+        v += stretch_rate * (x - xc) * np.array([1.0, -0.5, -0.5])
     w = c3_cylinder(dx=dx, radius=2 * dx, nlayers=2)
     rho = np.full(x.shape[0], w.params["rho0"])
     omega, m, E, ids = _fluid_state(x, v, rho, dx)

@@ -152,6 +152,37 @@ def test_interact_rejects_bad_arguments():
         assert "must be below 134217728" in _last()
 
 
+def test_neighbor_census_rejects_bad_arguments():
+    lib = L.load()
+    g = _grid()
+    cells = L.SphCells(FAKE, 64, 0)
+    p = _particles(10)
+
+    def census(params, pass_, t, s, count, csum, tidx=None, nt=None, cl=cells):
+        return lib.sph_neighbor_census(C.byref(params), C.byref(g), pass_, C.byref(t), tidx, nt, C.byref(s), cl,
+                                       count, csum, FAKE, 1 << 40, None)
+
+    assert census(_params(h=0.6), 0, p, p, FAKE, FAKE) == L.SPH_ERR_ARG
+    assert "smaller than the support" in _last()
+    assert census(_params(), 5, p, p, FAKE, FAKE) == L.SPH_ERR_ARG
+    assert "unknown pass" in _last()
+    assert census(_params(), 0, p, p, None, FAKE) == L.SPH_ERR_ARG
+    assert "count_out" in _last()
+    assert census(_params(), 0, p, p, FAKE, None) == L.SPH_ERR_ARG
+    assert census(_params(), 0, p, p, FAKE, FAKE, tidx=FAKE) == L.SPH_ERR_ARG
+    assert census(_params(), 0, p, p, FAKE, FAKE, cl=L.SphCells(FAKE, 63, 0)) == L.SPH_ERR_ARG
+    assert census(_params(prec=L.SPH_FP32_SPLIT), 0, p, p, FAKE, FAKE) == L.SPH_ERR_ARG
+    ps = _params()
+    ps.material, ps.K, ps.G = L.SPH_SOLID_J2, 1e9, 1e9
+    assert census(ps, 0, p, p, FAKE, FAKE) == L.SPH_ERR_ARG
+    assert "S[0]" in _last()
+    big = _particles(1 << 27)
+    assert census(_params(), 0, p, big, FAKE, FAKE) == L.SPH_ERR_ARG
+    assert "must be below 134217728" in _last()
+    # no targets: nothing to do, even without outputs
+    assert census(_params(), 0, _particles(0), p, None, None) == L.SPH_OK
+
+
 def test_integrate_and_adjoint_reject_bad_arguments():
     lib = L.load()
     p = _particles(10)

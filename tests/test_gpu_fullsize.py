@@ -49,15 +49,16 @@ def test_column_full_size(prec):
     assert_within(got, ref, bound, "column rates (sample)")
 
 
-def test_cylinder_full_size_solid_loops():
-    """4M-particle cylinder, FP32 split: GRADIENT pass, stress stage and FORCE
-    pass of one solid step, each checked on a sample from the device's inputs."""
+@pytest.mark.parametrize("prec", [FP32, FP64])
+def test_cylinder_full_size_solid_loops(prec):
+    """4M-particle cylinder: GRADIENT pass, stress stage and FORCE pass of one
+    solid step, each checked on a sample from the device's inputs."""
     from paper_2310_03596_amd import _lib as L
     from paper_2310_03596_amd.sim import Sim
     from paper_2310_03596_amd.state import stream_handle
     wl = S.c3_cylinder()
-    print(f"[cylinder full] n={wl.n}", flush=True)
-    sim = Sim(wl, FP32)
+    print(f"[cylinder full] n={wl.n} prec={prec}", flush=True)
+    sim = Sim(wl, prec)
     sim.build()
     sim.interact(pass_=L.SPH_PASS_GRADIENT)
     torch.cuda.synchronize()
@@ -65,7 +66,7 @@ def test_cylinder_full_size_solid_loops():
     start = cpu.cell_start(st.hash, cpu.ncells(wl.grid))
     tidx = _sample(wl.n, 2048, 91)
     refL = cpu.interact(wl.params, wl.grid, cpu.GRADIENT, st, st, start, True, tidx=tidx)[tidx]
-    bL = rate_bound(wl.params, wl.grid, cpu.GRADIENT, st, st, start, True, FP32, tidx=tidx)[tidx]
+    bL = rate_bound(wl.params, wl.grid, cpu.GRADIENT, st, st, start, True, prec, tidx=tidx)[tidx]
     Lgpu = sim.rates.grad().T.cpu().numpy()
     assert_within(Lgpu[tidx], refL, bL, "cylinder velocity gradient (sample)")
     # stress stage from the device's L
@@ -79,16 +80,16 @@ def test_cylinder_full_size_solid_loops():
     o = cpu.State(len(tidx), True)
     o.m[:] = 1.0
     o.w[:] = 1.0
-    o.S[:] = S0[tidx].astype(np.float32).astype(np.float64)
+    o.S[:] = S0[tidx]
     cpu.integrate(wl.params, cpu.STRESS, o, L=Lgpu[tidx], dt=dt)
     scale = np.abs(o.S).max() + wl.params["G"] * 1e-6
-    assert np.abs(h1["S"][tidx] - o.S).max() <= 2e-6 * scale
+    assert np.abs(h1["S"][tidx] - o.S).max() <= (2e-6 if prec == FP32 else 1e-12) * scale
     # FORCE pass with the updated stress
     sim.interact()
     torch.cuda.synchronize()
     st2 = oracle_state(sim.A.host(), True)
     ref = cpu.interact(wl.params, wl.grid, cpu.FORCE, st2, st2, start, True, tidx=tidx)[tidx]
-    b = rate_bound(wl.params, wl.grid, cpu.FORCE, st2, st2, start, True, FP32, tidx=tidx)[tidx]
+    b = rate_bound(wl.params, wl.grid, cpu.FORCE, st2, st2, start, True, prec, tidx=tidx)[tidx]
     assert_within(sim.rates.force().T.cpu().numpy()[tidx], ref, b, "cylinder FORCE (sample)")
 
 
@@ -131,3 +132,10 @@ def test_share_full_size(layout):
     bound += rate_bound(loc.params, loc.grid, cpu.FORCE, sl, sr, rstart, False, FP32, tidx=tidx[inB])
     got = sp.rates.force().T.cpu().numpy()
     assert_within(got[tidx], ref[tidx], bound[tidx], f"share {layout} rates (sample)")
+    # neighbour sets of both passes on the same sample (tests/test_gpu_census.py)
+    from tests.test_gpu_census import check_census
+    c_ll, s_ll, c_lr, s_lr = sp.census()
+    hh = loc.params["h"]
+    check_census(c_ll, s_ll, tidx, hl["x"][tidx], hl["x"], hl["id"], hh, FP32, f"share {layout} local-local sample")
+    tb = tidx[inB]
+    check_census(c_lr, s_lr, tb, hl["x"][tb], hr["x"], hr["id"], hh, FP32, f"share {layout} local-remote sample")

@@ -38,12 +38,13 @@ def test_hvi_steps_match_oracle_each_step(prec):
 
 
 @pytest.mark.timeout(900)
-def test_hvi_full_size_sampled():
+@pytest.mark.parametrize("prec", [FP32, FP64])
+def test_hvi_full_size_sampled(prec):
     from paper_2310_03596_amd import _lib as L
     from paper_2310_03596_amd.sim import Sim
     wl = S.c6_hvi()
-    print(f"[hvi full] n={wl.n}", flush=True)
-    sim = Sim(wl, FP32)
+    print(f"[hvi full] n={wl.n} prec={prec}", flush=True)
+    sim = Sim(wl, prec)
     for _ in range(3):
         sim.step()
     sim.build()
@@ -61,8 +62,9 @@ def test_hvi_full_size_sampled():
     for k, i in enumerate(tidx):
         pe[k], ce[k] = cpu.eos(wl.params, h["m"][i] / h["w"][i], h["e"][i])
     ps = wl.params["rho0"] * wl.params["c0"] ** 2
-    assert np.abs(h["p"][tidx] - pe).max() <= 2e-6 * ps
-    assert np.abs(h["c"][tidx] - ce).max() <= 2e-6 * ce.max()
+    tol = 2e-6 if prec == FP32 else 1e-12
+    assert np.abs(h["p"][tidx] - pe).max() <= tol * ps
+    assert np.abs(h["c"][tidx] - ce).max() <= tol * ce.max()
     assert (h["p"][tidx] >= wl.params["p_cut"]).all()
     assert np.abs(h["p"][near]).max() > 1e8      # the shock has formed
     # FORCE pass on the sample
@@ -71,6 +73,6 @@ def test_hvi_full_size_sampled():
     st = oracle_state(sim.A.host(), True)
     start = cpu.cell_start(st.hash, cpu.ncells(wl.grid))
     ref = cpu.interact(wl.params, wl.grid, cpu.FORCE, st, st, start, True, tidx=tidx)[tidx]
-    b = rate_bound(wl.params, wl.grid, cpu.FORCE, st, st, start, True, FP32, tidx=tidx)[tidx]
+    b = rate_bound(wl.params, wl.grid, cpu.FORCE, st, st, start, True, prec, tidx=tidx)[tidx]
     assert_within(sim.rates.force().T.cpu().numpy()[tidx], ref, b, "hvi FORCE (sample)")
     assert L.SPH_EOS_MIE_GRUNEISEN == wl.params["eos"]

@@ -94,6 +94,20 @@ def _far_origin():
     return w
 
 
+def _exact_edge():
+    """Pairs exactly at r = 2h and r = h: h = 1/16 and a lattice of spacing
+    1/8 = 2h (with a second lattice shifted by h along x), so every
+    difference, offset and squared distance is exact in both forms and the
+    strict predicate r^2 < (2h)^2 leaves the pairs at r = 2h out."""
+    h = 0.0625
+    w = S.random_cloud(2 * 6 ** 3, seed=59, h=h, box=0.75, rho_sigma=0.01)
+    g = np.arange(6) * (2 * h) + 2 * h
+    a = np.stack(np.meshgrid(g, g, g, indexing="ij"), axis=-1).reshape(-1, 3)
+    b = a + np.array([h, 0.0, 0.0])
+    w.x = np.concatenate([a, b])
+    return w
+
+
 CASES = {
     "one": lambda: S.random_cloud(1, seed=50, h=0.05),
     "cloud2049": lambda: S.random_cloud(2049, seed=53, h=0.04, rho_sigma=0.01),
@@ -104,6 +118,7 @@ CASES = {
     "lattice12": lambda: S.jittered_lattice(12, seed=55, rho_sigma=0.01),
     "far_origin": _far_origin,
     "coincident": _coincident,
+    "exact_edge": _exact_edge,
 }
 
 
@@ -136,8 +151,7 @@ def test_build_cells_bit_exact(case, prec):
 
 
 @pytest.mark.parametrize("prec", PRECS)
-@pytest.mark.parametrize("case", ["one", "cloud2049", "cube8000", "faces", "clamped", "dense", "lattice12",
-                                  "far_origin", "coincident"])
+@pytest.mark.parametrize("case", list(CASES))
 def test_force_pass_matches_oracle(case, prec):
     wl = CASES[case]()
     print(f"[force] case={case} prec={prec} n={wl.n}", flush=True)
@@ -243,6 +257,25 @@ def test_solid_steps_match_oracle_each_step(prec):
     wl = S.solid_block(8, seed=59)
     worst = _step_vs_oracle(wl, prec, 3, TOL_STEP[prec])
     print("solid worst per-field error:", worst)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_solid_block_yields_with_hardening(prec):
+    """A block at 0.9 of the yield stress under an isochoric stretch that
+    raises its deviator by about 100 MPa a step: the interior goes plastic in
+    the first step, so the radial return with linear hardening (the
+    cylinder's H = E / 100) decides S and the plastic strain at every step."""
+    wl = S.solid_block(8, seed=62, vz=0.0, s_sigma=1e6, s_axial=270e6, stretch_rate=2e4)
+    assert wl.params["H"] == pytest.approx(70e9 / 100)
+    worst = _step_vs_oracle(wl, prec, 3, TOL_STEP[prec])
+    print("yielding block worst per-field error:", worst)
+    # the same three steps went plastic (inside at the first step, the
+    # surface, where the stretch is resolved only in part, soon after)
+    sim = _sim(wl, prec)
+    sim.run(3)
+    torch.cuda.synchronize()
+    ep = sim.A.host()["ep"]
+    assert (ep > 0).mean() > 0.5 and ep.max() > 1e-3, ((ep > 0).mean(), ep.max())
 
 
 @pytest.mark.parametrize("prec", PRECS)
