@@ -169,7 +169,8 @@ def other_workloads_leg():
 def adjoint_leg(prec, reps=5):
     """Adjoint/forward time ratio on the 250,047-particle box: 50 fixed-dt
     steps with checkpoints every 10 (forward), then the reverse pass
-    (recompute of every segment + reverse kernels).  Best of `reps`."""
+    (recompute of every segment + reverse kernels).  Best of `reps`.  Also
+    returns the gradient (dJ/dv0, dJ/dc0) of the last round."""
     import torch
 
     import sph_synth as S
@@ -177,20 +178,32 @@ def adjoint_leg(prec, reps=5):
 
     wl = S.c5_box()
     best = None
+    grad = None
     for _ in range(reps + 1):      # the first round warms up
         ro = KineticEnergyRollout(wl, prec, wl.extra["steps"], wl.extra["ckpt"], wl.extra["dt"])
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         ro.forward(wl.v, wl.params["c0"])
         t1 = time.perf_counter()
-        ro.backward(1.0)
+        grad = ro.backward(1.0)
         t2 = time.perf_counter()
         cur = (t1 - t0, t2 - t1)
         best = cur if best is None or sum(cur) < sum(best) else best
+        del ro
     fwd, bwd = best
     return {"n_particles": wl.n, "steps": wl.extra["steps"], "checkpoint_every": wl.extra["ckpt"],
             "forward_s": fwd, "backward_s": bwd, "adjoint_over_forward": bwd / fwd,
-            "form": "FP32 split" if prec == 1 else "FP64"}
+            "form": "FP32 split" if prec == 1 else "FP64"}, grad
+
+
+def adjoint_error(g32, g64):
+    """FP32-split gradient against the FP64 one: max-norm and RMS of the
+    difference over those of the FP64 gradient, and the relative c0 error."""
+    import numpy as np
+    (v32, c32), (v64, c64) = g32, g64
+    return {"dJ_dv0_maxnorm_rel": float(np.abs(v32 - v64).max() / np.abs(v64).max()),
+            "dJ_dv0_rms_rel": float(np.sqrt(np.mean((v32 - v64) ** 2) / np.mean(v64 ** 2))),
+            "dJ_dc0_rel": float(abs(c32 - c64) / abs(c64))}
 
 
 def share_leg(reps=5):
@@ -428,8 +441,10 @@ def main():
     if not args.no_share:
         out["other_workloads"] = other_workloads_leg()
     if not args.no_adjoint:
-        out["adjoint"] = {"fp32_split": adjoint_leg(1), "fp64": adjoint_leg(0)}
-        out["adjoint_forward_ratio"] = out["adjoint"]["fp32_split"]["adjoint_over_forward"]
+        a32, g32 = adjoint_leg(1)
+        a64, g64 = adjoint_leg(0)
+        out["adjoint"] = {"fp32_split": a32, "fp64": a64, "fp32_gradient_error_vs_fp64": adjoint_error(g32, g64)}
+        out["adjoint_forward_ratio"] = a32["adjoint_over_forward"]
     if not args.no_share:
         out["share_pass"] = share_leg()
         out["balance_round"] = balance_leg()

@@ -225,10 +225,12 @@ int sph_interact(const sph_params *params, const sph_grid *grid, int pass,
  * then the EOS (rho = m / omega, p, c, e).  SPH_STAGE_STRESS (solids): Jaumann
  * rate of S from L, J2 radial return with linear hardening.  SPH_STAGE_EOS:
  * the EOS alone (priming the initial state).  dt_dev: one double on the
- * device.  diag_dev (7 doubles, may be NULL for SPH_STAGE_STRESS): [0] next dt
+ * device.  diag_dev (8 doubles, may be NULL for SPH_STAGE_STRESS): [0] next dt
  * = cfl h / max(c + |v|), [1] total mass, [2..4] total momentum, [5] total
- * energy sum m E, [6] kinetic energy; sums are deterministic.  Errors:
- * SPH_ERR_ARG, SPH_ERR_WORKSPACE. */
+ * energy sum m E, [6] kinetic energy, [7] number of particles with a field
+ * that is not finite after the stage (x, v, m, omega, E, rho, p, c: a
+ * blow-up guard the caller reads when it synchronises); sums are
+ * deterministic.  Errors: SPH_ERR_ARG, SPH_ERR_WORKSPACE. */
 int sph_integrate(const sph_params *params, int stage, sph_particles *p, const sph_rates *rates,
                   const double *dt_dev, double *diag_dev, void *ws, size_t ws_bytes, void *stream);
 
@@ -267,19 +269,38 @@ int sph_neighbor_census(const sph_params *params, const sph_grid *grid, int pass
                         sph_cells source_cells, uint32_t *count_out, uint64_t *checksum_out,
                         void *ws, size_t ws_bytes, void *stream);
 
-/* Adjoint of the local-local FORCE pass (step e) of a fluid.  With rates_bar
- * the cotangents of the rates (hi only), accumulates into `bar` the
- * cotangents of x, v, omega, rho, p, c and e of every particle of the
- * hash-sorted array p.  Each pair term T(s_i, s_j) equals +-T(s_j, s_i)
- * (odd for mass, momentum and energy, even for volume), so a particle
- * gathers its whole cotangent from its neighbours' rate cotangents without
- * atomics.  The workspace (sph_workspace_size with SPH_SOLID_J2, which has
- * room for the extra staged records) receives packed copies of the
- * particles and their rate cotangents.  Errors: SPH_ERR_ARG (also p->n at
- * or above 2^27), SPH_ERR_WORKSPACE, SPH_ERR_UNSUPPORTED (solids). */
-int sph_interact_adjoint(const sph_params *params, const sph_grid *grid, const sph_particles *p,
-                         sph_cells cells, const sph_rates *rates_bar, const sph_adjoint *bar,
-                         void *ws, size_t ws_bytes, void *stream);
+/* Adjoint of a FORCE pass of a fluid, steps (e) and (f).  The pass being
+ * reversed is the sph_interact call with the same targets, target_idx,
+ * n_targets_dev, sources and source_cells.  Each pair term satisfies
+ * T(s_j, s_i) = +-T(s_i, s_j) (odd for mass, momentum and energy, even for
+ * volume), so every target gathers its cotangent from its own pairs without
+ * atomics: for each target i and source j within 2h it accumulates into
+ * `bar` (at i) the cotangent of x, v, omega, rho, p, c and e of target i
+ * from the weight  rates_bar_targets[i] + sigma * rates_bar_sources[j], where
+ * rates_bar_targets (hi only; NULL = zero) is the cotangent of the targets'
+ * rates summed by this pass and rates_bar_sources (hi only; NULL = zero) that
+ * of the sources' rates in the mirrored pass, which sums T(s_j, s_i).
+ *   - local-local pass (e): targets = sources, both cotangents the same;
+ *   - local-remote pass (f), local side: targets = the local array with its
+ *     boundary list, sources = the remote array, rates_bar_targets = the
+ *     local rates' cotangent, rates_bar_sources = the remote particles' rate
+ *     cotangent (from their owner, whose own pass (f) mirrors this one), or
+ *     NULL when the remote rates are not differentiated;
+ *   - remote side of (f): targets = the remote array, sources = the local
+ *     array, rates_bar_targets = NULL, rates_bar_sources = the local rates'
+ *     cotangent: the cotangent of the received particles, which their owner
+ *     adds to its own.
+ * The pair terms read p and c, not c0: d/dc0 comes from the EOS reverse
+ * (sph_integrate_adjoint, SPH_STAGE_EOS).  The workspace (sph_workspace_size
+ * for sources->n with SPH_SOLID_J2, which has room for the extra staged
+ * records) receives packed copies of the sources and their cotangents.
+ * Errors: SPH_ERR_ARG (also sources->n at or above 2^27, both cotangents
+ * NULL), SPH_ERR_WORKSPACE, SPH_ERR_UNSUPPORTED (solids). */
+int sph_interact_adjoint(const sph_params *params, const sph_grid *grid, const sph_particles *targets,
+                         const uint32_t *target_idx, const uint32_t *n_targets_dev,
+                         const sph_particles *sources, sph_cells source_cells,
+                         const sph_rates *rates_bar_targets, const sph_rates *rates_bar_sources,
+                         const sph_adjoint *bar, void *ws, size_t ws_bytes, void *stream);
 
 /* Adjoint of step (g) for a fluid.  stage = SPH_STAGE_MOTION: p is the state
  * BEFORE the update (hash-sorted), rates its FORCE rates; on entry bar holds

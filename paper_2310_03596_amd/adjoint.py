@@ -157,8 +157,9 @@ class KineticEnergyRollout:
                     ps = srt.struct()
                     L.sph_integrate_adjoint(sim.params, L.SPH_STAGE_MOTION, ps, rates.struct(), fixed,
                                             bar.struct(), rbar.struct(), None, None, 0, st_b)
-                    L.sph_interact_adjoint(sim.params, sim.grid, ps, cells_struct(start, sim.nc), rbar.struct(),
-                                           bar.struct(), ws_adj.data_ptr(), ws_adj_bytes, st_b)
+                    rb = rbar.struct()
+                    L.sph_interact_adjoint(sim.params, sim.grid, ps, None, None, ps, cells_struct(start, sim.nc),
+                                           rb, rb, bar.struct(), ws_adj.data_ptr(), ws_adj_bytes, st_b)
                     L.sph_integrate_adjoint(sim.params, L.SPH_STAGE_EOS, ps, None, None, bar.struct(), None,
                                             c0bar.data_ptr(), ws_adj.data_ptr(), ws_adj_bytes, st_b)
                     L.sph_permute_adjoint(prec, n, perm.data_ptr(), bar.state_struct(), tmp.state_struct(), st_b)
@@ -172,6 +173,106 @@ class KineticEnergyRollout:
         v0 = self.ckpts[0].v.double()
         vbar = bar.v.double() + bar.E.double()[None, :] * v0
         return vbar.T.cpu().numpy(), float(c0bar.cpu()[0])
+
+
+class TwoSetKineticEnergyRollout:
+    """The kinetic energy after `nsteps` fixed-dt steps of two particle sets
+    stepping as two GPUs' shares (decomp.TwoSets without balancing: steps
+    a-g of Section II for both sets, the local-remote passes reading the
+    other set), and its hand adjoint, including the reverse of both
+    local-remote passes (step f).  The gradient is that of the same function
+    as for one set holding every particle: the split only reorders sums.
+
+    Reverse of one step, per set X with the other set Y (rates_X sums X's
+    local-local and local-remote terms):
+      MOTION reverse of X -> cotangent of rates_X;
+      local-local pair reverse of X (both cotangents rates_X);
+      local-remote pair reverse: targets X with its boundary list, sources Y,
+        weights rates_X-bar (X's pass) + sigma rates_Y-bar (Y's mirrored pass);
+      EOS reverse of X (and d/dc0); permutation of X.
+    """
+
+    def __init__(self, wl, owner, prec: int, nsteps: int, ckpt: int, dt: float, device="cuda"):
+        self.wl, self.owner = wl, np.asarray(owner, dtype=bool)
+        self.prec, self.nsteps, self.ckpt, self.dt, self.device = prec, nsteps, max(1, ckpt), dt, device
+        self.e0 = wl.E - 0.5 * np.einsum("ij,ij->i", wl.v, wl.v)
+
+    def forward(self, v0: np.ndarray, c0: float) -> float:
+        from .decomp import TwoSets
+        w = copy.copy(self.wl)
+        w.v = np.ascontiguousarray(v0, dtype=np.float64)
+        w.E = self.e0 + 0.5 * np.einsum("ij,ij->i", w.v, w.v)
+        w.params = dict(self.wl.params, c0=float(c0))
+        ts = TwoSets(w, self.owner, self.prec, self.device, fixed_dt=self.dt, period=0)
+        self.ts = ts
+        self.ckpts = []
+        for k in range(self.nsteps):
+            if k % self.ckpt == 0:
+                self.ckpts.append([s.A.clone() for s in ts.sides])
+            ts.step()
+        torch.cuda.synchronize()
+        return float(sum(s.diagnostics()[6] for s in ts.sides))
+
+    def backward(self, gJ: float):
+        ts = self.ts
+        prec, dev = self.prec, self.device
+        real = real_dtype(prec)
+        sides = ts.sides
+        bars = [Cotangent(s.n, prec, dev) for s in sides]
+        tmps = [Cotangent(s.n, prec, dev) for s in sides]
+        for s, b in zip(sides, bars):
+            v = s.A.v.double()
+            b.v.copy_((gJ * s.A.m.double() * v).to(real))
+            b.m.copy_((gJ * 0.5 * (v * v).sum(0)).to(real))
+        c0bar = torch.zeros(1, dtype=torch.float64, device=dev)
+        rbars = [Rates(s.n, prec, False, dev) for s in sides]
+        nmax = max(s.n for s in sides)
+        ws_bytes = L.sph_workspace_size(ts.grid, nmax, prec, L.SPH_SOLID_J2)
+        ws = torch.zeros(ws_bytes, dtype=torch.uint8, device=dev)
+        fixed = sides[0].fixed.data_ptr()
+        st = stream_handle()
+        for seg in reversed(range(len(self.ckpts))):
+            k0 = seg * self.ckpt
+            k1 = min(k0 + self.ckpt, self.nsteps)
+            for s, c in zip(sides, self.ckpts[seg]):
+                s.A.copy_from(c)
+            saved = []
+            for _ in range(k0, k1):
+                ts.rates_pass()
+                saved.append([(s.A.clone(), s.perm.clone(), s.start.clone(), s.rates.clone()) for s in sides]
+                             + [(ts.bidx[0].clone(), ts.bidx[1].clone(), ts.nb.clone())])
+                ts.update(fixed)
+            for rec in reversed(saved):
+                (b0, b1, nb) = rec[2]
+                blist = (b0, b1)
+                for q in range(2):
+                    srt, perm, start, rates = rec[q]
+                    L.sph_integrate_adjoint(ts.params, L.SPH_STAGE_MOTION, srt.struct(), rates.struct(), fixed,
+                                            bars[q].struct(), rbars[q].struct(), None, None, 0, st)
+                for q in range(2):
+                    srt, perm, start, rates = rec[q]
+                    oth, _, ostart, _ = rec[1 - q]
+                    ps, rb = srt.struct(), rbars[q].struct()
+                    L.sph_interact_adjoint(ts.params, ts.grid, ps, None, None, ps, cells_struct(start, ts.nc), rb, rb,
+                                           bars[q].struct(), ws.data_ptr(), ws_bytes, st)
+                    L.sph_interact_adjoint(ts.params, ts.grid, ps, blist[q].data_ptr(), nb[q:q + 1].data_ptr(),
+                                           oth.struct(), cells_struct(ostart, ts.nc), rb, rbars[1 - q].struct(),
+                                           bars[q].struct(), ws.data_ptr(), ws_bytes, st)
+                for q in range(2):
+                    srt, perm, start, rates = rec[q]
+                    L.sph_integrate_adjoint(ts.params, L.SPH_STAGE_EOS, srt.struct(), None, None, bars[q].struct(),
+                                            None, c0bar.data_ptr(), ws.data_ptr(), ws_bytes, st)
+                    L.sph_permute_adjoint(prec, sides[q].n, perm.data_ptr(), bars[q].state_struct(),
+                                          tmps[q].state_struct(), st)
+                    bars[q], tmps[q] = tmps[q], bars[q]
+        torch.cuda.synchronize()
+        # back to the caller's order: set A holds the particles with owner False
+        vbar = np.empty((self.wl.n, 3))
+        for q, mask in enumerate((~self.owner, self.owner)):
+            v0 = self.ckpts[0][q].v.double()
+            vb = bars[q].v.double() + bars[q].E.double()[None, :] * v0
+            vbar[mask] = vb.T.cpu().numpy()
+        return vbar, float(c0bar.cpu()[0])
 
 
 class KineticEnergy(torch.autograd.Function):

@@ -354,29 +354,45 @@ int sph_integrate(const sph_params *params, int stage, sph_particles *p, const s
                       "sph_integrate");
 }
 
-int sph_interact_adjoint(const sph_params *params, const sph_grid *grid, const sph_particles *p, sph_cells cells,
-                         const sph_rates *rates_bar, const sph_adjoint *bar, void *ws, size_t ws_bytes, void *stream)
+int sph_interact_adjoint(const sph_params *params, const sph_grid *grid, const sph_particles *targets,
+                         const uint32_t *target_idx, const uint32_t *n_targets_dev, const sph_particles *sources,
+                         sph_cells source_cells, const sph_rates *rates_bar_targets,
+                         const sph_rates *rates_bar_sources, const sph_adjoint *bar, void *ws, size_t ws_bytes,
+                         void *stream)
 {
     Grid g;
     Params P;
     if (!make_grid(grid, g) || !make_params(params, grid, P)) return SPH_ERR_ARG;
     if (params->material != SPH_FLUID_TAIT) return fail(SPH_ERR_UNSUPPORTED, "adjoint is provided for fluids");
-    if (!p || p->prec != params->prec) return fail(SPH_ERR_ARG, "particles missing or precision mismatch");
-    if (!check_particles(p, "particles", true, false)) return SPH_ERR_ARG;
-    if (!cells.start || cells.ncells != g.ncells) return fail(SPH_ERR_ARG, "bucket table missing or not on grid");
-    if (!rates_bar || !bar) return fail(SPH_ERR_ARG, "rates_bar/bar is NULL");
-    for (int k = 0; k < 6; ++k)
-        if (!rates_bar->hi[k]) return fail(SPH_ERR_ARG, "rates_bar.hi[%d] is NULL", k);
+    if (!targets || !sources) return fail(SPH_ERR_ARG, "targets/sources is NULL");
+    if (targets->prec != params->prec || sources->prec != params->prec)
+        return fail(SPH_ERR_ARG, "particle precision does not match params.prec");
+    if (!check_particles(targets, "targets", true, false) || !check_particles(sources, "sources", true, false))
+        return SPH_ERR_ARG;
+    if (target_idx && !n_targets_dev) return fail(SPH_ERR_ARG, "target_idx given without n_targets_dev");
+    if (!source_cells.start || source_cells.ncells != g.ncells)
+        return fail(SPH_ERR_ARG, "source bucket table missing or not on this grid");
+    if (!rates_bar_targets && !rates_bar_sources) return fail(SPH_ERR_ARG, "no rate cotangents given");
+    const sph_rates *rb[2] = {rates_bar_targets, rates_bar_sources};
+    for (int q = 0; q < 2; ++q)
+        if (rb[q])
+            for (int k = 0; k < 6; ++k)
+                if (!rb[q]->hi[k]) return fail(SPH_ERR_ARG, "rates_bar_%s.hi[%d] is NULL", q ? "sources" : "targets", k);
+    if (!bar) return fail(SPH_ERR_ARG, "bar is NULL");
     for (int d = 0; d < 3; ++d)
         if (!bar->x[d] || !bar->v[d]) return fail(SPH_ERR_ARG, "bar.x / bar.v is NULL");
     if (!bar->omega || !bar->rho || !bar->p || !bar->c || !bar->e)
         return fail(SPH_ERR_ARG, "bar.omega/rho/p/c/e is NULL");
-    if (p->n == 0) return SPH_OK;
+    if (targets->n == 0) return SPH_OK;
     const uint32_t src_max = 1u << 27;   // as in sph_interact
-    if (p->n >= src_max) return fail(SPH_ERR_ARG, "n = %u must be below %u", p->n, src_max);
+    if (sources->n >= src_max) return fail(SPH_ERR_ARG, "sources.n = %u must be below %u", sources->n, src_max);
     Workspace w;
-    if (!check_ws(ws, ws_bytes, p->n, w, stage_bytes(params->prec, SPH_SOLID_J2))) return SPH_ERR_WORKSPACE;
-    return hip_status(launch_interact_adjoint(P, g, params->prec, *p, cells.start, *rates_bar, *bar, w,
+    if (!check_ws(ws, ws_bytes, sources->n, w, stage_bytes(params->prec, SPH_SOLID_J2))) return SPH_ERR_WORKSPACE;
+    bool self = targets->hash == sources->hash;
+    const sph_rates none{};
+    return hip_status(launch_interact_adjoint(P, g, params->prec, *targets, target_idx, n_targets_dev, *sources,
+                                              source_cells.start, self, rates_bar_targets ? *rates_bar_targets : none,
+                                              rates_bar_sources ? *rates_bar_sources : none, *bar, w,
                                               (hipStream_t)stream),
                       "sph_interact_adjoint");
 }

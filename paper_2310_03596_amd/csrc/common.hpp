@@ -30,8 +30,9 @@ constexpr int kSortItems = SPH_SORT_ITEMS;   // keys per thread in a radix-sort 
 constexpr int kSortTile = kBlock * kSortItems;
 constexpr int kMaxRadixBits = 10;     // digits of 8 to 10 bits: keys up to 20 bits sort in two passes
 constexpr int kMaxRadixBins = 1 << kMaxRadixBits;
-constexpr int kDiag = 7;             // integrate diagnostics
+constexpr int kDiag = 8;             // integrate diagnostics (next dt, totals, non-finite count)
 constexpr int kDiagPartial = 8;      // per-block partial record (doubles)
+static_assert(kDiag <= kDiagPartial, "a partial record holds the diagnostics");
 constexpr int kMaxTypes = SPH_MAX_TYPES;   // particle types balanced separately
 
 // Device view of the grid: origin, bucket side and its float copy.
@@ -292,9 +293,11 @@ hipError_t launch_count_pairs(const Params &P, const Grid &g, int prec, const sp
 hipError_t launch_integrate(const Params &P, int prec, int stage, const sph_particles &p,
                             const sph_rates &r, const double *dt, double *diag, const Workspace &ws,
                             hipStream_t s);
-hipError_t launch_interact_adjoint(const Params &P, const Grid &g, int prec, const sph_particles &p,
-                                   const uint32_t *start, const sph_rates &rbar, const sph_adjoint &bar,
-                                   const Workspace &ws, hipStream_t s);
+hipError_t launch_interact_adjoint(const Params &P, const Grid &g, int prec, const sph_particles &tg,
+                                   const uint32_t *tidx, const uint32_t *nt, const sph_particles &sr,
+                                   const uint32_t *sstart, bool self, const sph_rates &rbar_t,
+                                   const sph_rates &rbar_s, const sph_adjoint &bar, const Workspace &ws,
+                                   hipStream_t s);
 hipError_t launch_integrate_adjoint(const Params &P, int prec, int stage, const sph_particles &p,
                                     const sph_rates &r, const double *dt, const sph_adjoint &bar,
                                     const sph_rates &rbar, double *pbar, const Workspace &ws,

@@ -54,7 +54,7 @@ __device__ inline void eos(const Params &P, double rho, double e, double &p, dou
     }
 }
 
-// Fixed-order workgroup reduction of 7 values: slot 0 by max, the rest by sum.
+// Fixed-order workgroup reduction of the record: slot 0 by max, the rest by sum.
 __device__ inline void block_reduce_record(double r[kDiag], double *out)
 {
     __shared__ double sh[kDiag][kBlock / kWave];
@@ -77,13 +77,17 @@ __device__ inline void block_reduce_record(double r[kDiag], double *out)
             for (int w = 1; w < kBlock / kWave; ++w) v = (k == 0) ? fmax(v, sh[k][w]) : v + sh[k][w];
             out[k] = v;
         }
-        out[kDiag] = 0.0;
+        for (int k = kDiag; k < kDiagPartial; ++k) out[k] = 0.0;
     }
 }
 
+// EOS of the stored state, then the particle's share of the diagnostics:
+// c + |v| for the next dt, mass, momentum, energy, kinetic energy, and 1 in
+// slot 7 when any stored field (or `bad`, the caller's own check) is not
+// finite, so a blow-up is seen on the device without reading the state back.
 template <typename real>
 __device__ inline void finish(const Params &P, const PV<real> &s, uint32_t i, double m, double w, const double v[3],
-                              double E, double rec[kDiag])
+                              double E, double rec[kDiag], bool bad = false)
 {
     double rho = m / w;
     double v2 = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
@@ -101,6 +105,9 @@ __device__ inline void finish(const Params &P, const PV<real> &s, uint32_t i, do
     rec[4] += m * v[2];
     rec[5] += m * E;
     rec[6] += 0.5 * m * v2;
+    const bool ok = isfinite(m) && isfinite(w) && isfinite(v2) && isfinite(E) && isfinite((double)(real)rho) &&
+                    isfinite((double)(real)p) && isfinite((double)(real)c);
+    rec[7] += (ok && !bad) ? 0.0 : 1.0;
 }
 
 // The update and EOS kernels run on at most kDiagBlocks workgroups, each
@@ -113,7 +120,7 @@ template <typename real, bool SPLIT>
 __global__ __launch_bounds__(kBlock) void k_motion(Params P, PV<real> s, RV<real> R, const double *__restrict__ dtp,
                                                    double *__restrict__ partials)
 {
-    double rec[kDiag] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    double rec[kDiag] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     const uint32_t stride = gridDim.x * kBlock;
     for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < s.n; i += stride) {
         const double dt = *dtp;
@@ -134,9 +141,11 @@ __global__ __launch_bounds__(kBlock) void k_motion(Params P, PV<real> s, RV<real
         for (int a = 0; a < 3; ++a) vn[a] = (m * v[a] + dt * (r[1 + a] + m * P.g[a])) / mn;
         double En = (m * E0 + dt * (r[4] + m * gv)) / mn;
         double wn = w0 + dt * r[5];
+        bool bad = false;
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
             double xn = x0[a] + dt * vn[a];
+            bad = bad || !isfinite(xn);
             if ((P.wall_mask >> (2 * a)) & 1u)
                 if (xn < P.wlo[a]) {
                     xn = 2.0 * P.wlo[a] - xn;
@@ -156,7 +165,7 @@ __global__ __launch_bounds__(kBlock) void k_motion(Params P, PV<real> s, RV<real
         s.E[i] = En;
         // the stored (possibly rounded) state defines the EOS and the totals
         double vs[3] = {(double)(real)vn[0], (double)(real)vn[1], (double)(real)vn[2]};
-        finish<real>(P, s, i, (double)mr, (double)wr, vs, En, rec);
+        finish<real>(P, s, i, (double)mr, (double)wr, vs, En, rec, bad);
     }
     block_reduce_record(rec, partials + (size_t)blockIdx.x * kDiagPartial);
 }
@@ -164,11 +173,12 @@ __global__ __launch_bounds__(kBlock) void k_motion(Params P, PV<real> s, RV<real
 template <typename real>
 __global__ __launch_bounds__(kBlock) void k_eos(Params P, PV<real> s, double *__restrict__ partials)
 {
-    double rec[kDiag] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    double rec[kDiag] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     const uint32_t stride = gridDim.x * kBlock;
     for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < s.n; i += stride) {
         double v[3] = {(double)s.v[0][i], (double)s.v[1][i], (double)s.v[2][i]};
-        finish<real>(P, s, i, (double)s.m[i], (double)s.w[i], v, s.E[i], rec);
+        const bool bad = !(isfinite(s.x[0][i]) && isfinite(s.x[1][i]) && isfinite(s.x[2][i]));
+        finish<real>(P, s, i, (double)s.m[i], (double)s.w[i], v, s.E[i], rec, bad);
     }
     block_reduce_record(rec, partials + (size_t)blockIdx.x * kDiagPartial);
 }

@@ -386,7 +386,7 @@ void k_pairs(Params P, Grid g, PV<real> tg, const uint32_t *__restrict__ tidx, c
     }
     if constexpr (ADJ) {
 #pragma unroll
-        for (int k = 0; k < 6; ++k) rbi[k] = R.hi[k][i];
+        for (int k = 0; k < 6; ++k) rbi[k] = R.hi[0] ? R.hi[k][i] : real(0);
     }
 
     Acc acc[NOUT];
@@ -706,21 +706,22 @@ void k_pairs(Params P, Grid g, PV<real> tg, const uint32_t *__restrict__ tidx, c
     }
 }
 
-// Adjoint pass: the sources' rate cotangents in the two spare records.
+// Adjoint pass: the sources' rate cotangents in the two spare records
+// (zeros when the sources' rates have no cotangent: rb.hi[0] == NULL).
 template <typename real>
 __global__ __launch_bounds__(kBlock) void k_stage_rbar(uint32_t n, RV<real> rb, Stage<real> st)
 {
     uint32_t j = blockIdx.x * kBlock + threadIdx.x;
     if (j >= n) return;
-    typename Vec4<real>::type a, b;
-    a.x = rb.hi[0][j];
-    a.y = rb.hi[1][j];
-    a.z = rb.hi[2][j];
-    a.w = rb.hi[3][j];
-    b.x = rb.hi[4][j];
-    b.y = rb.hi[5][j];
-    b.z = 0;
-    b.w = 0;
+    typename Vec4<real>::type a = {0, 0, 0, 0}, b = {0, 0, 0, 0};
+    if (rb.hi[0]) {
+        a.x = rb.hi[0][j];
+        a.y = rb.hi[1][j];
+        a.z = rb.hi[2][j];
+        a.w = rb.hi[3][j];
+        b.x = rb.hi[4][j];
+        b.y = rb.hi[5][j];
+    }
     st.s0[rec_stride<real> * j] = a;
     st.s1[rec_stride<real> * j] = b;
 }
@@ -808,7 +809,7 @@ template <typename real, int PASS, bool SOLID>
 hipError_t go(const Params &P, const Grid &g, const sph_particles &tg, const uint32_t *tidx,
               const uint32_t *nt, const sph_particles &sr, const uint32_t *sstart, bool self, int zero_first,
               const sph_rates &r, const sph_adjoint &bar, const Workspace &ws, hipStream_t s,
-              const Census cz = Census{}, bool census_of_gradient = false)
+              const Census cz = Census{}, bool census_of_gradient = false, const sph_rates *rsrc = nullptr)
 {
     if (tg.n == 0) return hipSuccess;
     constexpr bool ADJ = PASS == kPassAdjoint;
@@ -834,7 +835,10 @@ hipError_t go(const Params &P, const Grid &g, const sph_particles &tg, const uin
         // one more workgroup (the first) builds the wavefront plan
         k_stage<real, SOLID><<<div_up(sr.n, kBlock) + (plan ? 1 : 0), kBlock, 0, s>>>(g, view<real>(sr), st, sstart,
                                                                                     plan, nplan);
-        if constexpr (ADJ) k_stage_rbar<real><<<div_up(sr.n, kBlock), kBlock, 0, s>>>(sr.n, view<real>(r), st);
+        if constexpr (ADJ) {
+            const sph_rates none{};
+            k_stage_rbar<real><<<div_up(sr.n, kBlock), kBlock, 0, s>>>(sr.n, view<real>(rsrc ? *rsrc : none), st);
+        }
     }
     if (self)
         k_pairs<real, PASS, SOLID, true><<<blocks, kPairBlock, 0, s>>>(P, g, view<real>(tg), tidx, nt, st, sstart,
@@ -905,13 +909,17 @@ hipError_t launch_census(const Params &P, const Grid &g, int prec, int pass, con
     return go<float, kPassCensus, false>(P, g, tg, tidx, nt, sr, sstart, self, 1, none, nobar, ws, s, cz, grad);
 }
 
-hipError_t launch_interact_adjoint(const Params &P, const Grid &g, int prec, const sph_particles &p,
-                                   const uint32_t *start, const sph_rates &rbar, const sph_adjoint &bar,
-                                   const Workspace &ws, hipStream_t s)
+hipError_t launch_interact_adjoint(const Params &P, const Grid &g, int prec, const sph_particles &tg,
+                                   const uint32_t *tidx, const uint32_t *nt, const sph_particles &sr,
+                                   const uint32_t *sstart, bool self, const sph_rates &rbar_t,
+                                   const sph_rates &rbar_s, const sph_adjoint &bar, const Workspace &ws,
+                                   hipStream_t s)
 {
     if (prec == SPH_FP64)
-        return go<double, kPassAdjoint, false>(P, g, p, nullptr, nullptr, p, start, true, 0, rbar, bar, ws, s);
-    return go<float, kPassAdjoint, false>(P, g, p, nullptr, nullptr, p, start, true, 0, rbar, bar, ws, s);
+        return go<double, kPassAdjoint, false>(P, g, tg, tidx, nt, sr, sstart, self, 0, rbar_t, bar, ws, s, Census{},
+                                               false, &rbar_s);
+    return go<float, kPassAdjoint, false>(P, g, tg, tidx, nt, sr, sstart, self, 0, rbar_t, bar, ws, s, Census{},
+                                          false, &rbar_s);
 }
 
 hipError_t launch_interact(const Params &P, const Grid &g, int prec, int pass, const sph_particles &tg,

@@ -67,27 +67,42 @@ class TwoSets:
         return self.dt.data_ptr()
 
     def step(self):
-        st = stream_handle()
         dtp = self._dt_ptr()
+        self.rates_pass()
+        self.update(dtp)
+        self.steps_done += 1
+        if self.period and self.steps_done % self.period == 0:
+            self.balance()
+
+    def rates_pass(self):
+        """Steps a-f for both sets: sort and table, marking, local-local and
+        local-remote FORCE passes (the sorted states and rates stay in the
+        sets until update)."""
+        st = stream_handle()
         for s in self.sides:
             s.build()
         ws, wsb = self.ws.data_ptr(), self.ws_bytes
-        for q, (X, Y) in enumerate(((self.sides[0], self.sides[1]), (self.sides[1], self.sides[0]))):
+        for q, (X, Y) in enumerate(self.pairs()):
             L.sph_mark_boundary(self.grid, X.A.struct(), Y.cells, self.comm[q].data_ptr(), self.bidx[q].data_ptr(),
                                 X.n, self.nb[q:q + 1].data_ptr(), ws, wsb, st)
-        for q, (X, Y) in enumerate(((self.sides[0], self.sides[1]), (self.sides[1], self.sides[0]))):
+        for q, (X, Y) in enumerate(self.pairs()):
             a, r = X.A.struct(), X.rates.struct()
             L.sph_interact(self.params, self.grid, L.SPH_PASS_FORCE, a, None, None, a, X.cells, 1, r, ws, wsb, st)
             L.sph_interact(self.params, self.grid, L.SPH_PASS_FORCE, a, self.bidx[q].data_ptr(),
                            self.nb[q:q + 1].data_ptr(), Y.A.struct(), Y.cells, 0, r, ws, wsb, st)
+
+    def update(self, dtp):
+        """Step g for both sets with the time step at dtp (device)."""
+        st = stream_handle()
         for X in self.sides:
             nxt = 1 - X.cur
             L.sph_integrate(self.params, L.SPH_STAGE_MOTION, X.A.struct(), X.rates.struct(), dtp,
-                            X.diag[nxt].data_ptr(), ws, wsb, st)
+                            X.diag[nxt].data_ptr(), self.ws.data_ptr(), self.ws_bytes, st)
             X.cur = nxt
-        self.steps_done += 1
-        if self.period and self.steps_done % self.period == 0:
-            self.balance()
+
+    def pairs(self):
+        """(own set, other set) for both sets."""
+        return ((self.sides[0], self.sides[1]), (self.sides[1], self.sides[0]))
 
     def balance(self):
         """One round of the swapping heuristic between the two sets (in place)."""

@@ -121,7 +121,30 @@ class Sim:
         return cnt.cpu().numpy().view(np.uint32), chk.cpu().numpy().view(np.uint64)
 
     def diagnostics(self) -> np.ndarray:
-        return self.diag[self.cur, :7].cpu().numpy()
+        """[next dt, M, Px, Py, Pz, sum m E, kinetic energy, non-finite count]."""
+        return self.diag[self.cur, :8].cpu().numpy()
+
+    def save(self, path: str):
+        """Checkpoint: the particle state in its current array order (one
+        device-to-host copy of the state's single allocation), the
+        diagnostics record that holds the next dt, and the step count."""
+        torch.cuda.synchronize()
+        np.savez(path, state=self.A._buf.cpu().numpy(), diag=self.diag[self.cur].cpu().numpy(),
+                 steps=np.array([self.steps_done], dtype=np.int64),
+                 shape=np.array([self.n, self.prec, int(self.solid)], dtype=np.int64))
+
+    def load(self, path: str):
+        """Resume from a checkpoint of a Sim of the same workload and form:
+        the next steps are those the saved run would have taken, bit for bit."""
+        with np.load(path, allow_pickle=False) as z:
+            shape = z["shape"].tolist()
+            if shape != [self.n, self.prec, int(self.solid)]:
+                raise ValueError(f"checkpoint of (n, prec, solid) = {shape}, this run has "
+                                 f"{[self.n, self.prec, int(self.solid)]}")
+            self.A._buf.copy_(torch.from_numpy(z["state"]))
+            self.diag[self.cur].copy_(torch.from_numpy(z["diag"]))
+            self.steps_done = int(z["steps"][0])
+        torch.cuda.synchronize()
 
     def state_by_id(self) -> dict:
         h = self.A.host()

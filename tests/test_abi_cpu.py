@@ -208,8 +208,31 @@ def test_integrate_and_adjoint_reject_bad_arguments():
     # adjoint of a solid
     ps = _params()
     ps.material, ps.K, ps.G = L.SPH_SOLID_J2, 1e9, 1e9
-    assert lib.sph_interact_adjoint(C.byref(ps), C.byref(_grid()), C.byref(p), L.SphCells(FAKE, 64, 0),
-                                    C.byref(r), C.byref(bar), FAKE, 1 << 30, None) == L.SPH_ERR_UNSUPPORTED
+    cl = L.SphCells(FAKE, 64, 0)
+
+    def iadj(params, t, s, rt, rs, b, tidx=None, nt=None):
+        return lib.sph_interact_adjoint(C.byref(params), C.byref(_grid()), C.byref(t), tidx, nt, C.byref(s), cl,
+                                        None if rt is None else C.byref(rt), None if rs is None else C.byref(rs),
+                                        C.byref(b), FAKE, 1 << 40, None)
+
+    assert iadj(ps, p, p, r, r, bar) == L.SPH_ERR_UNSUPPORTED
+    full = L.SphAdjoint()
+    for d in range(3):
+        full.x[d] = full.v[d] = FAKE
+    for f in ("m", "omega", "E", "rho", "p", "c", "e"):
+        setattr(full, f, FAKE)
+    # neither rate cotangent given
+    assert iadj(_params(), p, p, None, None, full) == L.SPH_ERR_ARG
+    assert "no rate cotangents" in _last()
+    # a target list needs its device count; the state cotangent needs its fields
+    assert iadj(_params(), p, p, r, None, full, tidx=FAKE) == L.SPH_ERR_ARG
+    assert iadj(_params(), p, p, None, r, bar) == L.SPH_ERR_ARG
+    half = L.SphRates()
+    half.hi[0] = FAKE
+    assert iadj(_params(), p, p, r, half, full) == L.SPH_ERR_ARG
+    assert "rates_bar_sources.hi[1]" in _last()
+    assert iadj(_params(), p, _particles(1 << 27), None, r, full) == L.SPH_ERR_ARG
+    assert "must be below 134217728" in _last()
 
 
 def test_zero_particles_is_a_noop():

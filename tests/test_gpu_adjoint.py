@@ -161,3 +161,96 @@ def test_displacement_adjoint_matches_central_differences_full_box():
     fdc = (J(w.v, c0 + h) - J(w.v, c0 - h)) / (2 * h)
     print(f"c0: FD {fdc:.12e} adjoint {gc:.12e}", flush=True)
     assert abs(fdc - gc) <= 1e-6 * abs(fdc)
+
+
+def test_fp32_adjoint_full_box_error():
+    """The adjoint configuration as prescribed (250,047 particles, 50 FP32
+    steps, checkpoints every 10): the FP32-split gradient against the FP64
+    adjoint (max-norm and RMS, relative) and, along 8 random directions,
+    against central differences of the FP64 forward."""
+    w = S.c5_box()
+    dt, nsteps, ckpt = w.extra["dt"], w.extra["steps"], w.extra["ckpt"]
+    c0 = w.params["c0"]
+    print(f"[FP32 adjoint full box] n={w.n} steps={nsteps} ckpt={ckpt}", flush=True)
+    out = {}
+    for prec in (FP64, FP32):
+        ro = _rollout(w, prec, nsteps, ckpt, dt)
+        ro.forward(w.v, c0)
+        out[prec] = ro.backward(1.0)
+        del ro
+    g64, c64 = out[FP64]
+    g32, c32 = out[FP32]
+    rel_max = np.abs(g32 - g64).max() / np.abs(g64).max()
+    rel_rms = np.sqrt(np.mean((g32 - g64) ** 2) / np.mean(g64 ** 2))
+    rel_c0 = abs(c32 - c64) / abs(c64)
+    rng = np.random.default_rng(7)
+    eps = 1e-4
+    worst = 0.0
+    for _ in range(8):
+        d = rng.normal(size=w.v.shape)
+        fd = (_rollout(w, FP64, nsteps, nsteps, dt).forward(w.v + eps * d, c0)
+              - _rollout(w, FP64, nsteps, nsteps, dt).forward(w.v - eps * d, c0)) / (2 * eps)
+        worst = max(worst, abs(fd - float((g32 * d).sum())) / abs(fd))
+    print(f"FP32 adjoint vs FP64 adjoint: max-norm {rel_max:.3e}, RMS {rel_rms:.3e}, c0 {rel_c0:.3e}; "
+          f"vs central differences along 8 directions: worst {worst:.3e}", flush=True)
+    assert rel_max < 5e-2 and rel_rms < 1e-2 and rel_c0 < 1e-2 and worst < 1e-2
+
+
+@pytest.mark.parametrize("layout", ["random", "slab"])
+def test_two_set_adjoint_matches_reverse_mode_on_the_union(layout):
+    """Two sets stepping as two GPUs' shares (local-local and local-remote
+    passes, steps e and f), FP64: the hand adjoint of the two-set rollout,
+    including the reverse of both local-remote passes, equals the reverse-mode
+    gradient of one dense rollout over the union of the sets."""
+    from paper_2310_03596_amd.adjoint import TwoSetKineticEnergyRollout
+    w = small_box(n_side=7, seed=84)
+    owner = (np.random.default_rng(85).random(w.n) < 0.5) if layout == "random" else w.x[:, 0] > np.median(w.x[:, 0])
+    dt, nsteps = 1.4e-5, 4
+    print(f"[two-set adjoint] n={w.n} layout={layout} set B={int(owner.sum())}", flush=True)
+    J_ref, gv_ref, gc_ref = torch_ref.gradient(w, w.params["c0"], dt, nsteps)
+    ro = TwoSetKineticEnergyRollout(w, owner, FP64, nsteps, 2, dt)
+    J = ro.forward(w.v, w.params["c0"])
+    nb = ro.ts.nb.cpu().numpy()
+    assert nb.min() > 0            # both local-remote passes had targets
+    gv, gc = ro.backward(1.0)
+    assert J == pytest.approx(J_ref, rel=1e-13)
+    assert np.abs(gv - gv_ref).max() <= 1e-9 * np.abs(gv_ref).max()
+    assert gc == pytest.approx(gc_ref, rel=1e-9)
+
+
+def test_interact_adjoint_splits_into_its_two_cotangents():
+    """The local-remote reverse with both cotangents equals the sum of the
+    call with the targets' cotangent alone and the call with the sources'
+    alone (the form a GPU uses when the remote rates are not differentiated,
+    and the one that gives the received particles' cotangent)."""
+    from paper_2310_03596_amd import _lib as L
+    from paper_2310_03596_amd.adjoint import Cotangent
+    from paper_2310_03596_amd.sim import SharePass
+    from paper_2310_03596_amd.state import Rates, cells_struct, stream_handle
+    loc, rem = S.c4_share("mixed", seed=86, nx=24, ny=12, nz=12, split_ix=18)
+    sp = SharePass(loc, rem, FP64)
+    sp.build()
+    sp.mark()
+    rng = np.random.default_rng(87)
+    rl, rr = Rates(sp.nl, FP64, False, "cuda"), Rates(sp.nr, FP64, False, "cuda")
+    rl.hi.copy_(torch.from_numpy(rng.normal(size=(6, sp.nl))))
+    rr.hi.copy_(torch.from_numpy(rng.normal(size=(6, sp.nr))))
+    ws_bytes = L.sph_workspace_size(sp.grid, max(sp.nl, sp.nr), FP64, L.SPH_SOLID_J2)
+    ws = torch.zeros(ws_bytes, dtype=torch.uint8, device="cuda")
+    st = stream_handle()
+    outs = []
+    for rt, rs in ((rl, rr), (rl, None), (None, rr)):
+        b = Cotangent(sp.nl, FP64, "cuda")
+        L.sph_interact_adjoint(sp.params, sp.grid, sp.LB.struct(), sp.bidx.data_ptr(), sp.nb.data_ptr(),
+                               sp.RB.struct(), cells_struct(sp.rstart, sp.nc), None if rt is None else rt.struct(),
+                               None if rs is None else rs.struct(), b.struct(), ws.data_ptr(), ws_bytes, st)
+        torch.cuda.synchronize()
+        outs.append(torch.cat([b.x, b.v, b.w[None], b.rho[None], b.p[None], b.c[None], b.e[None]]).cpu().numpy())
+    both, only_t, only_s = outs
+    scale = np.abs(both).max(axis=1, keepdims=True) + 1e-300
+    assert np.abs(both - (only_t + only_s)).max(axis=1, keepdims=True).max() <= (1e-12 * scale).max()
+    assert np.abs(only_t).max() > 0 and np.abs(only_s).max() > 0
+    # targets off the boundary list have no remote pairs: nothing accumulated there
+    nb = int(sp.nb.cpu()[0])
+    off = np.setdiff1d(np.arange(sp.nl), sp.bidx.cpu().numpy()[:nb])
+    assert not np.abs(both[:, off]).any()
