@@ -194,6 +194,20 @@ int sph_mark_boundary(const sph_grid *grid, const sph_particles *local, sph_cell
                       uint32_t *comm_hash_out, uint32_t *boundary_idx_out, uint32_t boundary_cap,
                       uint32_t *n_boundary_dev, void *ws, size_t ws_bytes, void *stream);
 
+/* sph_mark_boundary for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): the same step (c) and the same results, with no workspace
+ * argument.  Its temporary block counts live in a fixed array inside the
+ * library, one per GPU (1 MiB, held until the process ends), so it takes at
+ * most 2^26 = 67,108,864 local particles and calls no allocator.  Every call
+ * on one GPU shares that GPU's array: calls that overlap on one GPU (on
+ * different streams or host threads) race and must be ordered by the caller.
+ * Errors: SPH_ERR_ARG (as sph_mark_boundary, and local->n above 2^26),
+ * SPH_ERR_HIP. */
+int sph_mark_boundary_noalloc(const sph_grid *grid, const sph_particles *local, sph_cells remote_cells,
+                              uint32_t *comm_hash_out, uint32_t *boundary_idx_out, uint32_t boundary_cap,
+                              uint32_t *n_boundary_dev, void *stream);
+
 /* Packing for step (d): payload[k] = local[boundary_idx[k]] for
  * k < min(*n_boundary_dev, payload->n), every field present in payload
  * (payload->n is its capacity; its fields must be a subset of local's).

@@ -57,7 +57,7 @@ class SphAdjoint(C.Structure):
 
 
 EXPORTS = ("sph_version", "sph_last_error", "sph_workspace_size", "sph_build_cells", "sph_mark_boundary",
-           "sph_pack_boundary", "sph_interact", "sph_count_pairs", "sph_neighbor_census", "sph_integrate", "sph_interact_adjoint",
+           "sph_mark_boundary_noalloc", "sph_pack_boundary", "sph_interact", "sph_count_pairs", "sph_neighbor_census", "sph_integrate", "sph_interact_adjoint",
            "sph_integrate_adjoint", "sph_permute_adjoint", "sph_centroid", "sph_balance_hash",
            "sph_balance_select", "sph_swap", "sph_centroid_types", "sph_balance_hash_types",
            "sph_balance_select_types")
@@ -89,6 +89,7 @@ def load():
                                   C.c_size_t, _vp]
     L.sph_mark_boundary.argtypes = [P(SphGrid), P(SphParticles), SphCells, _vp, _vp, C.c_uint32, _vp, _vp,
                                     C.c_size_t, _vp]
+    L.sph_mark_boundary_noalloc.argtypes = [P(SphGrid), P(SphParticles), SphCells, _vp, _vp, C.c_uint32, _vp, _vp]
     L.sph_pack_boundary.argtypes = [P(SphParticles), _vp, _vp, P(SphParticles), _vp]
     L.sph_interact.argtypes = [P(SphParams), P(SphGrid), C.c_int, P(SphParticles), _vp, _vp,
                                P(SphParticles), SphCells, C.c_int, P(SphRates), _vp, C.c_size_t, _vp]
@@ -148,6 +149,12 @@ def sph_mark_boundary(grid, local, remote_cells, comm_ptr, bidx_ptr, cap, nb_ptr
     return check("sph_mark_boundary", load().sph_mark_boundary(C.byref(grid), C.byref(local), remote_cells,
                                                                comm_ptr, bidx_ptr, cap, nb_ptr, ws_ptr,
                                                                ws_bytes, stream))
+
+
+def sph_mark_boundary_noalloc(grid, local, remote_cells, comm_ptr, bidx_ptr, cap, nb_ptr, stream):
+    return check("sph_mark_boundary_noalloc",
+                 load().sph_mark_boundary_noalloc(C.byref(grid), C.byref(local), remote_cells, comm_ptr, bidx_ptr, cap,
+                                                  nb_ptr, stream))
 
 
 def sph_pack_boundary(local, bidx_ptr, nb_ptr, payload, stream):

@@ -215,6 +215,27 @@ int sph_mark_boundary(const sph_grid *grid, const sph_particles *local, sph_cell
                       "sph_mark_boundary");
 }
 
+int sph_mark_boundary_noalloc(const sph_grid *grid, const sph_particles *local, sph_cells remote_cells,
+                              uint32_t *comm_hash_out, uint32_t *boundary_idx_out, uint32_t boundary_cap,
+                              uint32_t *n_boundary_dev, void *stream)
+{
+    Grid g;
+    if (!make_grid(grid, g)) return SPH_ERR_ARG;
+    if (!local) return fail(SPH_ERR_ARG, "local is NULL");
+    if (local->n > kNoAllocMarkMax)
+        return fail(SPH_ERR_ARG, "local.n = %u exceeds the %u particles sph_mark_boundary_noalloc takes", local->n,
+                    kNoAllocMarkMax);
+    if (local->n > 0 && !local->hash) return fail(SPH_ERR_ARG, "local.hash is NULL");
+    if (!remote_cells.start || remote_cells.ncells != g.ncells)
+        return fail(SPH_ERR_ARG, "remote bucket table missing or not on this grid");
+    if (!n_boundary_dev) return fail(SPH_ERR_ARG, "n_boundary_dev is NULL");
+    if (local->n > 0 && !comm_hash_out) return fail(SPH_ERR_ARG, "comm_hash_out is NULL");
+    if (boundary_cap > 0 && !boundary_idx_out) return fail(SPH_ERR_ARG, "boundary_idx_out is NULL");
+    return hip_status(launch_mark_boundary_noalloc(g, *local, remote_cells.start, comm_hash_out, boundary_idx_out,
+                                                   boundary_cap, n_boundary_dev, (hipStream_t)stream),
+                      "sph_mark_boundary_noalloc");
+}
+
 int sph_pack_boundary(const sph_particles *local, const uint32_t *boundary_idx, const uint32_t *n_boundary_dev,
                       sph_particles *payload, void *stream)
 {

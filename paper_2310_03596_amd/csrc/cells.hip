@@ -2,6 +2,8 @@
 // step a of Section II), communication hash and boundary compaction (step c)
 // and the boundary payload packing for step d.  The sort itself is in
 // radix.hpp.
+#include <mutex>
+
 #include "radix.hpp"
 
 namespace sph {
@@ -252,6 +254,48 @@ hipError_t launch_mark_boundary(const Grid &g, const sph_particles &local, const
     k_scan_counts<<<1, kScanBlock, 0, s>>>(ws.counts, blocks, nb);
     k_compact<<<blocks, kBlock, 0, s>>>(n, g.ncells, comm, ws.counts, bidx, cap);
     return hipGetLastError();
+}
+
+// Block counts of the mark and compaction for callers that cannot allocate
+// (sph_mark_boundary_noalloc): one copy per GPU, held until the process
+// ends.  k_mark writes every entry the scan and the compaction read, so
+// nothing needs clearing between calls; calls that overlap on one GPU race.
+static __device__ __align__(256) uint32_t scratch[kNoAllocMarkMax / kBlock + 1];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+uint32_t *g_scratch_dev[kMaxDevices] = {};
+
+// The address of this GPU's copy of `scratch`, looked up once per device with
+// that device current (the host-side name is not a device address).
+hipError_t scratch_of_current_device(uint32_t **out)
+{
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_dev[dev] = static_cast<uint32_t *>(p);
+    }
+    *out = g_scratch_dev[dev];
+    return hipSuccess;
+}
+}  // namespace
+
+hipError_t launch_mark_boundary_noalloc(const Grid &g, const sph_particles &local, const uint32_t *rstart,
+                                        uint32_t *comm, uint32_t *bidx, uint32_t cap, uint32_t *nb, hipStream_t s)
+{
+    uint32_t *counts = nullptr;
+    hipError_t e = scratch_of_current_device(&counts);
+    if (e != hipSuccess) return e;
+    Workspace ws{};
+    ws.counts = counts;
+    return launch_mark_boundary(g, local, rstart, comm, bidx, cap, nb, ws, s);
 }
 
 hipError_t launch_pack(int prec, const sph_particles &local, const uint32_t *bidx, const uint32_t *nb,

@@ -275,6 +275,11 @@ inline Stage<real> stage_view(const Workspace &w, uint32_t n, bool solid)
 
 hipError_t launch_build_cells(const Grid &g, int prec, const sph_particles &in, const sph_particles &out,
                               uint32_t *perm, uint32_t *start, const Workspace &ws, hipStream_t s);
+// Largest local array sph_mark_boundary_noalloc takes (its block counts live
+// in a fixed device array of kNoAllocMarkMax / kBlock + 1 words, 1 MiB).
+constexpr uint32_t kNoAllocMarkMax = 1u << 26;
+hipError_t launch_mark_boundary_noalloc(const Grid &g, const sph_particles &local, const uint32_t *rstart,
+                                        uint32_t *comm, uint32_t *bidx, uint32_t cap, uint32_t *nb, hipStream_t s);
 hipError_t launch_mark_boundary(const Grid &g, const sph_particles &local, const uint32_t *rstart,
                                 uint32_t *comm, uint32_t *bidx, uint32_t cap, uint32_t *nb,
                                 const Workspace &ws, hipStream_t s);

@@ -183,6 +183,27 @@ def test_neighbor_census_rejects_bad_arguments():
     assert census(_params(), 0, _particles(0), p, None, None) == L.SPH_OK
 
 
+def test_mark_boundary_noalloc_rejects_bad_arguments():
+    lib = L.load()
+    g = _grid()
+    cells = L.SphCells(FAKE, 64, 0)
+
+    def mark(p, cl=cells, comm=FAKE, bidx=FAKE, cap=10, nb=FAKE):
+        return lib.sph_mark_boundary_noalloc(C.byref(g), C.byref(p), cl, comm, bidx, cap, nb, None)
+
+    # beyond the fixed block-count array: a clear error, before anything runs
+    assert mark(_particles((1 << 26) + 1)) == L.SPH_ERR_ARG
+    assert "exceeds the 67108864 particles" in _last()
+    p = _particles(10)
+    assert mark(p, cl=L.SphCells(FAKE, 63, 0)) == L.SPH_ERR_ARG
+    assert mark(p, nb=None) == L.SPH_ERR_ARG
+    assert mark(p, comm=None) == L.SPH_ERR_ARG
+    assert mark(p, bidx=None) == L.SPH_ERR_ARG
+    q = _particles(10)
+    q.hash = None
+    assert mark(q) == L.SPH_ERR_ARG
+
+
 def test_integrate_and_adjoint_reject_bad_arguments():
     lib = L.load()
     p = _particles(10)
