@@ -287,6 +287,8 @@ int sph_interact(const sph_params *params, const sph_grid *grid, int pass, const
     int staged_material = pass == SPH_PASS_FORCE ? params->material : SPH_FLUID_TAIT;
     if (!check_ws(ws, ws_bytes, sources->n, w, stage_bytes(params->prec, staged_material))) return SPH_ERR_WORKSPACE;
     bool self = targets->hash == sources->hash;
+    if (self && targets->n != sources->n)
+        return fail(SPH_ERR_ARG, "targets and sources share their hash array but not their size");
     return hip_status(launch_interact(P, g, params->prec, pass, *targets, target_idx, n_targets_dev, *sources,
                                       source_cells.start, self, zero_first, *rates, w, (hipStream_t)stream),
                       "sph_interact");
@@ -319,6 +321,8 @@ int sph_neighbor_census(const sph_params *params, const sph_grid *grid, int pass
     int staged_material = pass == SPH_PASS_FORCE ? params->material : SPH_FLUID_TAIT;
     if (!check_ws(ws, ws_bytes, sources->n, w, stage_bytes(params->prec, staged_material))) return SPH_ERR_WORKSPACE;
     bool self = targets->hash == sources->hash;
+    if (self && targets->n != sources->n)
+        return fail(SPH_ERR_ARG, "targets and sources share their hash array but not their size");
     return hip_status(launch_census(P, g, params->prec, pass, *targets, target_idx, n_targets_dev, *sources,
                                     source_cells.start, self, count_out, checksum_out, w, (hipStream_t)stream),
                       "sph_neighbor_census");
@@ -342,6 +346,8 @@ int sph_count_pairs(const sph_params *params, const sph_grid *grid, const sph_pa
     if (!counts_dev) return fail(SPH_ERR_ARG, "counts_dev is NULL");
     if (targets->n == 0) return SPH_OK;
     bool self = targets->hash == sources->hash;
+    if (self && targets->n != sources->n)
+        return fail(SPH_ERR_ARG, "targets and sources share their hash array but not their size");
     return hip_status(launch_count_pairs(P, g, params->prec, *targets, target_idx, n_targets_dev, *sources,
                                          source_cells.start, self, counts_dev, (hipStream_t)stream),
                       "sph_count_pairs");
@@ -410,6 +416,8 @@ int sph_interact_adjoint(const sph_params *params, const sph_grid *grid, const s
     Workspace w;
     if (!check_ws(ws, ws_bytes, sources->n, w, stage_bytes(params->prec, SPH_SOLID_J2))) return SPH_ERR_WORKSPACE;
     bool self = targets->hash == sources->hash;
+    if (self && targets->n != sources->n)
+        return fail(SPH_ERR_ARG, "targets and sources share their hash array but not their size");
     const sph_rates none{};
     return hip_status(launch_interact_adjoint(P, g, params->prec, *targets, target_idx, n_targets_dev, *sources,
                                               source_cells.start, self, rates_bar_targets ? *rates_bar_targets : none,

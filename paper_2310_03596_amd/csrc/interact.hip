@@ -63,10 +63,16 @@ constexpr int kMaxWin = 12;                // staged pages whose hits a list can
 // marks, pages, page tables) within 40 KB, four workgroups per CU; the page
 // covers the row union of a group in about 97 % (FP32) and 70 % (FP64) of
 // the cases on the column workload.
+#ifndef SPH_PAIR_PAGE_F32
+#define SPH_PAIR_PAGE_F32 160
+#endif
+#ifndef SPH_PAIR_CAP_F32
+#define SPH_PAIR_CAP_F32 88
+#endif
 template <typename real>
 struct Tune {
-    static constexpr int page = 160;
-    static constexpr int cap = 88;
+    static constexpr int page = sizeof(real) == 4 ? SPH_PAIR_PAGE_F32 : 160;
+    static constexpr int cap = sizeof(real) == 4 ? SPH_PAIR_CAP_F32 : 88;
 };
 static_assert(Tune<float>::page + kSub <= 256 && Tune<double>::page + kSub <= 256, "page index must fit a u8 entry");
 static_assert(Tune<float>::page % kSub == 0 && Tune<double>::page % kSub == 0, "reads stay below page + kSub");
@@ -151,6 +157,20 @@ __device__ inline int wave_min(int v)
 #pragma unroll
     for (int off = kWave / 2; off > 0; off >>= 1) v = min(v, __shfl_xor(v, off, kWave));
     return __builtin_amdgcn_readfirstlane(v);   // equal in every lane
+}
+
+// Largest value over the wavefront of a v in [0, 256), by eight ballots
+// (no cross-lane data movement: the page loop's bound costs no LDS round
+// trips; 1.5 % off the FP32 column FORCE pass with the page prefetch below).
+__device__ inline int wave_max_u8(int v)
+{
+    int r = 0;
+#pragma unroll
+    for (int b = 7; b >= 0; --b) {
+        const int c = r | (1 << b);
+        if (__ballot(v >= c)) r = c;
+    }
+    return r;
 }
 
 __device__ inline int wave_max(int v)
@@ -617,28 +637,55 @@ void k_pairs(Params P, Grid g, PV<real> tg, const uint32_t *__restrict__ tidx, c
                 // the page in the group's filter frame, then far sentinels up to
                 // kPage + kSub so that every read below stays in the array and
                 // nothing past the page can pass a test
-                for (uint32_t u = (uint32_t)lane; u < (uint32_t)(kPage + kSub); u += kWave) {
-                    float4 rec;
-                    if (u < len) {
-                        const v4 sp = src.pos[pb + u];
-                        if constexpr (SPLIT) {
-                            rec.x = (sp.w - gx0f) * T.Lf + sp.x;
-                            rec.y = ddy + sp.y;
-                            rec.z = ddz + sp.z;
+                if constexpr (SPLIT) {
+                    // every lane's records of the page in flight at once, then
+                    // staged (one memory round trip per page instead of three)
+                    constexpr int kIt = (kPage + kSub + kWave - 1) / kWave;
+                    v4 sp[kIt];
+#pragma unroll
+                    for (int it = 0; it < kIt; ++it) {
+                        const uint32_t u = (uint32_t)lane + (uint32_t)(it * kWave);
+                        if (u < len) sp[it] = src.pos[pb + u];
+                    }
+#pragma unroll
+                    for (int it = 0; it < kIt; ++it) {
+                        const uint32_t u = (uint32_t)lane + (uint32_t)(it * kWave);
+                        if (u >= (uint32_t)(kPage + kSub)) continue;
+                        float4 rec;
+                        if (u < len) {
+                            rec.x = (sp[it].w - gx0f) * T.Lf + sp[it].x;
+                            rec.y = ddy + sp[it].y;
+                            rec.z = ddz + sp[it].z;
+                            rec.w = rec.x * rec.x + rec.y * rec.y + rec.z * rec.z;
+                            rec.x *= 2.0f;
+                            rec.y *= 2.0f;
+                            rec.z *= 2.0f;
                         } else {
+                            rec.x = rec.y = rec.z = 0.0f;
+                            rec.w = kFar;
+                        }
+                        stage[wave][u] = rec;
+                    }
+                } else {
+                    // FP64 records (32 bytes): one in flight per lane, so that the
+                    // pass keeps its three wavefronts per SIMD
+                    for (uint32_t u = (uint32_t)lane; u < (uint32_t)(kPage + kSub); u += kWave) {
+                        float4 rec;
+                        if (u < len) {
+                            const v4 sp = src.pos[pb + u];
                             rec.x = (float)(sp.x - corner[0]);
                             rec.y = (float)(sp.y - corner[1]);
                             rec.z = (float)(sp.z - corner[2]);
+                            rec.w = rec.x * rec.x + rec.y * rec.y + rec.z * rec.z;
+                            rec.x *= 2.0f;   // staged as (2q, |q|^2)
+                            rec.y *= 2.0f;
+                            rec.z *= 2.0f;
+                        } else {
+                            rec.x = rec.y = rec.z = 0.0f;
+                            rec.w = kFar;
                         }
-                        rec.w = rec.x * rec.x + rec.y * rec.y + rec.z * rec.z;
-                        rec.x *= 2.0f;   // staged as (2q, |q|^2)
-                        rec.y *= 2.0f;
-                        rec.z *= 2.0f;
-                    } else {
-                        rec.x = rec.y = rec.z = 0.0f;
-                        rec.w = kFar;
+                        stage[wave][u] = rec;
                     }
-                    stage[wave][u] = rec;
                 }
                 wave_lds_sync();
                 // Each lane walks its own range clipped to the page.  Lanes whose
@@ -651,7 +698,7 @@ void k_pairs(Params P, Grid g, PV<real> tg, const uint32_t *__restrict__ tidx, c
                 const uint32_t hc = hi < pe ? hi : pe;
                 const uint32_t le = hc > pb ? hc - pb : 0u;
                 const int nl = le > la ? (int)(le - la) : 0;
-                const int nmax = wave_max(nl);
+                const int nmax = wave_max_u8(nl);   // nl <= kPage < 256
                 // every lane reads `span` records from a; moving a lane's start
                 // back (to records before its own range: nearer buckets of the
                 // row, also more than one bucket side away) keeps the reads
@@ -825,8 +872,10 @@ hipError_t go(const Params &P, const Grid &g, const sph_particles &tg, const uin
     // consecutive targets per wavefront.)
     const uint64_t nrows = (uint64_t)g.ny * (uint64_t)g.nz;
     const uint64_t pmax = div_up(tg.n, kWave) + nrows;
+    // (the workspace's key buffers hold 4 bytes for each of the sources->n
+    // particles it was sized for)
     if (!SOLID && PASS != SPH_PASS_GRADIENT && !census_of_gradient && self && !tidx &&
-        pmax * sizeof(uint2) <= 4ull * tg.n) {
+        pmax * sizeof(uint2) <= 4ull * sr.n) {
         plan = reinterpret_cast<uint2 *>(ws.keys[0]);
         nplan = ws.keys[1];
         blocks = div_up(pmax, kWaves);

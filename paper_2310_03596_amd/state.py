@@ -86,6 +86,7 @@ class _Flat:
     def _bind(self):
         for k, v in _carve(self._buf, self._layout).items():
             setattr(self, k, v)
+        self._struct = None   # the ABI struct of these buffers, built on first use
 
     def clone(self):
         """A copy with its own storage (one device copy)."""
@@ -116,6 +117,12 @@ class Particles(_Flat):
         self._allocate(layout, device)
 
     def struct(self) -> L.SphParticles:
+        """The ABI struct of this array (built once: the buffers never move)."""
+        if self._struct is None:
+            self._struct = self._make_struct()
+        return self._struct
+
+    def _make_struct(self) -> L.SphParticles:
         s = L.SphParticles()
         s.n = self.n
         s.prec = self.prec
@@ -179,6 +186,11 @@ class Rates(_Flat):
                         ("Llo", (9, n) if (gradient and split) else None, real)], device)
 
     def struct(self) -> L.SphRates:
+        if self._struct is None:
+            self._struct = self._make_struct()
+        return self._struct
+
+    def _make_struct(self) -> L.SphRates:
         r = L.SphRates()
         if self.hi.shape[1] == 0:
             return r

@@ -204,6 +204,32 @@ def test_mark_boundary_noalloc_rejects_bad_arguments():
     assert mark(q) == L.SPH_ERR_ARG
 
 
+def test_passes_over_one_array_need_one_size():
+    """A pass whose targets and sources share their hash array is a pass over
+    one array (the local-local pass): their sizes must agree."""
+    lib = L.load()
+    g = _grid()
+    cells = L.SphCells(FAKE, 64, 0)
+    t, s = _particles(10), _particles(12)
+    r = L.SphRates()
+    for k in range(6):
+        r.hi[k] = FAKE
+    assert lib.sph_interact(C.byref(_params()), C.byref(g), 0, C.byref(t), None, None, C.byref(s), cells, 1,
+                            C.byref(r), FAKE, 1 << 40, None) == L.SPH_ERR_ARG
+    assert "share their hash array" in _last()
+    assert lib.sph_count_pairs(C.byref(_params()), C.byref(g), C.byref(t), None, None, C.byref(s), cells, FAKE,
+                               None) == L.SPH_ERR_ARG
+    assert lib.sph_neighbor_census(C.byref(_params()), C.byref(g), 0, C.byref(t), None, None, C.byref(s), cells, FAKE,
+                                   FAKE, FAKE, 1 << 40, None) == L.SPH_ERR_ARG
+    full = L.SphAdjoint()
+    for d in range(3):
+        full.x[d] = full.v[d] = FAKE
+    for f in ("m", "omega", "E", "rho", "p", "c", "e"):
+        setattr(full, f, FAKE)
+    assert lib.sph_interact_adjoint(C.byref(_params()), C.byref(g), C.byref(t), None, None, C.byref(s), cells,
+                                    C.byref(r), C.byref(r), C.byref(full), FAKE, 1 << 40, None) == L.SPH_ERR_ARG
+
+
 def test_integrate_and_adjoint_reject_bad_arguments():
     lib = L.load()
     p = _particles(10)
