@@ -149,13 +149,16 @@ typedef struct sph_rates {
 } sph_rates;
 
 /* Adjoint (cotangent) of a particle state, same precision as the form:
- * x, v, m, omega, E are the state variables of one step; rho, p, c, e are the
- * cotangents of the derived fields that the pair terms read. */
+ * x, v, m, omega, E (and, for J2 solids, S and eps_p) are the state variables
+ * of one step; rho, p, c, e are the cotangents of the derived fields that the
+ * pair terms read.  S and eps_p are NULL for fluids. */
 typedef struct sph_adjoint {
     void *x[3];
     void *v[3];
     void *m, *omega, *E;
     void *rho, *p, *c, *e;
+    void *S[6];
+    void *eps_p;
 } sph_adjoint;
 
 /* Library version string (static storage). */
@@ -283,17 +286,21 @@ int sph_neighbor_census(const sph_params *params, const sph_grid *grid, int pass
                         sph_cells source_cells, uint32_t *count_out, uint64_t *checksum_out,
                         void *ws, size_t ws_bytes, void *stream);
 
-/* Adjoint of a FORCE pass of a fluid, steps (e) and (f).  The pass being
- * reversed is the sph_interact call with the same targets, target_idx,
- * n_targets_dev, sources and source_cells.  Each pair term satisfies
- * T(s_j, s_i) = +-T(s_i, s_j) (odd for mass, momentum and energy, even for
- * volume), so every target gathers its cotangent from its own pairs without
- * atomics: for each target i and source j within 2h it accumulates into
- * `bar` (at i) the cotangent of x, v, omega, rho, p, c and e of target i
- * from the weight  rates_bar_targets[i] + sigma * rates_bar_sources[j], where
- * rates_bar_targets (hi only; NULL = zero) is the cotangent of the targets'
- * rates summed by this pass and rates_bar_sources (hi only; NULL = zero) that
- * of the sources' rates in the mirrored pass, which sums T(s_j, s_i).
+/* Adjoint of an interaction pass, steps (e) and (f).  The pass being
+ * reversed is the sph_interact call with the same pass, targets, target_idx,
+ * n_targets_dev, sources and source_cells; every target gathers its
+ * cotangent from its own pairs, without atomics.
+ *
+ * pass = SPH_PASS_FORCE (fluids, and J2 solids with the linear EOS).  Each
+ * pair term satisfies T(s_j, s_i) = +-T(s_i, s_j) (odd for mass, momentum
+ * and energy, even for volume), so for each target i and source j within 2h
+ * it accumulates into `bar` (at i) the cotangent of x, v, omega, rho, p, c,
+ * e (and, for solids, S) of target i from the weight
+ *   rates_bar_targets[i] + sigma * rates_bar_sources[j],
+ * where rates_bar_targets (hi only; NULL = zero) is the cotangent of the
+ * targets' rates summed by this pass and rates_bar_sources (hi only; NULL =
+ * zero) that of the sources' rates in the mirrored pass, which sums
+ * T(s_j, s_i).
  *   - local-local pass (e): targets = sources, both cotangents the same;
  *   - local-remote pass (f), local side: targets = the local array with its
  *     boundary list, sources = the remote array, rates_bar_targets = the
@@ -304,35 +311,50 @@ int sph_neighbor_census(const sph_params *params, const sph_grid *grid, int pass
  *     array, rates_bar_targets = NULL, rates_bar_sources = the local rates'
  *     cotangent: the cotangent of the received particles, which their owner
  *     adds to its own.
+ * pass = SPH_PASS_GRADIENT (the velocity-gradient loop of solids).  A pair
+ * puts w_j (v_j - v_i) (x) g into L_i and w_i (v_j - v_i) (x) g into L_j
+ * (g = grad_i W), so with the cotangents Lbar of the targets' and of the
+ * sources' L (rates_bar_*->Lhi, 9 row-major entries; NULL = zero) it
+ * accumulates the cotangents of x, v and omega of every target.
+ *
  * The pair terms read p and c, not c0: d/dc0 comes from the EOS reverse
  * (sph_integrate_adjoint, SPH_STAGE_EOS).  The workspace (sph_workspace_size
  * for sources->n with SPH_SOLID_J2, which has room for the extra staged
  * records) receives packed copies of the sources and their cotangents.
  * Errors: SPH_ERR_ARG (also sources->n at or above 2^27, both cotangents
- * NULL), SPH_ERR_WORKSPACE, SPH_ERR_UNSUPPORTED (solids). */
-int sph_interact_adjoint(const sph_params *params, const sph_grid *grid, const sph_particles *targets,
-                         const uint32_t *target_idx, const uint32_t *n_targets_dev,
-                         const sph_particles *sources, sph_cells source_cells,
-                         const sph_rates *rates_bar_targets, const sph_rates *rates_bar_sources,
-                         const sph_adjoint *bar, void *ws, size_t ws_bytes, void *stream);
+ * NULL, a solid FORCE pass without S in the particles or in bar),
+ * SPH_ERR_WORKSPACE, SPH_ERR_UNSUPPORTED (the Mie-Gruneisen EOS). */
+int sph_interact_adjoint(const sph_params *params, const sph_grid *grid, int pass,
+                         const sph_particles *targets, const uint32_t *target_idx,
+                         const uint32_t *n_targets_dev, const sph_particles *sources,
+                         sph_cells source_cells, const sph_rates *rates_bar_targets,
+                         const sph_rates *rates_bar_sources, const sph_adjoint *bar, void *ws,
+                         size_t ws_bytes, void *stream);
 
-/* Adjoint of step (g) for a fluid.  stage = SPH_STAGE_MOTION: p is the state
- * BEFORE the update (hash-sorted), rates its FORCE rates; on entry bar holds
- * the cotangent of the state after the update (x, v, m, omega, E); on return
- * bar holds the direct cotangent of the state before it and rates_bar (hi) the
- * cotangents of the rates.  SPH_STAGE_EOS: folds the cotangents of rho, p, c
- * and e into m, omega, v, E (rho = m / omega, p and c from the Tait EOS,
- * e = E - |v|^2 / 2), clears them, and adds d/dc0 to param_bar_dev[0]
- * (deterministic sum).  Errors: SPH_ERR_ARG, SPH_ERR_WORKSPACE,
- * SPH_ERR_UNSUPPORTED (walls, gravity or solids). */
+/* Adjoint of step (g) and of the solid stress stage (no walls, no gravity;
+ * fluids, and J2 solids with the linear EOS).  stage = SPH_STAGE_MOTION: p is
+ * the state BEFORE the update (hash-sorted), rates its FORCE rates; on entry
+ * bar holds the cotangent of the state after the update (x, v, m, omega, E),
+ * on return the direct cotangent of the state before it, and rates_bar (hi)
+ * receives the cotangents of the rates; S and eps_p pass through the update
+ * unchanged.  SPH_STAGE_EOS: folds the cotangents of rho, p, c and e into m,
+ * omega, v, E (rho = m / omega, p and c from the EOS, e = E - |v|^2 / 2),
+ * clears them, and adds d/dc0 to param_bar_dev[0] (deterministic sum; 0 for
+ * the linear solid EOS, whose c does not depend on c0).  SPH_STAGE_STRESS
+ * (solids): p holds S and eps_p BEFORE the stage and rates->Lhi (and Llo in
+ * SPH_FP32_SPLIT) the velocity gradient it used; on entry bar->S and
+ * bar->eps_p hold the cotangents of the stage's outputs, on return those of
+ * its inputs, and rates_bar->Lhi receives the cotangent of L (overwritten).
+ * Errors: SPH_ERR_ARG, SPH_ERR_WORKSPACE, SPH_ERR_UNSUPPORTED (walls,
+ * gravity, the Mie-Gruneisen EOS). */
 int sph_integrate_adjoint(const sph_params *params, int stage, const sph_particles *p,
                           const sph_rates *rates, const double *dt_dev, const sph_adjoint *bar,
                           const sph_rates *rates_bar, double *param_bar_dev, void *ws,
                           size_t ws_bytes, void *stream);
 
 /* Adjoint of the reorder in sph_build_cells: out[perm[k]] = in[k] for every
- * non-NULL field of the state cotangent (x, v, m, omega, E), n entries.
- * Errors: SPH_ERR_ARG. */
+ * non-NULL field of the state cotangent (x, v, m, omega, E, and for solids S
+ * and eps_p), n entries.  Errors: SPH_ERR_ARG. */
 int sph_permute_adjoint(int prec, uint32_t n, const uint32_t *perm, const sph_adjoint *in,
                         const sph_adjoint *out, void *stream);
 

@@ -53,7 +53,7 @@ class SphRates(C.Structure):
 
 class SphAdjoint(C.Structure):
     _fields_ = [("x", _vp * 3), ("v", _vp * 3), ("m", _vp), ("omega", _vp), ("E", _vp), ("rho", _vp),
-                ("p", _vp), ("c", _vp), ("e", _vp)]
+                ("p", _vp), ("c", _vp), ("e", _vp), ("S", _vp * 6), ("eps_p", _vp)]
 
 
 EXPORTS = ("sph_version", "sph_last_error", "sph_workspace_size", "sph_build_cells", "sph_mark_boundary",
@@ -99,8 +99,9 @@ def load():
                                       P(SphParticles), SphCells, _vp, _vp, _vp, C.c_size_t, _vp]
     L.sph_integrate.argtypes = [P(SphParams), C.c_int, P(SphParticles), P(SphRates), _vp, _vp, _vp,
                                 C.c_size_t, _vp]
-    L.sph_interact_adjoint.argtypes = [P(SphParams), P(SphGrid), P(SphParticles), _vp, _vp, P(SphParticles),
-                                       SphCells, P(SphRates), P(SphRates), P(SphAdjoint), _vp, C.c_size_t, _vp]
+    L.sph_interact_adjoint.argtypes = [P(SphParams), P(SphGrid), C.c_int, P(SphParticles), _vp, _vp,
+                                       P(SphParticles), SphCells, P(SphRates), P(SphRates), P(SphAdjoint), _vp,
+                                       C.c_size_t, _vp]
     L.sph_integrate_adjoint.argtypes = [P(SphParams), C.c_int, P(SphParticles), P(SphRates), _vp,
                                         P(SphAdjoint), P(SphRates), _vp, _vp, C.c_size_t, _vp]
     L.sph_permute_adjoint.argtypes = [C.c_int, C.c_uint32, _vp, P(SphAdjoint), P(SphAdjoint), _vp]
@@ -188,10 +189,10 @@ def sph_integrate(params, stage, p, rates, dt_ptr, diag_ptr, ws_ptr, ws_bytes, s
                                                        diag_ptr, ws_ptr, ws_bytes, stream))
 
 
-def sph_interact_adjoint(params, grid, targets, tidx_ptr, nt_ptr, sources, source_cells, rbar_targets, rbar_sources,
-                         bar, ws_ptr, ws_bytes, stream):
+def sph_interact_adjoint(params, grid, pass_, targets, tidx_ptr, nt_ptr, sources, source_cells, rbar_targets,
+                         rbar_sources, bar, ws_ptr, ws_bytes, stream):
     return check("sph_interact_adjoint",
-                 load().sph_interact_adjoint(C.byref(params), C.byref(grid), C.byref(targets), tidx_ptr, nt_ptr,
+                 load().sph_interact_adjoint(C.byref(params), C.byref(grid), pass_, C.byref(targets), tidx_ptr, nt_ptr,
                                              C.byref(sources), source_cells, _ref(rbar_targets), _ref(rbar_sources),
                                              C.byref(bar), ws_ptr, ws_bytes, stream))
 

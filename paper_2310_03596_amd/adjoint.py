@@ -29,14 +29,24 @@ from .state import Particles, Rates, cells_struct, real_dtype, stream_handle
 
 
 class Cotangent:
-    """Device buffers of a state cotangent (sph_adjoint), in the form's precision."""
+    """Device buffers of a state cotangent (sph_adjoint), in the form's
+    precision; with solid=True also of the deviatoric stress and the plastic
+    strain."""
 
-    def __init__(self, n: int, prec: int, device):
+    def __init__(self, n: int, prec: int, device, solid: bool = False):
         real = real_dtype(prec)
         self.x = torch.zeros((3, n), dtype=real, device=device)
         self.v = torch.zeros((3, n), dtype=real, device=device)
         self.m, self.w, self.E, self.rho, self.p, self.c, self.e = [
             torch.zeros(n, dtype=real, device=device) for _ in range(7)]
+        self.S = torch.zeros((6, n), dtype=real, device=device) if solid else None
+        self.ep = torch.zeros(n, dtype=real, device=device) if solid else None
+
+    def _solid_fields(self, a):
+        if self.S is not None:
+            for k in range(6):
+                a.S[k] = self.S[k].data_ptr()
+            a.eps_p = self.ep.data_ptr()
 
     def struct(self) -> L.SphAdjoint:
         a = L.SphAdjoint()
@@ -45,6 +55,7 @@ class Cotangent:
             a.v[d] = self.v[d].data_ptr()
         a.m, a.omega, a.E = self.m.data_ptr(), self.w.data_ptr(), self.E.data_ptr()
         a.rho, a.p, a.c, a.e = self.rho.data_ptr(), self.p.data_ptr(), self.c.data_ptr(), self.e.data_ptr()
+        self._solid_fields(a)
         return a
 
     def state_struct(self) -> L.SphAdjoint:
@@ -54,6 +65,7 @@ class Cotangent:
             a.x[d] = self.x[d].data_ptr()
             a.v[d] = self.v[d].data_ptr()
         a.m, a.omega, a.E = self.m.data_ptr(), self.w.data_ptr(), self.E.data_ptr()
+        self._solid_fields(a)
         return a
 
 
@@ -158,8 +170,9 @@ class KineticEnergyRollout:
                     L.sph_integrate_adjoint(sim.params, L.SPH_STAGE_MOTION, ps, rates.struct(), fixed,
                                             bar.struct(), rbar.struct(), None, None, 0, st_b)
                     rb = rbar.struct()
-                    L.sph_interact_adjoint(sim.params, sim.grid, ps, None, None, ps, cells_struct(start, sim.nc),
-                                           rb, rb, bar.struct(), ws_adj.data_ptr(), ws_adj_bytes, st_b)
+                    L.sph_interact_adjoint(sim.params, sim.grid, L.SPH_PASS_FORCE, ps, None, None, ps,
+                                           cells_struct(start, sim.nc), rb, rb, bar.struct(), ws_adj.data_ptr(),
+                                           ws_adj_bytes, st_b)
                     L.sph_integrate_adjoint(sim.params, L.SPH_STAGE_EOS, ps, None, None, bar.struct(), None,
                                             c0bar.data_ptr(), ws_adj.data_ptr(), ws_adj_bytes, st_b)
                     L.sph_permute_adjoint(prec, n, perm.data_ptr(), bar.state_struct(), tmp.state_struct(), st_b)
@@ -173,6 +186,95 @@ class KineticEnergyRollout:
         v0 = self.ckpts[0].v.double()
         vbar = bar.v.double() + bar.E.double()[None, :] * v0
         return vbar.T.cpu().numpy(), float(c0bar.cpu()[0])
+
+
+class SolidKineticEnergyRollout:
+    """The kinetic energy after `nsteps` fixed-dt steps of a J2 solid (linear
+    EOS, free boundaries) and its hand adjoint with respect to the initial
+    velocities (at fixed specific internal energy) and the initial
+    deviatoric stress.  A solid step runs two interaction loops (the paper's
+    note on several loops per iteration): GRADIENT, the stress stage, FORCE,
+    then the update.  Reverse of one step: MOTION, FORCE pair reverse (with
+    the stress terms), EOS, the stress stage's reverse (Jaumann rate and
+    radial return with hardening), the GRADIENT pair reverse, the permutation.
+    Checkpoints every `ckpt` steps; the recompute keeps each step's sorted
+    state before and after the stress stage, its permutation, bucket table,
+    velocity gradient and rates."""
+
+    def __init__(self, wl, prec: int, nsteps: int, ckpt: int, dt: float, device="cuda"):
+        assert wl.S is not None, "a solid workload"
+        self.wl, self.prec, self.nsteps, self.ckpt, self.dt, self.device = wl, prec, nsteps, max(1, ckpt), dt, device
+        self.e0 = wl.E - 0.5 * np.einsum("ij,ij->i", wl.v, wl.v)
+
+    def forward(self, v0: np.ndarray, S0: np.ndarray | None = None) -> float:
+        w = copy.copy(self.wl)
+        w.v = np.ascontiguousarray(v0, dtype=np.float64)
+        w.E = self.e0 + 0.5 * np.einsum("ij,ij->i", w.v, w.v)
+        if S0 is not None:
+            w.S = np.ascontiguousarray(S0, dtype=np.float64)
+        sim = Sim(w, self.prec, self.device, fixed_dt=self.dt)
+        self.sim = sim
+        self.ckpts = []
+        for k in range(self.nsteps):
+            if k % self.ckpt == 0:
+                self.ckpts.append(sim.A.clone())
+            sim.step()
+        torch.cuda.synchronize()
+        self.final = sim.A
+        return float(sim.diagnostics()[6])
+
+    def backward(self, gJ: float):
+        sim = self.sim
+        n, prec, dev = sim.n, self.prec, self.device
+        real = real_dtype(prec)
+        bar = Cotangent(n, prec, dev, solid=True)
+        tmp = Cotangent(n, prec, dev, solid=True)
+        v = self.final.v.double()
+        bar.v.copy_((gJ * self.final.m.double() * v).to(real))
+        bar.m.copy_((gJ * 0.5 * (v * v).sum(0)).to(real))
+        c0bar = torch.zeros(1, dtype=torch.float64, device=dev)
+        rbar = Rates(n, prec, True, dev)
+        ws_bytes = L.sph_workspace_size(sim.grid, n, prec, L.SPH_SOLID_J2)
+        ws = torch.zeros(ws_bytes, dtype=torch.uint8, device=dev)
+        fixed = sim.fixed.data_ptr()
+        st = stream_handle()
+        FORCE, GRAD = L.SPH_PASS_FORCE, L.SPH_PASS_GRADIENT
+        for seg in reversed(range(len(self.ckpts))):
+            k0 = seg * self.ckpt
+            k1 = min(k0 + self.ckpt, self.nsteps)
+            sim.A.copy_from(self.ckpts[seg])
+            saved = []
+            for _ in range(k0, k1):
+                sim.build()
+                a, r = sim.A.struct(), sim.rates.struct()
+                pre = sim.A.clone()
+                L.sph_interact(sim.params, sim.grid, GRAD, a, None, None, a, sim.cells, 1, r, sim.ws.data_ptr(),
+                               sim.ws_bytes, st)
+                L.sph_integrate(sim.params, L.SPH_STAGE_STRESS, a, r, fixed, None, None, 0, st)
+                L.sph_interact(sim.params, sim.grid, FORCE, a, None, None, a, sim.cells, 1, r, sim.ws.data_ptr(),
+                               sim.ws_bytes, st)
+                saved.append((pre, sim.A.clone(), sim.perm.clone(), sim.start.clone(), sim.rates.clone()))
+                L.sph_integrate(sim.params, L.SPH_STAGE_MOTION, a, r, fixed, sim.diag[0].data_ptr(),
+                                sim.ws.data_ptr(), sim.ws_bytes, st)
+            for pre, post, perm, start, rates in reversed(saved):
+                cells = cells_struct(start, sim.nc)
+                ps, pp, rb = post.struct(), pre.struct(), rbar.struct()
+                L.sph_integrate_adjoint(sim.params, L.SPH_STAGE_MOTION, ps, rates.struct(), fixed, bar.struct(), rb,
+                                        None, None, 0, st)
+                L.sph_interact_adjoint(sim.params, sim.grid, FORCE, ps, None, None, ps, cells, rb, rb, bar.struct(),
+                                       ws.data_ptr(), ws_bytes, st)
+                L.sph_integrate_adjoint(sim.params, L.SPH_STAGE_EOS, ps, None, None, bar.struct(), None,
+                                        c0bar.data_ptr(), ws.data_ptr(), ws_bytes, st)
+                L.sph_integrate_adjoint(sim.params, L.SPH_STAGE_STRESS, pp, rates.struct(), fixed, bar.struct(), rb,
+                                        None, None, 0, st)
+                L.sph_interact_adjoint(sim.params, sim.grid, GRAD, pp, None, None, pp, cells, rb, rb, bar.struct(),
+                                       ws.data_ptr(), ws_bytes, st)
+                L.sph_permute_adjoint(prec, n, perm.data_ptr(), bar.state_struct(), tmp.state_struct(), st)
+                bar, tmp = tmp, bar
+        torch.cuda.synchronize()
+        v0 = self.ckpts[0].v.double()
+        vbar = bar.v.double() + bar.E.double()[None, :] * v0
+        return vbar.T.cpu().numpy(), bar.S.double().T.cpu().numpy()
 
 
 class TwoSetKineticEnergyRollout:
@@ -253,11 +355,12 @@ class TwoSetKineticEnergyRollout:
                     srt, perm, start, rates = rec[q]
                     oth, _, ostart, _ = rec[1 - q]
                     ps, rb = srt.struct(), rbars[q].struct()
-                    L.sph_interact_adjoint(ts.params, ts.grid, ps, None, None, ps, cells_struct(start, ts.nc), rb, rb,
-                                           bars[q].struct(), ws.data_ptr(), ws_bytes, st)
-                    L.sph_interact_adjoint(ts.params, ts.grid, ps, blist[q].data_ptr(), nb[q:q + 1].data_ptr(),
-                                           oth.struct(), cells_struct(ostart, ts.nc), rb, rbars[1 - q].struct(),
-                                           bars[q].struct(), ws.data_ptr(), ws_bytes, st)
+                    L.sph_interact_adjoint(ts.params, ts.grid, L.SPH_PASS_FORCE, ps, None, None, ps,
+                                           cells_struct(start, ts.nc), rb, rb, bars[q].struct(), ws.data_ptr(),
+                                           ws_bytes, st)
+                    L.sph_interact_adjoint(ts.params, ts.grid, L.SPH_PASS_FORCE, ps, blist[q].data_ptr(),
+                                           nb[q:q + 1].data_ptr(), oth.struct(), cells_struct(ostart, ts.nc), rb,
+                                           rbars[1 - q].struct(), bars[q].struct(), ws.data_ptr(), ws_bytes, st)
                 for q in range(2):
                     srt, perm, start, rates = rec[q]
                     L.sph_integrate_adjoint(ts.params, L.SPH_STAGE_EOS, srt.struct(), None, None, bars[q].struct(),

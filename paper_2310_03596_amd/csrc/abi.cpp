@@ -381,7 +381,7 @@ int sph_integrate(const sph_params *params, int stage, sph_particles *p, const s
                       "sph_integrate");
 }
 
-int sph_interact_adjoint(const sph_params *params, const sph_grid *grid, const sph_particles *targets,
+int sph_interact_adjoint(const sph_params *params, const sph_grid *grid, int pass, const sph_particles *targets,
                          const uint32_t *target_idx, const uint32_t *n_targets_dev, const sph_particles *sources,
                          sph_cells source_cells, const sph_rates *rates_bar_targets,
                          const sph_rates *rates_bar_sources, const sph_adjoint *bar, void *ws, size_t ws_bytes,
@@ -390,26 +390,42 @@ int sph_interact_adjoint(const sph_params *params, const sph_grid *grid, const s
     Grid g;
     Params P;
     if (!make_grid(grid, g) || !make_params(params, grid, P)) return SPH_ERR_ARG;
-    if (params->material != SPH_FLUID_TAIT) return fail(SPH_ERR_UNSUPPORTED, "adjoint is provided for fluids");
+    if (pass != SPH_PASS_FORCE && pass != SPH_PASS_GRADIENT) return fail(SPH_ERR_ARG, "unknown pass %d", pass);
+    const bool solid = params->material == SPH_SOLID_J2;
+    if (solid && pass == SPH_PASS_FORCE && params->eos != SPH_EOS_LINEAR)
+        return fail(SPH_ERR_UNSUPPORTED, "the solid adjoint is provided for the linear EOS");
     if (!targets || !sources) return fail(SPH_ERR_ARG, "targets/sources is NULL");
     if (targets->prec != params->prec || sources->prec != params->prec)
         return fail(SPH_ERR_ARG, "particle precision does not match params.prec");
-    if (!check_particles(targets, "targets", true, false) || !check_particles(sources, "sources", true, false))
+    const bool solid_force = solid && pass == SPH_PASS_FORCE;
+    if (!check_particles(targets, "targets", true, solid_force) ||
+        !check_particles(sources, "sources", true, solid_force))
         return SPH_ERR_ARG;
     if (target_idx && !n_targets_dev) return fail(SPH_ERR_ARG, "target_idx given without n_targets_dev");
     if (!source_cells.start || source_cells.ncells != g.ncells)
         return fail(SPH_ERR_ARG, "source bucket table missing or not on this grid");
     if (!rates_bar_targets && !rates_bar_sources) return fail(SPH_ERR_ARG, "no rate cotangents given");
     const sph_rates *rb[2] = {rates_bar_targets, rates_bar_sources};
-    for (int q = 0; q < 2; ++q)
-        if (rb[q])
+    for (int q = 0; q < 2; ++q) {
+        if (!rb[q]) continue;
+        const char *side = q ? "sources" : "targets";
+        if (pass == SPH_PASS_FORCE) {
             for (int k = 0; k < 6; ++k)
-                if (!rb[q]->hi[k]) return fail(SPH_ERR_ARG, "rates_bar_%s.hi[%d] is NULL", q ? "sources" : "targets", k);
+                if (!rb[q]->hi[k]) return fail(SPH_ERR_ARG, "rates_bar_%s.hi[%d] is NULL", side, k);
+        } else {
+            for (int k = 0; k < 9; ++k)
+                if (!rb[q]->Lhi[k]) return fail(SPH_ERR_ARG, "rates_bar_%s.Lhi[%d] is NULL", side, k);
+        }
+    }
     if (!bar) return fail(SPH_ERR_ARG, "bar is NULL");
     for (int d = 0; d < 3; ++d)
         if (!bar->x[d] || !bar->v[d]) return fail(SPH_ERR_ARG, "bar.x / bar.v is NULL");
-    if (!bar->omega || !bar->rho || !bar->p || !bar->c || !bar->e)
-        return fail(SPH_ERR_ARG, "bar.omega/rho/p/c/e is NULL");
+    if (!bar->omega) return fail(SPH_ERR_ARG, "bar.omega is NULL");
+    if (pass == SPH_PASS_FORCE && (!bar->rho || !bar->p || !bar->c || !bar->e))
+        return fail(SPH_ERR_ARG, "bar.rho/p/c/e is NULL");
+    if (solid_force)
+        for (int k = 0; k < 6; ++k)
+            if (!bar->S[k]) return fail(SPH_ERR_ARG, "bar.S[%d] is NULL for a solid", k);
     if (targets->n == 0) return SPH_OK;
     const uint32_t src_max = 1u << 27;   // as in sph_interact
     if (sources->n >= src_max) return fail(SPH_ERR_ARG, "sources.n = %u must be below %u", sources->n, src_max);
@@ -419,7 +435,7 @@ int sph_interact_adjoint(const sph_params *params, const sph_grid *grid, const s
     if (self && targets->n != sources->n)
         return fail(SPH_ERR_ARG, "targets and sources share their hash array but not their size");
     const sph_rates none{};
-    return hip_status(launch_interact_adjoint(P, g, params->prec, *targets, target_idx, n_targets_dev, *sources,
+    return hip_status(launch_interact_adjoint(P, g, params->prec, pass, *targets, target_idx, n_targets_dev, *sources,
                                               source_cells.start, self, rates_bar_targets ? *rates_bar_targets : none,
                                               rates_bar_sources ? *rates_bar_sources : none, *bar, w,
                                               (hipStream_t)stream),
@@ -432,26 +448,40 @@ int sph_integrate_adjoint(const sph_params *params, int stage, const sph_particl
 {
     Params P;
     if (!make_params(params, nullptr, P)) return SPH_ERR_ARG;
-    if (params->material != SPH_FLUID_TAIT) return fail(SPH_ERR_UNSUPPORTED, "adjoint is provided for fluids");
+    const bool solid = params->material == SPH_SOLID_J2;
+    if (solid && params->eos != SPH_EOS_LINEAR)
+        return fail(SPH_ERR_UNSUPPORTED, "the solid adjoint is provided for the linear EOS");
     if (params->wall_mask != 0 || params->gravity[0] != 0.0 || params->gravity[1] != 0.0 ||
         params->gravity[2] != 0.0)
         return fail(SPH_ERR_UNSUPPORTED, "adjoint is provided without walls and gravity");
-    if (stage != SPH_STAGE_MOTION && stage != SPH_STAGE_EOS)
-        return fail(SPH_ERR_ARG, "adjoint stage must be MOTION or EOS");
+    if (stage != SPH_STAGE_MOTION && stage != SPH_STAGE_EOS && stage != SPH_STAGE_STRESS)
+        return fail(SPH_ERR_ARG, "unknown adjoint stage %d", stage);
+    if (stage == SPH_STAGE_STRESS && !solid) return fail(SPH_ERR_ARG, "the stress stage needs a solid");
     if (!p || p->prec != params->prec) return fail(SPH_ERR_ARG, "particles missing or precision mismatch");
-    if (!check_particles(p, "particles", false, false)) return SPH_ERR_ARG;
+    if (!check_particles(p, "particles", false, stage == SPH_STAGE_STRESS)) return SPH_ERR_ARG;
     if (!bar) return fail(SPH_ERR_ARG, "bar is NULL");
-    for (int d = 0; d < 3; ++d)
-        if (!bar->x[d] || !bar->v[d]) return fail(SPH_ERR_ARG, "bar.x / bar.v is NULL");
-    if (!bar->m || !bar->omega || !bar->E) return fail(SPH_ERR_ARG, "bar.m/omega/E is NULL");
     Workspace w{};
+    if (stage == SPH_STAGE_STRESS) {
+        if (!dt_dev) return fail(SPH_ERR_ARG, "dt_dev is NULL");
+        if (!check_rates(rates, SPH_PASS_GRADIENT, params->prec)) return SPH_ERR_ARG;
+        if (!rates_bar) return fail(SPH_ERR_ARG, "rates_bar is NULL");
+        for (int k = 0; k < 9; ++k)
+            if (!rates_bar->Lhi[k]) return fail(SPH_ERR_ARG, "rates_bar.Lhi[%d] is NULL", k);
+        for (int k = 0; k < 6; ++k)
+            if (!bar->S[k]) return fail(SPH_ERR_ARG, "bar.S[%d] is NULL", k);
+        if (!bar->eps_p) return fail(SPH_ERR_ARG, "bar.eps_p is NULL");
+    } else {
+        for (int d = 0; d < 3; ++d)
+            if (!bar->x[d] || !bar->v[d]) return fail(SPH_ERR_ARG, "bar.x / bar.v is NULL");
+        if (!bar->m || !bar->omega || !bar->E) return fail(SPH_ERR_ARG, "bar.m/omega/E is NULL");
+    }
     if (stage == SPH_STAGE_MOTION) {
         if (!dt_dev) return fail(SPH_ERR_ARG, "dt_dev is NULL");
         if (!check_rates(rates, SPH_PASS_FORCE, params->prec)) return SPH_ERR_ARG;
         if (!rates_bar) return fail(SPH_ERR_ARG, "rates_bar is NULL");
         for (int k = 0; k < 6; ++k)
             if (!rates_bar->hi[k]) return fail(SPH_ERR_ARG, "rates_bar.hi[%d] is NULL", k);
-    } else {
+    } else if (stage == SPH_STAGE_EOS) {
         if (!bar->rho || !bar->p || !bar->c || !bar->e) return fail(SPH_ERR_ARG, "bar.rho/p/c/e is NULL");
         if (!param_bar_dev) return fail(SPH_ERR_ARG, "param_bar_dev is NULL");
         if (!check_ws(ws, ws_bytes, p->n, w)) return SPH_ERR_WORKSPACE;
@@ -469,9 +499,11 @@ int sph_permute_adjoint(int prec, uint32_t n, const uint32_t *perm, const sph_ad
     if (prec != SPH_FP64 && prec != SPH_FP32_SPLIT) return fail(SPH_ERR_ARG, "unknown precision %d", prec);
     if (n == 0) return SPH_OK;
     if (!perm || !in || !out) return fail(SPH_ERR_ARG, "perm/in/out is NULL");
-    const void *a[] = {in->x[0], in->x[1], in->x[2], in->v[0], in->v[1], in->v[2], in->m, in->omega, in->E};
-    const void *b[] = {out->x[0], out->x[1], out->x[2], out->v[0], out->v[1], out->v[2], out->m, out->omega, out->E};
-    for (int k = 0; k < 9; ++k) {
+    const void *a[] = {in->x[0], in->x[1], in->x[2], in->v[0], in->v[1], in->v[2], in->m, in->omega, in->E,
+                       in->S[0], in->S[1], in->S[2], in->S[3], in->S[4], in->S[5], in->eps_p};
+    const void *b[] = {out->x[0], out->x[1], out->x[2], out->v[0], out->v[1], out->v[2], out->m, out->omega, out->E,
+                       out->S[0], out->S[1], out->S[2], out->S[3], out->S[4], out->S[5], out->eps_p};
+    for (int k = 0; k < 16; ++k) {
         if ((a[k] == nullptr) != (b[k] == nullptr)) return fail(SPH_ERR_ARG, "in/out field %d mismatch", k);
         if (a[k] && a[k] == b[k]) return fail(SPH_ERR_ARG, "in and out field %d overlap", k);
     }

@@ -77,7 +77,9 @@ __global__ __launch_bounds__(kBlock) void k_motion_adj(PV<real> s, RV<real> R, c
 }
 
 // Fold the cotangents of rho, p, c, e into m, omega, v, E; clear them; the
-// per-block partial of d/dc0 goes to partials (slot 0).
+// per-block partial of d/dc0 goes to partials (slot 0).  Tait fluid:
+// p' = c^2, c' = c (gamma - 1) / (2 rho), and p and c scale as c0^2 and c0;
+// linear solid EOS: p' = K / rho0 and a constant c (no c0 term).
 template <typename real>
 __global__ __launch_bounds__(kBlock) void k_eos_adj(Params P, PV<real> s, AV<real> bar, double *__restrict__ partials)
 {
@@ -87,15 +89,19 @@ __global__ __launch_bounds__(kBlock) void k_eos_adj(Params P, PV<real> s, AV<rea
     if (i < s.n) {
         const double m = (double)s.m[i], w = (double)s.w[i];
         const double rho = m / w;
-        const double sr = rho / P.rho0;
-        double s_gam, s_half;
-        tait_powers<real>(P, sr, s_gam, s_half);
-        const double p = P.B * (s_gam - 1.0);
-        const double c = P.c0 * s_half;
         const double bp = (double)bar.p[i], bc = (double)bar.c[i], be = (double)bar.e[i];
-        // p' = c^2, c' = c (gamma - 1) / (2 rho); p and c scale as c0^2 and c0
-        const double brho = (double)bar.rho[i] + bp * c * c + bc * c * (P.gamma - 1.0) / (2.0 * rho);
-        dc0 = (bp * 2.0 * p + bc * c) / P.c0;
+        double brho = (double)bar.rho[i];
+        if (P.material == SPH_FLUID_TAIT) {
+            const double sr = rho / P.rho0;
+            double s_gam, s_half;
+            tait_powers<real>(P, sr, s_gam, s_half);
+            const double p = P.B * (s_gam - 1.0);
+            const double c = P.c0 * s_half;
+            brho += bp * c * c + bc * c * (P.gamma - 1.0) / (2.0 * rho);
+            dc0 = (bp * 2.0 * p + bc * c) / P.c0;
+        } else {
+            brho += bp * P.K / P.rho0;
+        }
         bar.m[i] = (real)((double)bar.m[i] + brho / w);
         bar.w[i] = (real)((double)bar.w[i] - brho * rho / w);
         bar.E[i] = (real)((double)bar.E[i] + be);
@@ -116,6 +122,111 @@ __global__ __launch_bounds__(kBlock) void k_eos_adj(Params P, PV<real> s, AV<rea
         for (int k = 0; k < kBlock / kWave; ++k) t += sh[k];
         partials[blockIdx.x] = t;
     }
+}
+
+// Reverse of the stress stage (Jaumann rate and J2 radial return with linear
+// hardening), one thread per particle.  s holds the stress and plastic strain
+// BEFORE the stage, L the velocity gradient it used; on entry bar.S and
+// bar.ep hold the cotangents of the stage's outputs S+ and eps_p+, on return
+// those of its inputs S and eps_p, and Lbar (overwritten) that of L.  On the
+// plastic branch S+ = f S_tr with f = (1 - a) + a sy / q, a = 3G / (3G + H),
+// and eps_p+ = eps_p + (q - sy) / (3G + H), sy = Y0 + H eps_p.
+template <typename real, bool SPLIT>
+__global__ __launch_bounds__(kBlock) void k_stress_adj(Params P, PV<real> s, RV<real> R, const double *__restrict__ dtp,
+                                                       AV<real> bar, RV<real> Lbar)
+{
+    uint32_t i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= s.n) return;
+    const double dt = *dtp, G = P.G;
+    double L[3][3], D[3][3], W[3][3], S[3][3];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) L[k / 3][k % 3] = (double)R.Lhi[k][i] + (SPLIT ? (double)R.Llo[k][i] : 0.0);
+    const double s6[6] = {(double)s.S[0][i], (double)s.S[1][i], (double)s.S[2][i],
+                          (double)s.S[3][i], (double)s.S[4][i], (double)s.S[5][i]};
+    const int sym[3][3] = {{0, 3, 4}, {3, 1, 5}, {4, 5, 2}};
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            D[a][b] = 0.5 * (L[a][b] + L[b][a]);
+            W[a][b] = 0.5 * (L[a][b] - L[b][a]);
+            S[a][b] = s6[sym[a][b]];
+        }
+    const double tr = D[0][0] + D[1][1] + D[2][2];
+    double St[3][3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            double ws = 0.0, sw = 0.0;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                ws += W[a][k] * S[k][b];
+                sw += S[a][k] * W[k][b];
+            }
+            St[a][b] = S[a][b] + dt * (2.0 * G * (D[a][b] - (a == b ? tr / 3.0 : 0.0)) + ws - sw);
+        }
+    const double t6[6] = {St[0][0], St[1][1], St[2][2], St[0][1], St[0][2], St[1][2]};
+    const double J = (t6[0] * t6[0] + t6[1] * t6[1] + t6[2] * t6[2]) + 2.0 * (t6[3] * t6[3] + t6[4] * t6[4] + t6[5] * t6[5]);
+    const double q = sqrt(1.5 * J);
+    const double ep = (double)s.ep[i];
+    const double sy = P.Y0 + P.H * ep;
+    double bS6[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) bS6[k] = (double)bar.S[k][i];
+    const double bep_out = (double)bar.ep[i];
+    double bt6[6], bep = bep_out;
+    if (q > sy) {
+        const double a = 3.0 * G / (3.0 * G + P.H);
+        const double f = (1.0 - a) + a * sy / q;
+        double bf = 0.0;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            bt6[k] = f * bS6[k];
+            bf += bS6[k] * t6[k];
+        }
+        const double bq = -bf * a * sy / (q * q) + bep_out / (3.0 * G + P.H);
+        const double bsy = bf * a / q - bep_out / (3.0 * G + P.H);
+        bep += P.H * bsy;
+        // q = sqrt(3/2 J), J counts the off-diagonals twice
+#pragma unroll
+        for (int k = 0; k < 6; ++k) bt6[k] += bq * 1.5 * (k < 3 ? 1.0 : 2.0) * t6[k] / q;
+    } else {
+#pragma unroll
+        for (int k = 0; k < 6; ++k) bt6[k] = bS6[k];
+    }
+    // full symmetric cotangent B of S_tr (a stored off-diagonal splits in two halves)
+    double B[3][3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) B[a][b] = a == b ? bt6[sym[a][b]] : 0.5 * bt6[sym[a][b]];
+    // S_tr = S + dt (2G dev D + W S - S W):
+    //   Sbar += B + dt (B W - W B),  Lbar = dt (2G dev B + B S - S B)
+    const double trB = B[0][0] + B[1][1] + B[2][2];
+    double bSf[3][3], bL[3][3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            double bw = 0.0, wb = 0.0, bs = 0.0, sb = 0.0;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                bw += B[a][k] * W[k][b];
+                wb += W[a][k] * B[k][b];
+                bs += B[a][k] * S[k][b];
+                sb += S[a][k] * B[k][b];
+            }
+            bSf[a][b] = B[a][b] + dt * (bw - wb);
+            bL[a][b] = dt * (2.0 * G * (B[a][b] - (a == b ? trB / 3.0 : 0.0)) + bs - sb);
+        }
+    const double out6[6] = {bSf[0][0], bSf[1][1], bSf[2][2], bSf[0][1] + bSf[1][0], bSf[0][2] + bSf[2][0],
+                            bSf[1][2] + bSf[2][1]};
+#pragma unroll
+    for (int k = 0; k < 6; ++k) bar.S[k][i] = (real)out6[k];
+    bar.ep[i] = (real)bep;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) Lbar.Lhi[k][i] = (real)bL[k / 3][k % 3];
 }
 
 // One workgroup folds the block partials in a fixed order and adds to *out.
@@ -149,6 +260,10 @@ __global__ __launch_bounds__(kBlock) void k_permute(uint32_t n, const uint32_t *
     if (in.m) out.m[d] = in.m[k];
     if (in.w) out.w[d] = in.w[k];
     if (in.E) out.E[d] = in.E[k];
+#pragma unroll
+    for (int q = 0; q < 6; ++q)
+        if (in.S[q]) out.S[q][d] = in.S[q][k];
+    if (in.ep) out.ep[d] = in.ep[k];
 }
 
 template <typename real>
@@ -160,6 +275,10 @@ hipError_t go(const Params &P, int stage, const sph_particles &p, const sph_rate
     if (stage == SPH_STAGE_MOTION) {
         if (blocks)
             k_motion_adj<real, SPLIT><<<blocks, kBlock, 0, s>>>(view<real>(p), view<real>(r), dt, view<real>(bar),
+                                                                view<real>(rbar));
+    } else if (stage == SPH_STAGE_STRESS) {
+        if (blocks)
+            k_stress_adj<real, SPLIT><<<blocks, kBlock, 0, s>>>(P, view<real>(p), view<real>(r), dt, view<real>(bar),
                                                                 view<real>(rbar));
     } else {
         if (blocks) k_eos_adj<real><<<blocks, kBlock, 0, s>>>(P, view<real>(p), view<real>(bar), ws.partials);

@@ -156,6 +156,8 @@ struct AV {
     real *x[3];
     real *v[3];
     real *m, *w, *E, *rho, *p, *c, *e;
+    real *S[6];
+    real *ep;
 };
 
 template <typename real>
@@ -173,6 +175,8 @@ inline AV<real> view(const sph_adjoint &a)
     o.p = static_cast<real *>(a.p);
     o.c = static_cast<real *>(a.c);
     o.e = static_cast<real *>(a.e);
+    for (int k = 0; k < 6; ++k) o.S[k] = static_cast<real *>(a.S[k]);
+    o.ep = static_cast<real *>(a.eps_p);
     return o;
 }
 
@@ -199,17 +203,23 @@ struct Vec4<double> {
 template <typename real>
 constexpr uint32_t rec_stride = sizeof(real) == 4 ? 2 : 1;
 
+// Adjoint passes add two records of cotangents: r0 = (rbar 0..3) and
+// r1 = (rbar 4, 5, 0, 0) of the sources' rates (FORCE), or, for the
+// GRADIENT reverse, the velocity-gradient cotangent Lbar in vb (0..3), r0
+// (4..7) and r1.x (8).
 template <typename real>
 struct Stage {
     using v4 = typename Vec4<real>::type;
-    v4 *pos, *va, *vb, *s0, *s1;   // va, vb, s0, s1: record j at [rec_stride<real> j]
+    v4 *pos, *va, *vb, *s0, *s1, *r0, *r1;   // all but pos: record j at [rec_stride<real> j]
 };
 
-// Bytes per source particle of the packed records.
+// Bytes per source particle of the packed records: three for a fluid pass,
+// seven for material SPH_SOLID_J2 (the solid pass's two stress records and
+// the adjoint passes' two cotangent records).
 inline size_t stage_bytes(int prec, int material)
 {
     size_t rec = prec == SPH_FP64 ? 32 : 16;
-    return rec * (material == SPH_SOLID_J2 ? 5 : 3);
+    return rec * (material == SPH_SOLID_J2 ? 7 : 3);
 }
 
 // Workspace layout for n particles (256-byte aligned pieces).  The packed
@@ -255,18 +265,24 @@ inline Workspace carve(void *base, uint32_t n, size_t stage_per_particle)
     return w;
 }
 
+// Records 0 (pos), 1-2 (va, vb), 3-4 (s0, s1 for solids), then the adjoint's
+// (r0, r1): records 3-4 of a fluid adjoint, 5-6 of a solid one.
 template <typename real>
-inline Stage<real> stage_view(const Workspace &w, uint32_t n, bool solid)
+inline Stage<real> stage_view(const Workspace &w, uint32_t n, bool solid, bool adj = false)
 {
     using v4 = typename Vec4<real>::type;
     Stage<real> s;
     v4 *b = reinterpret_cast<v4 *>(w.stage);
     size_t nn = n > 0 ? n : 1;
+    auto pair_at = [&](size_t rec, v4 *&first, v4 *&second) {
+        first = b + rec * nn;
+        second = rec_stride<real> == 2 ? first + 1 : b + (rec + 1) * nn;
+    };
     s.pos = b;
-    s.va = b + nn;
-    s.vb = rec_stride<real> == 2 ? s.va + 1 : b + 2 * nn;
-    s.s0 = solid ? b + 3 * nn : nullptr;
-    s.s1 = solid ? (rec_stride<real> == 2 ? s.s0 + 1 : b + 4 * nn) : nullptr;
+    pair_at(1, s.va, s.vb);
+    s.s0 = s.s1 = s.r0 = s.r1 = nullptr;
+    if (solid) pair_at(3, s.s0, s.s1);
+    if (adj) pair_at(solid ? 5 : 3, s.r0, s.r1);
     return s;
 }
 
@@ -298,7 +314,7 @@ hipError_t launch_count_pairs(const Params &P, const Grid &g, int prec, const sp
 hipError_t launch_integrate(const Params &P, int prec, int stage, const sph_particles &p,
                             const sph_rates &r, const double *dt, double *diag, const Workspace &ws,
                             hipStream_t s);
-hipError_t launch_interact_adjoint(const Params &P, const Grid &g, int prec, const sph_particles &tg,
+hipError_t launch_interact_adjoint(const Params &P, const Grid &g, int prec, int pass, const sph_particles &tg,
                                    const uint32_t *tidx, const uint32_t *nt, const sph_particles &sr,
                                    const uint32_t *sstart, bool self, const sph_rates &rbar_t,
                                    const sph_rates &rbar_s, const sph_adjoint &bar, const Workspace &ws,

@@ -77,7 +77,8 @@ struct Tune {
 static_assert(Tune<float>::page + kSub <= 256 && Tune<double>::page + kSub <= 256, "page index must fit a u8 entry");
 static_assert(Tune<float>::page % kSub == 0 && Tune<double>::page % kSub == 0, "reads stay below page + kSub");
 static_assert(Tune<float>::cap <= 255 && Tune<double>::cap <= 255 && kMaxWin <= 255, "marks hold a u8 fill and slot");
-constexpr int kPassAdjoint = 2;            // reverse mode of the FORCE pass (fluid)
+constexpr int kPassAdjoint = 2;            // reverse mode of the FORCE pass
+constexpr int kPassGradAdjoint = 4;        // reverse mode of the GRADIENT pass
 constexpr int kPassCensus = 3;             // neighbour census of a FORCE or GRADIENT pass
 
 // Census outputs: per target, the number of sources the pass evaluates
@@ -104,11 +105,13 @@ __device__ inline unsigned long long mix64(uint32_t id)
 #endif
 // Occupancy target (waves per SIMD; caps VGPRs at 512 / target) per
 // variant: the LDS of a workgroup allows four per SIMD, which the fluid
-// passes and the FP32 solid pass reach; the FP64 solid body fits 3 and the
-// adjoint body (11 cotangents) 3 (FP32) and 2 (FP64).
-template <typename real, bool SOLID, bool ADJ>
+// passes and the FP32 solid pass reach; the FP64 solid body fits 3, the
+// fluid adjoint body (11 cotangents) 3 (FP32) and 2 (FP64), the solid
+// adjoint body (17) 2, the GRADIENT reverse 3 and 2.
+template <typename real, bool SOLID, int PASS>
 struct PairOccupancy {
-    static constexpr int fp32 = ADJ ? 3 : (SOLID ? 4 : SPH_PAIR_WAVES_PER_EU);
+    static constexpr bool ADJ = PASS == kPassAdjoint || PASS == kPassGradAdjoint;
+    static constexpr int fp32 = ADJ ? ((SOLID && PASS == kPassAdjoint) ? 2 : 3) : (SOLID ? 4 : SPH_PAIR_WAVES_PER_EU);
     static constexpr int fp64 = ADJ ? 2 : 3;   // measured: FP64 passes run faster at 3 than at 4 (no spills)
     static constexpr int value = sizeof(real) == 4 ? fp32 : fp64;
 };
@@ -317,7 +320,7 @@ struct Acc {
 
 template <typename real, int PASS, bool SOLID, bool SELF>
 __global__ __launch_bounds__(kPairBlock)
-__attribute__((amdgpu_waves_per_eu(PairOccupancy<real, SOLID, PASS == kPassAdjoint>::value)))
+__attribute__((amdgpu_waves_per_eu(PairOccupancy<real, SOLID, PASS>::value)))
 void k_pairs(Params P, Grid g, PV<real> tg, const uint32_t *__restrict__ tidx, const uint32_t *__restrict__ ntdev,
              Stage<real> src, const uint32_t *__restrict__ sstart, int zero_first, RV<real> R, AV<real> B,
              const uint2 *__restrict__ plan, const uint32_t *__restrict__ nplan, Census cz)
@@ -325,8 +328,9 @@ void k_pairs(Params P, Grid g, PV<real> tg, const uint32_t *__restrict__ tidx, c
     using v4 = typename Vec4<real>::type;
     constexpr bool SPLIT = sizeof(real) == 4;
     constexpr bool ADJ = PASS == kPassAdjoint;
+    constexpr bool GADJ = PASS == kPassGradAdjoint;
     constexpr bool CENSUS = PASS == kPassCensus;
-    constexpr int NOUT = PASS == SPH_PASS_FORCE ? 6 : (ADJ ? 11 : (CENSUS ? 1 : 9));
+    constexpr int NOUT = PASS == SPH_PASS_FORCE ? 6 : (ADJ ? (SOLID ? 17 : 11) : (GADJ ? 7 : (CENSUS ? 1 : 9)));
     constexpr int kPage = Tune<real>::page;
     constexpr int kHitCap = Tune<real>::cap;
     // List entries and marks are laid out so that the 64 lanes of a wavefront
@@ -397,23 +401,28 @@ void k_pairs(Params P, Grid g, PV<real> tg, const uint32_t *__restrict__ tidx, c
         }
     }
     Part<real, SOLID> I;
-    real rbi[6];   // adjoint: the target's rate cotangents
+    real rbi[GADJ ? 9 : 6];   // adjoint: the target's rate (or velocity-gradient) cotangents
     if constexpr (PASS == SPH_PASS_FORCE || ADJ) {
         load_part<real, SOLID>(tg, i, I);
     } else if constexpr (!CENSUS) {
 #pragma unroll
         for (int d = 0; d < 3; ++d) I.v[d] = tg.v[d][i];
+        if constexpr (GADJ) I.w = tg.w[i];
     }
     if constexpr (ADJ) {
 #pragma unroll
         for (int k = 0; k < 6; ++k) rbi[k] = R.hi[0] ? R.hi[k][i] : real(0);
+    }
+    if constexpr (GADJ) {
+#pragma unroll
+        for (int k = 0; k < 9; ++k) rbi[k] = R.Lhi[0] ? R.Lhi[k][i] : real(0);
     }
 
     Acc acc[NOUT];
 #pragma unroll
     for (int k = 0; k < NOUT; ++k) {
         double s0 = 0.0;
-        if constexpr (!ADJ && !CENSUS) {
+        if constexpr (!ADJ && !GADJ && !CENSUS) {
             real *hi = PASS == SPH_PASS_FORCE ? R.hi[k] : R.Lhi[k];
             real *lo = PASS == SPH_PASS_FORCE ? R.lo[k] : R.Llo[k];
             if (!zero_first && valid) {
@@ -430,7 +439,7 @@ void k_pairs(Params P, Grid g, PV<real> tg, const uint32_t *__restrict__ tidx, c
     // Records of one listed hit; the next hit's are loaded while the current
     // pair is evaluated (software pipelining hides the L2 latency).
     struct Rec {
-        v4 p, a, b, s0, s1;
+        v4 p, a, b, s0, s1, r0, r1;
         real qy, qz;
         uint32_t j;
     };
@@ -456,10 +465,14 @@ void k_pairs(Params P, Grid g, PV<real> tg, const uint32_t *__restrict__ tidx, c
         if constexpr (CENSUS) return q;
         const uint32_t ob2 = ob * rec_stride<real>;
         q.a = at(src.va, ob2);
-        if constexpr (PASS == SPH_PASS_FORCE || ADJ) q.b = at(src.vb, ob2);
-        if constexpr ((PASS == SPH_PASS_FORCE && SOLID) || ADJ) {
+        if constexpr (PASS == SPH_PASS_FORCE || ADJ || GADJ) q.b = at(src.vb, ob2);
+        if constexpr ((PASS == SPH_PASS_FORCE || ADJ) && SOLID) {
             q.s0 = at(src.s0, ob2);
             q.s1 = at(src.s1, ob2);
+        }
+        if constexpr (ADJ || GADJ) {
+            q.r0 = at(src.r0, ob2);
+            q.r1 = at(src.r1, ob2);
         }
         return q;
     };
@@ -499,7 +512,7 @@ void k_pairs(Params P, Grid g, PV<real> tg, const uint32_t *__restrict__ tidx, c
 #pragma unroll
                 for (int k = 0; k < 6; ++k) acc[k].add(o[k]);
             } else if constexpr (ADJ) {
-                Part<real, false> J, Ii;
+                Part<real, SOLID> J;
                 J.v[0] = cur.a.x;
                 J.v[1] = cur.a.y;
                 J.v[2] = cur.a.z;
@@ -508,24 +521,35 @@ void k_pairs(Params P, Grid g, PV<real> tg, const uint32_t *__restrict__ tidx, c
                 J.p = cur.b.y;
                 J.c = cur.b.z;
                 J.e = cur.b.w;
-#pragma unroll
-                for (int k = 0; k < 3; ++k) Ii.v[k] = I.v[k];
-                Ii.w = I.w;
-                Ii.rho = I.rho;
-                Ii.p = I.p;
-                Ii.c = I.c;
-                Ii.e = I.e;
+                if constexpr (SOLID) {
+                    J.S[0] = cur.s0.x;
+                    J.S[1] = cur.s0.y;
+                    J.S[2] = cur.s0.z;
+                    J.S[3] = cur.s0.w;
+                    J.S[4] = cur.s1.x;
+                    J.S[5] = cur.s1.y;
+                }
                 // T(s_j, s_i) = sigma T(s_i, s_j): mass, momentum and energy terms
                 // are odd (sigma = -1), the volume term even (+1)
-                const real rbj[6] = {cur.s0.x, cur.s0.y, cur.s0.z, cur.s0.w, cur.s1.x, cur.s1.y};
+                const real rbj[6] = {cur.r0.x, cur.r0.y, cur.r0.z, cur.r0.w, cur.r1.x, cur.r1.y};
                 real wb[6];
 #pragma unroll
                 for (int k = 0; k < 5; ++k) wb[k] = rbi[k] - rbj[k];
                 wb[5] = rbi[5] + rbj[5];
-                real o[11] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-                pair_force_vjp<real>(d, r2, Ii, J, K, wb, o);
+                real o[NOUT];
 #pragma unroll
-                for (int k = 0; k < 11; ++k) acc[k].add(o[k]);
+                for (int k = 0; k < NOUT; ++k) o[k] = real(0);
+                pair_force_vjp<real, SOLID>(d, r2, I, J, K, wb, o);
+#pragma unroll
+                for (int k = 0; k < NOUT; ++k) acc[k].add(o[k]);
+            } else if constexpr (GADJ) {
+                const real vj[3] = {cur.a.x, cur.a.y, cur.a.z};
+                const real Lj[9] = {cur.b.x, cur.b.y, cur.b.z, cur.b.w, cur.r0.x, cur.r0.y, cur.r0.z, cur.r0.w,
+                                    cur.r1.x};
+                real o[7] = {0, 0, 0, 0, 0, 0, 0};
+                pair_grad_vjp<real>(d, r2, I.v, vj, I.w, cur.a.w, rbi, Lj, K, o);
+#pragma unroll
+                for (int k = 0; k < 7; ++k) acc[k].add(o[k]);
             } else {
                 const real vj[3] = {cur.a.x, cur.a.y, cur.a.z};
                 real o[9];
@@ -737,10 +761,16 @@ void k_pairs(Params P, Grid g, PV<real> tg, const uint32_t *__restrict__ tidx, c
         cz.count[i] = ncen;
         cz.sum[i] = scen;
     } else if constexpr (ADJ) {
-        // accumulate the cotangents of x, v, omega, rho, p, c, e
-        real *out[11] = {B.x[0], B.x[1], B.x[2], B.v[0], B.v[1], B.v[2], B.w, B.rho, B.p, B.c, B.e};
+        // accumulate the cotangents of x, v, omega, rho, p, c, e (and S)
+        real *out[17] = {B.x[0], B.x[1], B.x[2], B.v[0], B.v[1], B.v[2], B.w, B.rho, B.p, B.c, B.e,
+                         B.S[0], B.S[1], B.S[2], B.S[3], B.S[4], B.S[5]};
 #pragma unroll
-        for (int k = 0; k < 11; ++k) out[k][i] = (real)((double)out[k][i] + acc[k].s);
+        for (int k = 0; k < NOUT; ++k) out[k][i] = (real)((double)out[k][i] + acc[k].s);
+    } else if constexpr (GADJ) {
+        // accumulate the cotangents of x, v, omega
+        real *out[7] = {B.x[0], B.x[1], B.x[2], B.v[0], B.v[1], B.v[2], B.w};
+#pragma unroll
+        for (int k = 0; k < 7; ++k) out[k][i] = (real)((double)out[k][i] + acc[k].s);
     } else {
 #pragma unroll
         for (int k = 0; k < NOUT; ++k) {
@@ -769,8 +799,24 @@ __global__ __launch_bounds__(kBlock) void k_stage_rbar(uint32_t n, RV<real> rb, 
         b.x = rb.hi[4][j];
         b.y = rb.hi[5][j];
     }
-    st.s0[rec_stride<real> * j] = a;
-    st.s1[rec_stride<real> * j] = b;
+    st.r0[rec_stride<real> * j] = a;
+    st.r1[rec_stride<real> * j] = b;
+}
+
+// GRADIENT reverse: the sources' velocity-gradient cotangents in vb (0..3),
+// r0 (4..7) and r1.x (8) (zeros when rb.Lhi[0] == NULL).
+template <typename real>
+__global__ __launch_bounds__(kBlock) void k_stage_lbar(uint32_t n, RV<real> rb, Stage<real> st)
+{
+    uint32_t j = blockIdx.x * kBlock + threadIdx.x;
+    if (j >= n) return;
+    real L[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) L[k] = rb.Lhi[0] ? rb.Lhi[k][j] : real(0);
+    typename Vec4<real>::type a = {L[0], L[1], L[2], L[3]}, b = {L[4], L[5], L[6], L[7]}, c = {L[8], 0, 0, 0};
+    st.vb[rec_stride<real> * j] = a;
+    st.r0[rec_stride<real> * j] = b;
+    st.r1[rec_stride<real> * j] = c;
 }
 
 // Candidates and hits of one pass, with the predicate of the pair kernel.
@@ -859,8 +905,8 @@ hipError_t go(const Params &P, const Grid &g, const sph_particles &tg, const uin
               const Census cz = Census{}, bool census_of_gradient = false, const sph_rates *rsrc = nullptr)
 {
     if (tg.n == 0) return hipSuccess;
-    constexpr bool ADJ = PASS == kPassAdjoint;
-    Stage<real> st = stage_view<real>(ws, sr.n, SOLID || ADJ);
+    constexpr bool ADJ = PASS == kPassAdjoint || PASS == kPassGradAdjoint;
+    Stage<real> st = stage_view<real>(ws, sr.n, SOLID, ADJ);
     uint32_t blocks = div_up(tg.n, kPairBlock);
     uint2 *plan = nullptr;
     uint32_t *nplan = nullptr;
@@ -874,7 +920,7 @@ hipError_t go(const Params &P, const Grid &g, const sph_particles &tg, const uin
     const uint64_t pmax = div_up(tg.n, kWave) + nrows;
     // (the workspace's key buffers hold 4 bytes for each of the sources->n
     // particles it was sized for)
-    if (!SOLID && PASS != SPH_PASS_GRADIENT && !census_of_gradient && self && !tidx &&
+    if (!SOLID && PASS != SPH_PASS_GRADIENT && PASS != kPassGradAdjoint && !census_of_gradient && self && !tidx &&
         pmax * sizeof(uint2) <= 4ull * sr.n) {
         plan = reinterpret_cast<uint2 *>(ws.keys[0]);
         nplan = ws.keys[1];
@@ -886,7 +932,11 @@ hipError_t go(const Params &P, const Grid &g, const sph_particles &tg, const uin
                                                                                     plan, nplan);
         if constexpr (ADJ) {
             const sph_rates none{};
-            k_stage_rbar<real><<<div_up(sr.n, kBlock), kBlock, 0, s>>>(sr.n, view<real>(rsrc ? *rsrc : none), st);
+            const RV<real> rs = view<real>(rsrc ? *rsrc : none);
+            if constexpr (PASS == kPassGradAdjoint)
+                k_stage_lbar<real><<<div_up(sr.n, kBlock), kBlock, 0, s>>>(sr.n, rs, st);
+            else
+                k_stage_rbar<real><<<div_up(sr.n, kBlock), kBlock, 0, s>>>(sr.n, rs, st);
         }
     }
     if (self)
@@ -958,15 +1008,29 @@ hipError_t launch_census(const Params &P, const Grid &g, int prec, int pass, con
     return go<float, kPassCensus, false>(P, g, tg, tidx, nt, sr, sstart, self, 1, none, nobar, ws, s, cz, grad);
 }
 
-hipError_t launch_interact_adjoint(const Params &P, const Grid &g, int prec, const sph_particles &tg,
+hipError_t launch_interact_adjoint(const Params &P, const Grid &g, int prec, int pass, const sph_particles &tg,
                                    const uint32_t *tidx, const uint32_t *nt, const sph_particles &sr,
                                    const uint32_t *sstart, bool self, const sph_rates &rbar_t,
                                    const sph_rates &rbar_s, const sph_adjoint &bar, const Workspace &ws,
                                    hipStream_t s)
 {
-    if (prec == SPH_FP64)
+    const bool solid = P.material == SPH_SOLID_J2;
+    if (prec == SPH_FP64) {
+        if (pass == SPH_PASS_GRADIENT)
+            return go<double, kPassGradAdjoint, false>(P, g, tg, tidx, nt, sr, sstart, self, 0, rbar_t, bar, ws, s,
+                                                       Census{}, false, &rbar_s);
+        if (solid)
+            return go<double, kPassAdjoint, true>(P, g, tg, tidx, nt, sr, sstart, self, 0, rbar_t, bar, ws, s,
+                                                  Census{}, false, &rbar_s);
         return go<double, kPassAdjoint, false>(P, g, tg, tidx, nt, sr, sstart, self, 0, rbar_t, bar, ws, s, Census{},
                                                false, &rbar_s);
+    }
+    if (pass == SPH_PASS_GRADIENT)
+        return go<float, kPassGradAdjoint, false>(P, g, tg, tidx, nt, sr, sstart, self, 0, rbar_t, bar, ws, s,
+                                                  Census{}, false, &rbar_s);
+    if (solid)
+        return go<float, kPassAdjoint, true>(P, g, tg, tidx, nt, sr, sstart, self, 0, rbar_t, bar, ws, s, Census{},
+                                             false, &rbar_s);
     return go<float, kPassAdjoint, false>(P, g, tg, tidx, nt, sr, sstart, self, 0, rbar_t, bar, ws, s, Census{},
                                           false, &rbar_s);
 }

@@ -227,15 +227,16 @@ __device__ inline void pair_force(const real d[3], real r2, const Part<real, SOL
     out[5] = real(0.5) * A * G * s1;
 }
 
-// Reverse mode of pair_force (fluid) with respect to the TARGET's inputs:
-// given cotangents wb[6] of the six terms, adds to g[11] the cotangents of
-// (x_i[3], v_i[3], omega_i, rho_i, p_i, c_i, e_i).  Every intermediate of
-// the forward evaluation is recomputed, then differentiated in reverse
-// order.  A pair with r = 0 contributes nothing.
-template <typename real>
-__device__ inline void pair_force_vjp(const real d[3], real r2, const Part<real, false> &I,
-                                      const Part<real, false> &J, const PairK<real> &K, const real wb[6],
-                                      real g[11])
+// Reverse mode of pair_force with respect to the TARGET's inputs: given
+// cotangents wb[6] of the six terms, adds to g the cotangents of
+// (x_i[3], v_i[3], omega_i, rho_i, p_i, c_i, e_i) and, for solids, of the
+// stored deviatoric stress S_i[6] (g[11..16]).  Every intermediate of the
+// forward evaluation is recomputed, then differentiated in reverse order.
+// A pair with r = 0 contributes nothing.
+template <typename real, bool SOLID>
+__device__ inline void pair_force_vjp(const real d[3], real r2, const Part<real, SOLID> &I,
+                                      const Part<real, SOLID> &J, const PairK<real> &K, const real wb[6],
+                                      real g[SOLID ? 17 : 11])
 {
     if (!(r2 > real(0))) return;
     // forward
@@ -257,20 +258,37 @@ __device__ inline void pair_force_vjp(const real d[3], real r2, const Part<real,
     const real pb = real(0.5) * (I.p + J.p);
     const real Z = rb * cb;
     const real Zinv = rcp<real>(Z);
-    const real du = K.half_beta * (I.p - J.p) * Zinv;
+    // solids: si = S_i d, sj = S_j d, P = p - d.S.d / r^2, Sd = si + sj
+    real si[3] = {0, 0, 0}, sj[3] = {0, 0, 0}, Sd[3] = {0, 0, 0};
+    real dsi = 0, dsj = 0, r2inv = 0, Pi = I.p, Pj = J.p;
+    if constexpr (SOLID) {
+        sym_mul<real>(I.S, d, si);
+        sym_mul<real>(J.S, d, sj);
+        r2inv = rinv * rinv;
+        dsi = d[0] * si[0] + d[1] * si[1] + d[2] * si[2];
+        dsj = d[0] * sj[0] + d[1] * sj[1] + d[2] * sj[2];
+        Pi = I.p - dsi * r2inv;
+        Pj = J.p - dsj * r2inv;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) Sd[a] = si[a] + sj[a];
+    }
+    const real du = K.half_beta * (Pi - Pj) * Zinv;
     const real ps = pb - (K.half_beta * Z * s1) * rinv;
     const real A = real(2) * I.w * J.w;
     const real Phi = rb * du * F;
     const real k1 = -A * ((Phi * du) * rinv + ps * G);
     const real ca = real(-0.5) * A * Phi;
+    const real kS = real(0.5) * A * G;
     const real sv2 = sv[0] * sv[0] + sv[1] * sv[1] + sv[2] * sv[2];
     const real vs2 = real(0.25) * sv2 + du * (s2 * rinv + du);
     const real Es = real(0.5) * (I.e + J.e) + real(0.5) * vs2;
     const real vsd = real(0.5) * s2 + du * r;
-    const real tv = ps * G * vsd;
+    const real sdsv = Sd[0] * sv[0] + Sd[1] * sv[1] + Sd[2] * sv[2];
+    const real sdd = Sd[0] * d[0] + Sd[1] * d[1] + Sd[2] * d[2];
+    const real tv = ps * G * vsd - (SOLID ? real(0.5) * G * (real(0.5) * sdsv + du * rinv * sdd) : real(0));
     // reverse
     real bA = 0, bG = 0, bs1 = 0, bs2 = 0, bPhi = 0, bdu = 0, bps = 0, br = 0, brinv = 0, bF = 0;
-    real bsv[3] = {0, 0, 0}, bd[3] = {0, 0, 0};
+    real bsv[3] = {0, 0, 0}, bd[3] = {0, 0, 0}, bSd[3] = {0, 0, 0};
     // o5 = A G s1 / 2
     bA += real(0.5) * wb[5] * G * s1;
     bG += real(0.5) * wb[5] * A * s1;
@@ -280,10 +298,18 @@ __device__ inline void pair_force_vjp(const real d[3], real r2, const Part<real,
     bPhi -= wb[4] * A * Es;
     const real bEs = -wb[4] * A * Phi;
     const real btv = -wb[4] * A;
-    // tv = ps G vsd
+    // tv = ps G vsd - (G / 2) (sdsv / 2 + du rinv sdd)
     bps += btv * G * vsd;
     bG += btv * ps * vsd;
     const real bvsd = btv * ps * G;
+    real bsdsv = 0, bsdd = 0;
+    if constexpr (SOLID) {
+        bG -= btv * real(0.5) * (real(0.5) * sdsv + du * rinv * sdd);
+        bsdsv -= btv * real(0.25) * G;
+        bdu -= btv * real(0.5) * G * rinv * sdd;
+        brinv -= btv * real(0.5) * G * du * sdd;
+        bsdd -= btv * real(0.5) * G * du * rinv;
+    }
     // vsd = s2 / 2 + du r
     bs2 += real(0.5) * bvsd;
     bdu += bvsd * r;
@@ -296,14 +322,29 @@ __device__ inline void pair_force_vjp(const real d[3], real r2, const Part<real,
     bdu += bvs2 * (s2 * rinv + real(2) * du);
     bs2 += bvs2 * du * rinv;
     brinv += bvs2 * du * s2;
-    // o_{1+a} = ca sv_a + k1 d_a
-    real bca = 0, bk1 = 0;
+    // o_{1+a} = ca sv_a + k1 d_a + kS Sd_a
+    real bca = 0, bk1 = 0, bkS = 0;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         bca += wb[1 + a] * sv[a];
         bsv[a] += wb[1 + a] * ca + real(2) * bsv2 * sv[a];
         bk1 += wb[1 + a] * d[a];
         bd[a] += wb[1 + a] * k1;
+        if constexpr (SOLID) {
+            bkS += wb[1 + a] * Sd[a];
+            bSd[a] += wb[1 + a] * kS;
+        }
+    }
+    if constexpr (SOLID) {
+        // kS = A G / 2; sdsv = Sd . sv; sdd = Sd . d
+        bA += real(0.5) * G * bkS;
+        bG += real(0.5) * A * bkS;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            bSd[a] += bsdsv * sv[a] + bsdd * d[a];
+            bsv[a] += bsdsv * Sd[a];
+            bd[a] += bsdd * Sd[a];
+        }
     }
     // k1 = -A (Phi du rinv + ps G)
     bA -= bk1 * ((Phi * du) * rinv + ps * G);
@@ -326,9 +367,40 @@ __device__ inline void pair_force_vjp(const real d[3], real r2, const Part<real,
     real bZ = -bps * K.half_beta * s1 * rinv;
     bs1 -= bps * K.half_beta * Z * rinv;
     brinv -= bps * K.half_beta * Z * s1;
-    // du = hb (p_i - p_j) / Z
-    g[8] += bdu * K.half_beta * Zinv;
+    // du = hb (P_i - P_j) / Z
+    const real bPi = bdu * K.half_beta * Zinv;
+    const real bPj = -bPi;
     bZ -= bdu * du * Zinv;
+    // P_i = p_i - dsi / r^2 (fluids: P_i = p_i)
+    g[8] += bPi;
+    if constexpr (SOLID) {
+        const real bdsi = -bPi * r2inv, bdsj = -bPj * r2inv;
+        const real br2inv = -(bPi * dsi + bPj * dsj);
+        brinv += real(2) * rinv * br2inv;
+        // dsi = d.S_i d, dsj = d.S_j d; si = S_i d, sj = S_j d (S symmetric)
+        real bsi[3], bsj[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            bsi[a] = bSd[a];
+            bsj[a] = bSd[a];
+            bd[a] += real(2) * (bdsi * si[a] + bdsj * sj[a]);
+        }
+        real t[3];
+        sym_mul<real>(I.S, bsi, t);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) bd[a] += t[a];
+        sym_mul<real>(J.S, bsj, t);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) bd[a] += t[a];
+        // stored (xx yy zz xy xz yz): d(d.S d) = d_a d_b (off-diagonals twice),
+        // d(S d)_a / dS_ab = d_b
+        g[11] += bdsi * d[0] * d[0] + bsi[0] * d[0];
+        g[12] += bdsi * d[1] * d[1] + bsi[1] * d[1];
+        g[13] += bdsi * d[2] * d[2] + bsi[2] * d[2];
+        g[14] += real(2) * bdsi * d[0] * d[1] + bsi[0] * d[1] + bsi[1] * d[0];
+        g[15] += real(2) * bdsi * d[0] * d[2] + bsi[0] * d[2] + bsi[2] * d[0];
+        g[16] += real(2) * bdsi * d[1] * d[2] + bsi[1] * d[2] + bsi[2] * d[1];
+    }
     // Z = rb cb ; rb, cb, pb are means
     brb += bZ * cb;
     const real bcb = bZ * rb;
@@ -350,6 +422,54 @@ __device__ inline void pair_force_vjp(const real d[3], real r2, const Part<real,
     const real br2 = real(0.5) * rinv * (br - brinv * rinv * rinv);
 #pragma unroll
     for (int a = 0; a < 3; ++a) g[a] -= bd[a] + real(2) * br2 * d[a];
+}
+
+// Reverse of the GRADIENT loop for one pair (target i, source j).  With
+// g = G(r) d (d = x_j - x_i, G = F / r), dv = v_j - v_i, the loop puts
+// w_j dv (x) g into L_i and, from the mirrored pair, w_i dv (x) g into L_j.
+// Given the cotangents Lbar_i and Lbar_j (row-major 3 x 3) and
+// M = w_j Lbar_i + w_i Lbar_j, the pair's part of the target's cotangents:
+//   vbar_i -= M g,  wbar_i += dv . Lbar_j g,
+//   xbar_i -= G M^T dv + ((F' - G) / r^2) (dv . M d) d.
+// out: (x_i[3], v_i[3], omega_i).  A pair with r = 0 contributes nothing.
+template <typename real>
+__device__ inline void pair_grad_vjp(const real d[3], real r2, const real vi[3], const real vj[3], real wi, real wj,
+                                     const real Li[9], const real Lj[9], const PairK<real> &K, real out[7])
+{
+    if (!(r2 > real(0))) return;
+    real r, rinv;
+    inv_len<real>(r2, r, rinv);
+    const real q = r * K.hinv;
+    const real tq = max(real(2) - q, real(0));
+    const bool inner = q < real(1);
+    const real f = inner ? q * (real(3) - real(2.25) * q) : real(0.75) * tq * tq;
+    const real fp = inner ? real(3) - real(4.5) * q : real(-1.5) * tq;
+    const real F = K.Fc * f;
+    const real Fr = K.Fc * fp * K.hinv;   // dF/dr
+    const real G = F * rinv;
+    const real gv[3] = {G * d[0], G * d[1], G * d[2]};
+    const real dv[3] = {vj[0] - vi[0], vj[1] - vi[1], vj[2] - vi[2]};
+    real Mg[3], Mtdv[3] = {0, 0, 0}, Ljg[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        Mg[a] = 0;
+        Ljg[a] = 0;
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            const real M = wj * Li[3 * a + b] + wi * Lj[3 * a + b];
+            Mg[a] += M * gv[b];
+            Mtdv[b] += M * dv[a];
+            Ljg[a] += Lj[3 * a + b] * gv[b];
+        }
+    }
+    const real s = Mtdv[0] * d[0] + Mtdv[1] * d[1] + Mtdv[2] * d[2];
+    const real k = (Fr - G) * rinv * rinv * s;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        out[a] -= G * Mtdv[a] + k * d[a];
+        out[3 + a] -= Mg[a];
+    }
+    out[6] += dv[0] * Ljg[0] + dv[1] * Ljg[1] + dv[2] * Ljg[2];
 }
 
 // GRADIENT terms: L_ab = w_j (v_j - v_i)_a g_b.

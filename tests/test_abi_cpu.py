@@ -226,7 +226,7 @@ def test_passes_over_one_array_need_one_size():
         full.x[d] = full.v[d] = FAKE
     for f in ("m", "omega", "E", "rho", "p", "c", "e"):
         setattr(full, f, FAKE)
-    assert lib.sph_interact_adjoint(C.byref(_params()), C.byref(g), C.byref(t), None, None, C.byref(s), cells,
+    assert lib.sph_interact_adjoint(C.byref(_params()), C.byref(g), 0, C.byref(t), None, None, C.byref(s), cells,
                                     C.byref(r), C.byref(r), C.byref(full), FAKE, 1 << 40, None) == L.SPH_ERR_ARG
 
 
@@ -258,11 +258,30 @@ def test_integrate_and_adjoint_reject_bad_arguments():
     cl = L.SphCells(FAKE, 64, 0)
 
     def iadj(params, t, s, rt, rs, b, tidx=None, nt=None):
-        return lib.sph_interact_adjoint(C.byref(params), C.byref(_grid()), C.byref(t), tidx, nt, C.byref(s), cl,
+        return lib.sph_interact_adjoint(C.byref(params), C.byref(_grid()), 0, C.byref(t), tidx, nt, C.byref(s), cl,
                                         None if rt is None else C.byref(rt), None if rs is None else C.byref(rs),
                                         C.byref(b), FAKE, 1 << 40, None)
 
-    assert iadj(ps, p, p, r, r, bar) == L.SPH_ERR_UNSUPPORTED
+    # the solid reverse needs the stress fields and takes the linear EOS only
+    full0 = L.SphAdjoint()
+    for d in range(3):
+        full0.x[d] = full0.v[d] = FAKE
+    for f in ("m", "omega", "E", "rho", "p", "c", "e"):
+        setattr(full0, f, FAKE)
+    assert iadj(ps, p, p, r, r, full0) == L.SPH_ERR_ARG
+    assert "S[0]" in _last()
+    pm = _params()
+    pm.material, pm.eos, pm.c0, pm.G, pm.mg_s = L.SPH_SOLID_J2, L.SPH_EOS_MIE_GRUNEISEN, 5000.0, 1e9, 1.3
+    assert iadj(pm, p, p, r, r, full0) == L.SPH_ERR_UNSUPPORTED
+    assert lib.sph_integrate_adjoint(C.byref(pm), L.SPH_STAGE_MOTION, C.byref(p), C.byref(r), FAKE, C.byref(full0),
+                                     C.byref(r), None, None, 0, None) == L.SPH_ERR_UNSUPPORTED
+    # the stress stage's reverse is for solids, and needs the stress cotangents
+    assert lib.sph_integrate_adjoint(C.byref(_params()), L.SPH_STAGE_STRESS, C.byref(p), C.byref(r), FAKE,
+                                     C.byref(full0), C.byref(r), None, None, 0, None) == L.SPH_ERR_ARG
+    # the GRADIENT reverse reads the velocity-gradient cotangents
+    assert lib.sph_interact_adjoint(C.byref(ps), C.byref(_grid()), 1, C.byref(p), None, None, C.byref(p), cl,
+                                    C.byref(r), None, C.byref(full0), FAKE, 1 << 40, None) == L.SPH_ERR_ARG
+    assert "Lhi[0]" in _last()
     full = L.SphAdjoint()
     for d in range(3):
         full.x[d] = full.v[d] = FAKE

@@ -80,3 +80,51 @@ def test_displacement_gradient_matches_central_differences():
     eps = 1e-4 * c0
     fdc = (Jof(w.v, c0 + eps) - Jof(w.v, c0 - eps)) / (2 * eps)
     assert fdc == pytest.approx(gc, rel=1e-5, abs=1e-14)
+
+
+def solid_block(seed, s_axial=0.0, rate=0.0, n_side=5):
+    """A free J2 block of the cylinder's metal; with s_axial near Y0 and a
+    stretch it yields (hardening H = E / 100)."""
+    w = S.solid_block(n_side, seed=seed, vz=0.0, s_sigma=2e7, s_axial=s_axial, stretch_rate=rate)
+    w.params = dict(w.params, wall_mask=0)
+    return w
+
+
+@pytest.mark.parametrize("plastic", [False, True])
+def test_dense_solid_forward_matches_c_oracle(plastic):
+    w = solid_block(90 + int(plastic), 270e6 if plastic else 0.0, 2e4 if plastic else 0.0)
+    dt, nsteps = 2e-8, 4
+    s = cpu.State.from_workload(w)
+    cpu.run(w.params, w.grid, s, nsteps, fixed_dt=dt)
+    ref = s.by_id()
+    got = torch_ref.solid_final_state(w, dt, nsteps)
+    for f in ("x", "v", "m", "w", "E", "S", "ep"):
+        a = getattr(ref, f)
+        err = np.abs(got[f] - a).max() / max(np.abs(a).max(), 1e-300)
+        assert err < 1e-13, (f, err)
+    assert ((ref.ep > 0).mean() > 0.8) == plastic
+
+
+@pytest.mark.parametrize("plastic", [False, True])
+def test_solid_reverse_mode_matches_central_differences(plastic):
+    w = solid_block(92 + int(plastic), 270e6 if plastic else 0.0, 2e4 if plastic else 0.0, n_side=4)
+    dt, nsteps = 2e-8, 3
+    J, gv, gS = torch_ref.solid_gradient(w, dt, nsteps)
+    t = {k: torch.tensor(getattr(w, k)) for k in ("x", "m", "omega", "eps_p")}
+    e0 = torch.tensor(w.E - 0.5 * (w.v * w.v).sum(1))
+
+    def Jof(v, Sx):
+        with torch.no_grad():
+            return float(torch_ref.solid_kinetic_energy_after(t["x"], torch.tensor(v), t["m"], t["omega"], e0,
+                                                              torch.tensor(Sx), t["eps_p"], w.params, dt, nsteps))
+
+    rng = np.random.default_rng(94)
+    for _ in range(3):
+        d = rng.normal(size=w.v.shape)
+        eps = 1e-4
+        fd = (Jof(w.v + eps * d, w.S) - Jof(w.v - eps * d, w.S)) / (2 * eps)
+        assert fd == pytest.approx(float((gv * d).sum()), rel=1e-7)
+        dS = rng.normal(size=w.S.shape)
+        epsS = 1e2     # Pa, against stresses of 1e7 - 1e8
+        fd = (Jof(w.v, w.S + epsS * dS) - Jof(w.v, w.S - epsS * dS)) / (2 * epsS)
+        assert fd == pytest.approx(float((gS * dS).sum()), rel=1e-6)
