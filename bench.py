@@ -97,43 +97,62 @@ def recorded_traffic(prec: int):
     return int(v) if v else None
 
 
-def time_form(wl, prec, steps, warmup):
+def time_forms(wl, plan, warmup):
+    """Time each (prec, steps) of `plan` in order on its own Sim of `wl`.
+    Every Sim is built and warmed up (`warmup` untimed steps) before the
+    first timed step, and the work counts are taken after the last, so the
+    timed runs follow one another with no host work between them and the
+    GPU stays at its sustained clocks (it drops them within milliseconds of
+    going idle, and a short timed run would otherwise measure the ramp)."""
     import torch
     from paper_2310_03596_amd.sim import Sim
 
-    sim = Sim(wl, prec)
-    for _ in range(warmup):
-        sim.step()
+    sims = {prec: Sim(wl, prec) for prec, _ in plan}
+    for prec, _ in plan:
+        for _ in range(warmup):
+            sims[prec].step()
     torch.cuda.synchronize()
-    # HIP events bracket the FORCE launch of every EVENT_EVERY-th timed step
-    # (an event pair costs a few microseconds of queue time, so timing every
-    # launch would slow the steps being timed)
-    sampled = list(range(0, steps, EVENT_EVERY))
-    evs = {k: (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for k in sampled}
-    t0 = time.perf_counter()
-    for k in range(steps):
-        sim.step(force_events=evs.get(k))
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    force_ms = sum(a.elapsed_time(b) for a, b in evs.values()) / max(len(evs), 1)
-    cand, pairs = sim.count_pairs()
-    flops = cand * FLOPS_CAND[prec] + pairs * FLOPS_PAIR[prec]
-    return {
-        "value": wl.n * steps / wall,
-        "ms_per_step": 1e3 * wall / steps,
-        "force_ms": force_ms,
-        "candidates": cand,
-        "pairs": pairs,
-        "flops_per_launch": flops,
-        "force_tflops": flops / (force_ms * 1e-3) / 1e12,
-        "pair_evals_per_s": pairs / (force_ms * 1e-3),
-        "candidates_per_s": cand / (force_ms * 1e-3),
-        "diag": sim.diagnostics().tolist(),
-    }
+    timed = {}
+    for prec, steps in plan:
+        sim = sims[prec]
+        # HIP events bracket the FORCE launch of every EVENT_EVERY-th timed step
+        # (an event pair costs a few microseconds of queue time, so timing every
+        # launch would slow the steps being timed)
+        sampled = list(range(0, steps, EVENT_EVERY))
+        evs = {k: (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for k in sampled}
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(steps):
+            sim.step(force_events=evs.get(k))
+        torch.cuda.synchronize()
+        timed[prec] = (time.perf_counter() - t0, evs)
+    out = {}
+    for prec, steps in plan:
+        sim = sims[prec]
+        wall, evs = timed[prec]
+        force_ms = sum(a.elapsed_time(b) for a, b in evs.values()) / max(len(evs), 1)
+        cand, pairs = sim.count_pairs()
+        flops = cand * FLOPS_CAND[prec] + pairs * FLOPS_PAIR[prec]
+        out[prec] = {
+            "value": wl.n * steps / wall,
+            "ms_per_step": 1e3 * wall / steps,
+            "force_ms": force_ms,
+            "candidates": cand,
+            "pairs": pairs,
+            "flops_per_launch": flops,
+            "force_tflops": flops / (force_ms * 1e-3) / 1e12,
+            "pair_evals_per_s": pairs / (force_ms * 1e-3),
+            "candidates_per_s": cand / (force_ms * 1e-3),
+            "diag": sim.diagnostics().tolist(),
+        }
+    del sims
+    torch.cuda.empty_cache()
+    return out
 
 
 def other_workloads_leg():
-    """Step throughput of the 8,000-particle cube (10 steps), the
+    """Step throughput of the 8,000-particle cube (10 steps, launched one by
+    one and replayed from a captured graph), the
     3,987,920-particle elastic-plastic cylinder (two interaction loops per
     step: GRADIENT, stress stage, FORCE; 20 steps) and the 6,668,204-particle
     hypervelocity impact (same loops, Mie-Gruneisen EOS; 20 steps from the
@@ -142,6 +161,8 @@ def other_workloads_leg():
 
     import sph_synth as S
     from paper_2310_03596_amd.sim import Sim
+
+    from paper_2310_03596_amd.graph import StepGraph
 
     out = {}
     for name, make, steps in (("cube_8000", S.c1_cube, 10), ("cylinder_3987920", S.c3_cylinder, 20),
@@ -160,6 +181,18 @@ def other_workloads_leg():
             wall = time.perf_counter() - t0
             out[name][tag] = {"steps": steps, "ms_per_step": 1e3 * wall / steps,
                               "particle_updates_per_s": wl.n * steps / wall}
+            if name == "cube_8000":
+                # the launch-bound cube again, its steps replayed from one captured graph
+                g = StepGraph(sim, steps=steps)
+                g.replay()
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                g.replay()
+                torch.cuda.synchronize()
+                wall = time.perf_counter() - t0
+                out[name][tag]["graph_ms_per_step"] = 1e3 * wall / steps
+                out[name][tag]["graph_particle_updates_per_s"] = wl.n * steps / wall
+                del g
             del sim
         del wl
         torch.cuda.empty_cache()
@@ -400,10 +433,9 @@ def main():
     wl = S.c2_column()
     out = {}
     res = {}
-    # The other GPU legs run first and the column's two forms last (the plain
-    # FP64 form, then the FP32 form, the headline): a GPU that has just been
-    # handed a job runs its first milliseconds below its sustained clocks, and
-    # a short timed run of the headline would otherwise measure that ramp.
+    # The other GPU legs run first and the column's two forms last, back to
+    # back (the plain FP64 form, then the FP32 form, the headline; see
+    # time_forms).
     legs = {}
     if not args.no_share:
         legs["other_workloads"] = other_workloads_leg()
@@ -417,10 +449,12 @@ def main():
         legs["balance_round"] = balance_leg()
         legs["balance_types_round"] = balance_leg(types=True)
         legs["decomposition"] = decomposition_leg()
+    plan = []
     if args.only in ("fp64", "both"):
-        res[0] = time_form(wl, 0, args.fp64_steps or args.steps, args.warmup)
+        plan.append((0, args.fp64_steps or args.steps))
     if args.only in ("fp32", "both"):
-        res[1] = time_form(wl, 1, args.steps, args.warmup)
+        plan.append((1, args.steps))
+    res = time_forms(wl, plan, args.warmup)
     main_prec = 1 if 1 in res else 0
     r = res[main_prec]
     out.update({

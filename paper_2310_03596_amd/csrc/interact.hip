@@ -661,7 +661,7 @@ void k_pairs(Params P, Grid g, PV<real> tg, const uint32_t *__restrict__ tidx, c
                 // the page in the group's filter frame, then far sentinels up to
                 // kPage + kSub so that every read below stays in the array and
                 // nothing past the page can pass a test
-                if constexpr (SPLIT) {
+                {
                     // every lane's records of the page in flight at once, then
                     // staged (one memory round trip per page instead of three)
                     constexpr int kIt = (kPage + kSub + kWave - 1) / kWave;
@@ -677,31 +677,17 @@ void k_pairs(Params P, Grid g, PV<real> tg, const uint32_t *__restrict__ tidx, c
                         if (u >= (uint32_t)(kPage + kSub)) continue;
                         float4 rec;
                         if (u < len) {
-                            rec.x = (sp[it].w - gx0f) * T.Lf + sp[it].x;
-                            rec.y = ddy + sp[it].y;
-                            rec.z = ddz + sp[it].z;
+                            if constexpr (SPLIT) {
+                                rec.x = (sp[it].w - gx0f) * T.Lf + sp[it].x;
+                                rec.y = ddy + sp[it].y;
+                                rec.z = ddz + sp[it].z;
+                            } else {
+                                rec.x = (float)(sp[it].x - corner[0]);
+                                rec.y = (float)(sp[it].y - corner[1]);
+                                rec.z = (float)(sp[it].z - corner[2]);
+                            }
                             rec.w = rec.x * rec.x + rec.y * rec.y + rec.z * rec.z;
                             rec.x *= 2.0f;
-                            rec.y *= 2.0f;
-                            rec.z *= 2.0f;
-                        } else {
-                            rec.x = rec.y = rec.z = 0.0f;
-                            rec.w = kFar;
-                        }
-                        stage[wave][u] = rec;
-                    }
-                } else {
-                    // FP64 records (32 bytes): one in flight per lane, so that the
-                    // pass keeps its three wavefronts per SIMD
-                    for (uint32_t u = (uint32_t)lane; u < (uint32_t)(kPage + kSub); u += kWave) {
-                        float4 rec;
-                        if (u < len) {
-                            const v4 sp = src.pos[pb + u];
-                            rec.x = (float)(sp.x - corner[0]);
-                            rec.y = (float)(sp.y - corner[1]);
-                            rec.z = (float)(sp.z - corner[2]);
-                            rec.w = rec.x * rec.x + rec.y * rec.y + rec.z * rec.z;
-                            rec.x *= 2.0f;   // staged as (2q, |q|^2)
                             rec.y *= 2.0f;
                             rec.z *= 2.0f;
                         } else {
