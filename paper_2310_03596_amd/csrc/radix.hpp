@@ -124,7 +124,11 @@ __global__ __launch_bounds__(kBlock) void k_upsweep(const uint32_t *__restrict__
     // LDS atomics do not serialise on one address).
     const int lane = threadIdx.x & (kWave - 1);
     constexpr int IT = sort_items<D>;
-    const uint32_t base = blockIdx.x * (kBlock * IT);
+    // Consecutive tiles run on one XCD: a digit's counts of 32 consecutive
+    // tiles share one 128-byte line of hist, which is then written (here)
+    // and read (in the scatter) through a single L2 instead of eight.
+    const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
+    const uint32_t base = tile * (kBlock * IT);
     uint32_t keyv[IT];
 #pragma unroll
     for (int it = 0; it < IT; ++it) {
@@ -144,7 +148,7 @@ __global__ __launch_bounds__(kBlock) void k_upsweep(const uint32_t *__restrict__
         if (valid && head) atomicAdd(&h[d], (uint32_t)(next - lane));
     }
     __syncthreads();
-    for (int b = threadIdx.x; b < BINS; b += kBlock) hist[(size_t)b * tiles + blockIdx.x] = h[b];
+    for (int b = threadIdx.x; b < BINS; b += kBlock) hist[(size_t)b * tiles + tile] = h[b];
 }
 
 // One workgroup per digit: exclusive scan of that digit's tile counts.
@@ -175,7 +179,11 @@ __global__ __launch_bounds__(kBlock) void k_downsweep(const uint32_t *__restrict
     // digit-base bookkeeping below and each other (a load issued inside the
     // loop would wait out a full round trip behind every barrier)
     constexpr int IT = sort_items<D>;
-    const uint32_t base = blockIdx.x * (kBlock * IT);
+    // the tile order of the histogram pass (same XCD for consecutive tiles,
+    // so the runs they write side by side in each digit's range fill whole
+    // lines in one L2)
+    const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
+    const uint32_t base = tile * (kBlock * IT);
     uint32_t keyv[IT], valv[IT];
 #pragma unroll
     for (int it = 0; it < IT; ++it) {
@@ -197,7 +205,7 @@ __global__ __launch_bounds__(kBlock) void k_downsweep(const uint32_t *__restrict
 #pragma unroll
     for (int k = 0; k < PT; ++k) {
         const int d = tid * PT + k;
-        dbase[d] = ex + loc[k] + hist[(size_t)d * tiles + blockIdx.x];
+        dbase[d] = ex + loc[k] + hist[(size_t)d * tiles + tile];
         run[d] = 0;
 #pragma unroll
         for (int w = 0; w < NW; ++w) cnt[w][d] = 0;
