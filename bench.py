@@ -254,26 +254,38 @@ def share_leg(reps=5):
         sp = SharePass(loc, rem, 1)
         sp.run()
         torch.cuda.synchronize()
-        ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
-        t_ll = t_lr = 0.0
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
+        t_b = t_ll = t_lr = t_rs = 0.0
         t0 = time.perf_counter()
         for _ in range(reps):
-            sp.build()
+            ev[0].record()
+            sp.build()          # both arrays from the generator's order
+            ev[1].record()
             sp.mark()
             sp.pack()
-            ev[0].record()
-            sp.interact_local()
-            ev[1].record()
-            sp.interact_remote()
             ev[2].record()
+            sp.interact_local()
+            ev[3].record()
+            sp.interact_remote()
+            ev[4].record()
             torch.cuda.synchronize()
-            t_ll += ev[0].elapsed_time(ev[1])
-            t_lr += ev[1].elapsed_time(ev[2])
+            t_b += ev[0].elapsed_time(ev[1])
+            t_ll += ev[2].elapsed_time(ev[3])
+            t_lr += ev[3].elapsed_time(ev[4])
         wall = (time.perf_counter() - t0) / reps
         nb = int(sp.nb.cpu()[0])
+        # step a as at every step of a run: both arrays re-sorted from the
+        # order the previous sort left them in
+        for _ in range(reps):
+            ev[0].record()
+            sp.resort()
+            ev[1].record()
+            torch.cuda.synchronize()
+            t_rs += ev[0].elapsed_time(ev[1])
         out[layout] = {"local": loc.n, "remote": rem.n, "boundary": nb, "pass_set_ms": 1e3 * wall,
                        "local_particle_updates_per_s": loc.n / wall, "local_local_ms": t_ll / reps,
-                       "local_remote_ms": t_lr / reps}
+                       "local_remote_ms": t_lr / reps, "build_ms_from_generator_order": t_b / reps,
+                       "build_ms_resort": t_rs / reps}
         del sp
         torch.cuda.empty_cache()
     return out

@@ -87,10 +87,20 @@ __global__ __launch_bounds__(kBlock) void k_eos_adj(Params P, PV<real> s, AV<rea
     uint32_t i = blockIdx.x * kBlock + threadIdx.x;
     double dc0 = 0.0;
     if (i < s.n) {
+        // every input is read before the first write (bar could alias s as
+        // far as the compiler knows, and a read issued after a write would
+        // wait out the write's round trip)
         const double m = (double)s.m[i], w = (double)s.w[i];
-        const double rho = m / w;
         const double bp = (double)bar.p[i], bc = (double)bar.c[i], be = (double)bar.e[i];
         double brho = (double)bar.rho[i];
+        const double bm = (double)bar.m[i], bw = (double)bar.w[i], bE = (double)bar.E[i];
+        double vv[3], bv[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            vv[a] = (double)s.v[a][i];
+            bv[a] = (double)bar.v[a][i];
+        }
+        const double rho = m / w;
         if (P.material == SPH_FLUID_TAIT) {
             const double sr = rho / P.rho0;
             double s_gam, s_half;
@@ -102,11 +112,11 @@ __global__ __launch_bounds__(kBlock) void k_eos_adj(Params P, PV<real> s, AV<rea
         } else {
             brho += bp * P.K / P.rho0;
         }
-        bar.m[i] = (real)((double)bar.m[i] + brho / w);
-        bar.w[i] = (real)((double)bar.w[i] - brho * rho / w);
-        bar.E[i] = (real)((double)bar.E[i] + be);
+        bar.m[i] = (real)(bm + brho / w);
+        bar.w[i] = (real)(bw - brho * rho / w);
+        bar.E[i] = (real)(bE + be);
 #pragma unroll
-        for (int a = 0; a < 3; ++a) bar.v[a][i] = (real)((double)bar.v[a][i] - be * (double)s.v[a][i]);
+        for (int a = 0; a < 3; ++a) bar.v[a][i] = (real)(bv[a] - be * vv[a]);
         bar.rho[i] = real(0);
         bar.p[i] = real(0);
         bar.c[i] = real(0);
@@ -252,18 +262,32 @@ __global__ __launch_bounds__(kBlock) void k_permute(uint32_t n, const uint32_t *
     uint32_t k = blockIdx.x * kBlock + threadIdx.x;
     if (k >= n) return;
     uint32_t d = perm[k];
+    // every cotangent is read before the first write (in and out could
+    // alias as far as the compiler knows, and a read issued after a write
+    // would wait out the write's round trip)
+    real x[3] = {0, 0, 0}, v[3] = {0, 0, 0}, S[6] = {0, 0, 0, 0, 0, 0};
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        if (in.x[a]) out.x[a][d] = in.x[a][k];
-        if (in.v[a]) out.v[a][d] = in.v[a][k];
+        if (in.x[a]) x[a] = in.x[a][k];
+        if (in.v[a]) v[a] = in.v[a][k];
     }
-    if (in.m) out.m[d] = in.m[k];
-    if (in.w) out.w[d] = in.w[k];
-    if (in.E) out.E[d] = in.E[k];
+    const real m = in.m ? in.m[k] : real(0), w = in.w ? in.w[k] : real(0), E = in.E ? in.E[k] : real(0);
 #pragma unroll
     for (int q = 0; q < 6; ++q)
-        if (in.S[q]) out.S[q][d] = in.S[q][k];
-    if (in.ep) out.ep[d] = in.ep[k];
+        if (in.S[q]) S[q] = in.S[q][k];
+    const real ep = in.ep ? in.ep[k] : real(0);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        if (in.x[a]) out.x[a][d] = x[a];
+        if (in.v[a]) out.v[a][d] = v[a];
+    }
+    if (in.m) out.m[d] = m;
+    if (in.w) out.w[d] = w;
+    if (in.E) out.E[d] = E;
+#pragma unroll
+    for (int q = 0; q < 6; ++q)
+        if (in.S[q]) out.S[q][d] = S[q];
+    if (in.ep) out.ep[d] = ep;
 }
 
 template <typename real>

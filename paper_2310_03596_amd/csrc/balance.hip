@@ -171,13 +171,29 @@ __global__ __launch_bounds__(kBlock) void k_select(uint32_t n, const uint32_t *_
     if (t == 0) *k_out = k;
 }
 
+// A field of both selected particles, read before any write (the two
+// arrays could alias as far as the compiler knows, and a read issued after a
+// write would wait out the write's round trip); absent fields stay absent.
 template <typename T>
-__device__ inline void swap_at(T *a, uint32_t i, T *b, uint32_t j)
+struct FieldPair {
+    T a, b;
+};
+template <typename T>
+__device__ inline FieldPair<T> read_pair(const T *a, uint32_t i, const T *b, uint32_t j)
+{
+    FieldPair<T> r{T(0), T(0)};
+    if (a && b) {
+        r.a = a[i];
+        r.b = b[j];
+    }
+    return r;
+}
+template <typename T>
+__device__ inline void write_swapped(T *a, uint32_t i, T *b, uint32_t j, const FieldPair<T> &q)
 {
     if (a && b) {
-        const T t = a[i];
-        a[i] = b[j];
-        b[j] = t;
+        a[i] = q.b;
+        b[j] = q.a;
     }
 }
 
@@ -193,24 +209,41 @@ __global__ __launch_bounds__(kBlock) void k_swap(PV<real> a, const uint32_t *__r
     if (t >= k) return;
     const uint32_t i = sel_a[t], j = sel_b[t];
     if (i >= a.n || j >= b.n) return;   // out-of-range selections are ignored
+    FieldPair<double> x[3];
+    FieldPair<float> off[3];
+    FieldPair<real> v[3], S[6];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-        swap_at(a.x[d], i, b.x[d], j);
-        swap_at(a.off[d], i, b.off[d], j);
-        swap_at(a.v[d], i, b.v[d], j);
+        x[d] = read_pair(a.x[d], i, b.x[d], j);
+        off[d] = read_pair(a.off[d], i, b.off[d], j);
+        v[d] = read_pair(a.v[d], i, b.v[d], j);
     }
-    swap_at(a.hash, i, b.hash, j);
-    swap_at(a.id, i, b.id, j);
-    swap_at(a.m, i, b.m, j);
-    swap_at(a.w, i, b.w, j);
-    swap_at(a.rho, i, b.rho, j);
-    swap_at(a.p, i, b.p, j);
-    swap_at(a.c, i, b.c, j);
-    swap_at(a.e, i, b.e, j);
-    swap_at(a.E, i, b.E, j);
+    const FieldPair<uint32_t> hash = read_pair(a.hash, i, b.hash, j), id = read_pair(a.id, i, b.id, j);
+    const FieldPair<real> m = read_pair(a.m, i, b.m, j), w = read_pair(a.w, i, b.w, j);
+    const FieldPair<real> rho = read_pair(a.rho, i, b.rho, j), p = read_pair(a.p, i, b.p, j);
+    const FieldPair<real> c = read_pair(a.c, i, b.c, j), e = read_pair(a.e, i, b.e, j);
+    const FieldPair<double> E = read_pair(a.E, i, b.E, j);
 #pragma unroll
-    for (int q = 0; q < 6; ++q) swap_at(a.S[q], i, b.S[q], j);
-    swap_at(a.ep, i, b.ep, j);
+    for (int q = 0; q < 6; ++q) S[q] = read_pair(a.S[q], i, b.S[q], j);
+    const FieldPair<real> ep = read_pair(a.ep, i, b.ep, j);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        write_swapped(a.x[d], i, b.x[d], j, x[d]);
+        write_swapped(a.off[d], i, b.off[d], j, off[d]);
+        write_swapped(a.v[d], i, b.v[d], j, v[d]);
+    }
+    write_swapped(a.hash, i, b.hash, j, hash);
+    write_swapped(a.id, i, b.id, j, id);
+    write_swapped(a.m, i, b.m, j, m);
+    write_swapped(a.w, i, b.w, j, w);
+    write_swapped(a.rho, i, b.rho, j, rho);
+    write_swapped(a.p, i, b.p, j, p);
+    write_swapped(a.c, i, b.c, j, c);
+    write_swapped(a.e, i, b.e, j, e);
+    write_swapped(a.E, i, b.E, j, E);
+#pragma unroll
+    for (int q = 0; q < 6; ++q) write_swapped(a.S[q], i, b.S[q], j, S[q]);
+    write_swapped(a.ep, i, b.ep, j, ep);
 }
 
 // ------------------------------------------------ several particle types

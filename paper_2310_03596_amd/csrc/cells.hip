@@ -18,18 +18,63 @@ __device__ inline int cell_coord(double x, double o, double L, int n)
     return (int)t;
 }
 
-__global__ __launch_bounds__(kBlock) void k_hash(Grid g, uint32_t n, const double *__restrict__ x0,
-                                                 const double *__restrict__ x1,
-                                                 const double *__restrict__ x2, uint32_t *keys,
-                                                 uint32_t *vals)
+__device__ inline uint32_t bucket_of(const Grid &g, double x, double y, double z)
 {
-    uint32_t i = blockIdx.x * kBlock + threadIdx.x;
-    if (i >= n) return;
-    int cx = cell_coord(x0[i], g.o[0], g.L, g.nx);
-    int cy = cell_coord(x1[i], g.o[1], g.L, g.ny);
-    int cz = cell_coord(x2[i], g.o[2], g.L, g.nz);
-    keys[i] = (uint32_t)cx + (uint32_t)g.nx * ((uint32_t)cy + (uint32_t)g.ny * (uint32_t)cz);
-    vals[i] = i;
+    const int cx = cell_coord(x, g.o[0], g.L, g.nx);
+    const int cy = cell_coord(y, g.o[1], g.L, g.ny);
+    const int cz = cell_coord(z, g.o[2], g.L, g.nz);
+    return (uint32_t)cx + (uint32_t)g.nx * ((uint32_t)cy + (uint32_t)g.ny * (uint32_t)cz);
+}
+
+// Bucket hash of every particle (keys, with values the particle indices),
+// and in the same pass the first radix pass's per-tile counts of the lowest
+// D-bit digit (same tiles and tile order as the histogram kernel), so the
+// sort starts at its digit scan.  A tile of 2,048 or 4,096 keys is one
+// workgroup of 1,024 threads (a column-sized sort has only a few hundred
+// tiles, so the sort's own 256-thread workgroups would leave the chip short
+// of wavefronts).  Also clears the count of long empty-bucket runs that the
+// bucket table queues for the reorder.
+constexpr int kHashBlock = 1024;
+template <int D>
+__global__ __launch_bounds__(kHashBlock) void k_hash_hist(Grid g, uint32_t n, const double *__restrict__ x0,
+                                                          const double *__restrict__ x1,
+                                                          const double *__restrict__ x2,
+                                                          uint32_t *__restrict__ keys, uint32_t *__restrict__ vals,
+                                                          uint32_t *__restrict__ hist, uint32_t tiles,
+                                                          uint32_t *__restrict__ ngaps)
+{
+    constexpr int BINS = 1 << D;
+    constexpr int TILE = kBlock * sort_items<D>;
+    static_assert(TILE % kHashBlock == 0, "a tile is whole rounds of the workgroup");
+    constexpr int IT = TILE / kHashBlock;
+    __shared__ uint32_t h[BINS];
+    for (int b = threadIdx.x; b < BINS; b += kHashBlock) h[b] = 0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) *ngaps = 0u;
+    __syncthreads();
+    const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
+    const uint32_t base = tile * (uint32_t)TILE;
+    double p[IT][3];
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+        const uint32_t e = base + it * kHashBlock + threadIdx.x;
+        const bool valid = e < n;
+        p[it][0] = valid ? x0[e] : 0.0;
+        p[it][1] = valid ? x1[e] : 0.0;
+        p[it][2] = valid ? x2[e] : 0.0;
+    }
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+        const uint32_t e = base + it * kHashBlock + threadIdx.x;
+        const bool valid = e < n;
+        const uint32_t key = bucket_of(g, p[it][0], p[it][1], p[it][2]);
+        if (valid) {
+            keys[e] = key;
+            vals[e] = e;
+        }
+        hist_chunk<D>(h, valid ? key & (BINS - 1) : (uint32_t)BINS, valid);
+    }
+    __syncthreads();
+    for (int b = threadIdx.x; b < BINS; b += kHashBlock) hist[(size_t)b * tiles + tile] = h[b];
 }
 
 // Float offset from the bucket corner, ((x - o) - c L) evaluated in IEEE
@@ -44,9 +89,23 @@ template <typename real>
 __global__ __launch_bounds__(kBlock) void k_gather(Grid g, PV<real> in, PV<real> out,
                                                    const uint32_t *__restrict__ keys,
                                                    const uint32_t *__restrict__ vals,
-                                                   uint32_t *__restrict__ perm, int split)
+                                                   uint32_t *__restrict__ perm, int split,
+                                                   uint32_t *__restrict__ start,
+                                                   const uint32_t *__restrict__ ngaps,
+                                                   const uint3 *__restrict__ gaps, uint32_t gap_cap)
 {
     uint32_t k = blockIdx.x * kBlock + threadIdx.x;
+    {
+        // the bucket table's long runs of empty buckets, each spread over
+        // every thread of the grid
+        uint32_t m = *ngaps;
+        m = m < gap_cap ? m : gap_cap;
+        const uint32_t T = gridDim.x * kBlock;
+        for (uint32_t r = 0; r < m; ++r) {
+            const uint3 gp = gaps[r];
+            for (uint32_t c = gp.x + k; c <= gp.y; c += T) start[c] = gp.z;
+        }
+    }
     if (k >= in.n) return;
     const uint32_t s = vals[k];
     const uint32_t h = keys[k];
@@ -100,21 +159,72 @@ __global__ __launch_bounds__(kBlock) void k_gather(Grid g, PV<real> in, PV<real>
     }
 }
 
-// start[c] = lower bound of c in the sorted keys, c = 0..ncells.
+// Bucket table from the sorted keys: start[c] is the number of keys below c,
+// so the buckets c with keys[i-1] < c <= keys[i] all start at i (with
+// keys[-1] = -1 and keys[n] = ncells).  Each thread takes kStartItems values
+// of i (its keys loaded at once) and writes the starts of their runs of
+// buckets: short runs itself, longer ones with its workgroup, and runs of
+// more than kLongRun empty buckets (wide empty regions of the box) go to a
+// list that the reorder kernel, launched next, fills with all its threads;
+// if the list is full the workgroup fills the run.  Every start[c] is
+// written exactly once, and no thread walks a long run alone.
+constexpr uint32_t kShortRun = 8;
+constexpr uint32_t kLongRun = 16 * kBlock;
+constexpr int kStartItems = 2;
 __global__ __launch_bounds__(kBlock) void k_cell_start(const uint32_t *__restrict__ keys, uint32_t n,
-                                                       uint32_t ncells, uint32_t *__restrict__ start)
+                                                       uint32_t ncells, uint32_t *__restrict__ start,
+                                                       uint32_t *__restrict__ ngaps, uint3 *__restrict__ gaps,
+                                                       uint32_t gap_cap)
 {
-    uint32_t c = blockIdx.x * kBlock + threadIdx.x;
-    if (c > ncells) return;
-    uint32_t lo = 0, hi = n;
-    while (lo < hi) {
-        uint32_t mid = lo + ((hi - lo) >> 1);
-        if (keys[mid] < c)
-            lo = mid + 1;
-        else
-            hi = mid;
+    __shared__ uint3 q[kBlock * kStartItems];
+    __shared__ uint32_t nq;
+    if (threadIdx.x == 0) nq = 0;
+    // consecutive key ranges on one XCD: the starts they write side by side
+    // fill whole lines in one L2
+    const uint32_t base = xcd_tile(blockIdx.x, gridDim.x) * (uint32_t)(kBlock * kStartItems);
+    uint32_t kp[kStartItems], kc[kStartItems];
+#pragma unroll
+    for (int it = 0; it < kStartItems; ++it) {
+        const uint32_t i = base + it * kBlock + threadIdx.x;
+        kp[it] = i >= 1 && i <= n ? keys[i - 1] : 0u;
+        kc[it] = i < n ? keys[i] : 0u;
     }
-    start[c] = lo;
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < kStartItems; ++it) {
+        const uint32_t i = base + it * kBlock + threadIdx.x;
+        if (i > n) break;
+        const uint32_t lo = i == 0 ? 0u : kp[it] + 1u;
+        const uint32_t hi = i == n ? ncells : kc[it];   // buckets lo..hi start at i
+        if (lo > hi) continue;
+        const uint32_t len = hi - lo + 1u;
+        if (len <= kShortRun) {
+            for (uint32_t c = lo; c <= hi; ++c) start[c] = i;
+            continue;
+        }
+        bool listed = false;
+        if (len > kLongRun) {
+            const uint32_t k = atomicAdd(ngaps, 1u);
+            if (k < gap_cap) {
+                gaps[k] = make_uint3(lo, hi, i);
+                listed = true;
+            }
+        }
+        if (!listed) q[atomicAdd(&nq, 1u)] = make_uint3(lo, hi, i);
+    }
+    __syncthreads();
+    const uint32_t m = nq;
+    for (uint32_t k = 0; k < m; ++k) {
+        const uint3 r = q[k];
+        for (uint32_t c = r.x + threadIdx.x; c <= r.y; c += kBlock) start[c] = r.z;
+    }
+}
+
+// start[0..ncells] = 0 (no particles).
+__global__ __launch_bounds__(kBlock) void k_start_empty(uint32_t ncells, uint32_t *__restrict__ start)
+{
+    const uint32_t c = blockIdx.x * kBlock + threadIdx.x;
+    if (c <= ncells) start[c] = 0u;
 }
 
 // ------------------------------------------------------------ step c: mark
@@ -199,25 +309,45 @@ __global__ __launch_bounds__(kBlock) void k_pack(PV<real> in, const uint32_t *__
     uint32_t cnt = *nb;
     if (k >= out.n || k >= cnt) return;
     uint32_t s = bidx[k];
+    // every field is read before the first write (the payload could alias
+    // the particles as far as the compiler knows, and a read issued after a
+    // write would wait out the write's round trip)
+    double x[3] = {0.0, 0.0, 0.0};
+    real off[3] = {0, 0, 0}, v[3] = {0, 0, 0}, S[6] = {0, 0, 0, 0, 0, 0};
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-        if (out.x[d]) out.x[d][k] = in.x[d][s];
-        if (out.off[d]) out.off[d][k] = in.off[d][s];
-        if (out.v[d]) out.v[d][k] = in.v[d][s];
+        if (out.x[d]) x[d] = in.x[d][s];
+        if (out.off[d]) off[d] = in.off[d][s];
+        if (out.v[d]) v[d] = in.v[d][s];
     }
-    if (out.hash) out.hash[k] = in.hash[s];
-    if (out.id) out.id[k] = in.id[s];
-    if (out.m) out.m[k] = in.m[s];
-    if (out.w) out.w[k] = in.w[s];
-    if (out.rho) out.rho[k] = in.rho[s];
-    if (out.p) out.p[k] = in.p[s];
-    if (out.c) out.c[k] = in.c[s];
-    if (out.e) out.e[k] = in.e[s];
-    if (out.E) out.E[k] = in.E[s];
+    const uint32_t hash = out.hash ? in.hash[s] : 0u, id = out.id ? in.id[s] : 0u;
+    const real m = out.m ? in.m[s] : real(0), w = out.w ? in.w[s] : real(0);
+    const real rho = out.rho ? in.rho[s] : real(0), p = out.p ? in.p[s] : real(0);
+    const real c = out.c ? in.c[s] : real(0), e = out.e ? in.e[s] : real(0);
+    const double E = out.E ? in.E[s] : 0.0;
 #pragma unroll
     for (int q = 0; q < 6; ++q)
-        if (out.S[q]) out.S[q][k] = in.S[q][s];
-    if (out.ep) out.ep[k] = in.ep[s];
+        if (out.S[q]) S[q] = in.S[q][s];
+    const real ep = out.ep ? in.ep[s] : real(0);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        if (out.x[d]) out.x[d][k] = x[d];
+        if (out.off[d]) out.off[d][k] = off[d];
+        if (out.v[d]) out.v[d][k] = v[d];
+    }
+    if (out.hash) out.hash[k] = hash;
+    if (out.id) out.id[k] = id;
+    if (out.m) out.m[k] = m;
+    if (out.w) out.w[k] = w;
+    if (out.rho) out.rho[k] = rho;
+    if (out.p) out.p[k] = p;
+    if (out.c) out.c[k] = c;
+    if (out.e) out.e[k] = e;
+    if (out.E) out.E[k] = E;
+#pragma unroll
+    for (int q = 0; q < 6; ++q)
+        if (out.S[q]) out.S[q][k] = S[q];
+    if (out.ep) out.ep[k] = ep;
 }
 
 }  // namespace
@@ -228,18 +358,36 @@ hipError_t launch_build_cells(const Grid &g, int prec, const sph_particles &in, 
     uint32_t n = in.n;
     uint32_t blocks = div_up(n, kBlock);
     if (n > 0) {
-        k_hash<<<blocks, kBlock, 0, s>>>(g, n, in.x[0], in.x[1], in.x[2], ws.keys[0], ws.vals[0]);
-        const int cur = radix_sort(ws, n, g.ncells, s);
-        if (prec == SPH_FP64)
-            k_gather<double><<<blocks, kBlock, 0, s>>>(g, view<double>(in), view<double>(out), ws.keys[cur],
-                                                       ws.vals[cur], perm, 0);
+        // the list of long empty-bucket runs takes the histogram area once the
+        // sort is done; its count sits in the first entry of counts
+        uint32_t *ngaps = ws.counts;
+        uint3 *gaps = reinterpret_cast<uint3 *>(ws.hist);
+        const uint32_t gap_cap = (uint32_t)(((uint64_t)kMaxRadixBins * div_up(n, kSortTile)) / 3u);
+        const int D = radix_digit_bits(g.ncells);
+        if (D == 8)
+            k_hash_hist<8><<<sort_tiles<8>(n), kHashBlock, 0, s>>>(g, n, in.x[0], in.x[1], in.x[2], ws.keys[0],
+                                                               ws.vals[0], ws.hist, sort_tiles<8>(n), ngaps);
+        else if (D == 9)
+            k_hash_hist<9><<<sort_tiles<9>(n), kHashBlock, 0, s>>>(g, n, in.x[0], in.x[1], in.x[2], ws.keys[0],
+                                                               ws.vals[0], ws.hist, sort_tiles<9>(n), ngaps);
         else
-            k_gather<float><<<blocks, kBlock, 0, s>>>(g, view<float>(in), view<float>(out), ws.keys[cur],
-                                                      ws.vals[cur], perm, 1);
-        k_cell_start<<<div_up((uint64_t)g.ncells + 1, kBlock), kBlock, 0, s>>>(ws.keys[cur], n, g.ncells,
-                                                                                start);
+            k_hash_hist<10><<<sort_tiles<10>(n), kHashBlock, 0, s>>>(g, n, in.x[0], in.x[1], in.x[2], ws.keys[0],
+                                                                 ws.vals[0], ws.hist, sort_tiles<10>(n), ngaps);
+        const int cur = radix_sort(ws, n, g.ncells, s, true);
+        // the reorder also fills the long empty runs: enough threads that each
+        // takes at most 16 buckets of the longest, whatever n
+        const uint64_t gblocks64 = div_up((uint64_t)g.ncells + 1, (uint64_t)kBlock * 16u);
+        const uint32_t gblocks = blocks > gblocks64 ? blocks : (uint32_t)gblocks64;
+        k_cell_start<<<div_up((uint64_t)n + 1, (uint64_t)kBlock * kStartItems), kBlock, 0, s>>>(
+            ws.keys[cur], n, g.ncells, start, ngaps, gaps, gap_cap);
+        if (prec == SPH_FP64)
+            k_gather<double><<<gblocks, kBlock, 0, s>>>(g, view<double>(in), view<double>(out), ws.keys[cur],
+                                                        ws.vals[cur], perm, 0, start, ngaps, gaps, gap_cap);
+        else
+            k_gather<float><<<gblocks, kBlock, 0, s>>>(g, view<float>(in), view<float>(out), ws.keys[cur],
+                                                       ws.vals[cur], perm, 1, start, ngaps, gaps, gap_cap);
     } else {
-        k_cell_start<<<div_up((uint64_t)g.ncells + 1, kBlock), kBlock, 0, s>>>(ws.keys[0], 0, g.ncells, start);
+        k_start_empty<<<div_up((uint64_t)g.ncells + 1, kBlock), kBlock, 0, s>>>(g.ncells, start);
     }
     return hipGetLastError();
 }

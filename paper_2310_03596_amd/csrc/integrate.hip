@@ -114,7 +114,14 @@ __device__ inline void finish(const Params &P, const PV<real> &s, uint32_t i, do
 // thread taking particles i, i + T, ... (T the grid's threads), so the final
 // fold of the per-workgroup records reads at most kDiagBlocks records in one
 // round trip; the records depend on n only, so the totals stay deterministic.
-constexpr uint32_t kDiagBlocks = 2048;
+#ifndef SPH_DIAG_BLOCKS
+// measured on the 810k column (300 steps, two rounds each): 1024 workgroups
+// 0.4706 ms per step, 2048 0.4750, 3072 0.4773, 4096 (one particle per
+// thread) slower still: a thread with several particles keeps more loads in
+// flight
+#define SPH_DIAG_BLOCKS 1024
+#endif
+constexpr uint32_t kDiagBlocks = SPH_DIAG_BLOCKS;
 
 template <typename real, bool SPLIT>
 __global__ __launch_bounds__(kBlock) void k_motion(Params P, PV<real> s, RV<real> R, const double *__restrict__ dtp,

@@ -247,8 +247,11 @@ __global__ __launch_bounds__(kBlock) void k_stage(Grid g, PV<real> s, Stage<real
     uint32_t j = (blockIdx.x - (plan ? 1u : 0u)) * kBlock + threadIdx.x;
     if (j >= s.n) return;
     using v4 = typename Vec4<real>::type;
-    v4 pos;
-    const uint32_t cx = s.hash[j] % (uint32_t)g.nx;
+    // every field is read before the first record is written: the records
+    // could alias the fields as far as the compiler knows, and a read issued
+    // after a write would wait out the write's round trip
+    v4 pos, a, b, c0, c1;
+    const uint32_t hj = s.hash[j];
     if constexpr (SPLIT) {
         pos.x = s.off[0][j];
         pos.y = s.off[1][j];
@@ -258,9 +261,6 @@ __global__ __launch_bounds__(kBlock) void k_stage(Grid g, PV<real> s, Stage<real
         pos.y = s.x[1][j];
         pos.z = s.x[2][j];
     }
-    pos.w = (real)cx;
-    st.pos[j] = pos;
-    v4 a, b;
     a.x = s.v[0][j];
     a.y = s.v[1][j];
     a.z = s.v[2][j];
@@ -269,10 +269,7 @@ __global__ __launch_bounds__(kBlock) void k_stage(Grid g, PV<real> s, Stage<real
     b.y = s.p[j];
     b.z = s.c[j];
     b.w = s.e[j];
-    st.va[rec_stride<real> * j] = a;
-    st.vb[rec_stride<real> * j] = b;
     if constexpr (SOLID) {
-        v4 c0, c1;
         c0.x = s.S[0][j];
         c0.y = s.S[1][j];
         c0.z = s.S[2][j];
@@ -281,6 +278,12 @@ __global__ __launch_bounds__(kBlock) void k_stage(Grid g, PV<real> s, Stage<real
         c1.y = s.S[5][j];
         c1.z = 0;
         c1.w = 0;
+    }
+    pos.w = (real)(hj % (uint32_t)g.nx);
+    st.pos[j] = pos;
+    st.va[rec_stride<real> * j] = a;
+    st.vb[rec_stride<real> * j] = b;
+    if constexpr (SOLID) {
         st.s0[rec_stride<real> * j] = c0;
         st.s1[rec_stride<real> * j] = c1;
     }

@@ -111,6 +111,22 @@ __device__ inline uint32_t block_scan_row(uint32_t *__restrict__ row, uint32_t l
     return carry;
 }
 
+// Adds one chunk of a tile (the kBlock keys' digits d, BINS for no key) to
+// the tile's histogram h in LDS.  Runs of equal digits in consecutive lanes
+// add their length once (the keys arrive nearly sorted, step after step, so
+// runs are long and the LDS atomics do not serialise on one address).
+template <int D>
+__device__ inline void hist_chunk(uint32_t *h, uint32_t d, bool valid)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    const uint32_t prev = __shfl_up(d, 1, kWave);
+    const bool head = lane == 0 || d != prev;
+    const uint64_t heads = __ballot(head);
+    const uint64_t above = heads & ~((2ull << lane) - 1ull);   // heads past this lane (2 << 63 wraps to 0)
+    const int next = above ? __ffsll((unsigned long long)above) - 1 : kWave;
+    if (valid && head) atomicAdd(&h[d], (uint32_t)(next - lane));
+}
+
 template <int D>
 __global__ __launch_bounds__(kBlock) void k_upsweep(const uint32_t *__restrict__ keys, uint32_t n, int shift,
                                                     uint32_t *__restrict__ hist, uint32_t tiles)
@@ -119,10 +135,6 @@ __global__ __launch_bounds__(kBlock) void k_upsweep(const uint32_t *__restrict__
     __shared__ uint32_t h[BINS];
     for (int b = threadIdx.x; b < BINS; b += kBlock) h[b] = 0;
     __syncthreads();
-    // Runs of equal digits in consecutive lanes add their length once (the
-    // keys arrive nearly sorted, step after step, so runs are long and the
-    // LDS atomics do not serialise on one address).
-    const int lane = threadIdx.x & (kWave - 1);
     constexpr int IT = sort_items<D>;
     // Consecutive tiles run on one XCD: a digit's counts of 32 consecutive
     // tiles share one 128-byte line of hist, which is then written (here)
@@ -139,13 +151,7 @@ __global__ __launch_bounds__(kBlock) void k_upsweep(const uint32_t *__restrict__
     for (int it = 0; it < IT; ++it) {
         const uint32_t e = base + it * kBlock + threadIdx.x;
         const bool valid = e < n;
-        const uint32_t d = valid ? (keyv[it] >> shift) & (BINS - 1) : (uint32_t)BINS;
-        const uint32_t prev = __shfl_up(d, 1, kWave);
-        const bool head = lane == 0 || d != prev;
-        const uint64_t heads = __ballot(head);
-        const uint64_t above = heads & ~((2ull << lane) - 1ull);   // heads past this lane (2 << 63 wraps to 0)
-        const int next = above ? __ffsll((unsigned long long)above) - 1 : kWave;
-        if (valid && head) atomicAdd(&h[d], (uint32_t)(next - lane));
+        hist_chunk<D>(h, valid ? (keyv[it] >> shift) & (BINS - 1) : (uint32_t)BINS, valid);
     }
     __syncthreads();
     for (int b = threadIdx.x; b < BINS; b += kBlock) hist[(size_t)b * tiles + tile] = h[b];
@@ -275,12 +281,21 @@ __global__ __launch_bounds__(kBlock) void k_downsweep(const uint32_t *__restrict
     }
 }
 
-// One LSD pass with D-bit digits starting at bit `shift`.
+// Keys per tile and tiles of a pass with D-bit digits over n keys.
 template <int D>
-void sort_pass(const Workspace &ws, uint32_t n, int shift, int cur, hipStream_t s)
+inline uint32_t sort_tiles(uint32_t n)
 {
-    const uint32_t tiles = div_up(n, (uint64_t)kBlock * sort_items<D>);   // at most the workspace's tiles
-    k_upsweep<D><<<tiles, kBlock, 0, s>>>(ws.keys[cur], n, shift, ws.hist, tiles);
+    return div_up(n, (uint64_t)kBlock * sort_items<D>);   // at most the workspace's tiles
+}
+
+// One LSD pass with D-bit digits starting at bit `shift`; with hist_ready the
+// per-tile digit counts are already in ws.hist (written by the kernel that
+// produced the keys, over the same tiles).
+template <int D>
+void sort_pass(const Workspace &ws, uint32_t n, int shift, int cur, hipStream_t s, bool hist_ready = false)
+{
+    const uint32_t tiles = sort_tiles<D>(n);
+    if (!hist_ready) k_upsweep<D><<<tiles, kBlock, 0, s>>>(ws.keys[cur], n, shift, ws.hist, tiles);
     k_scan_digit<<<1u << D, kBlock, 0, s>>>(ws.hist, tiles, ws.totals);
     k_downsweep<D><<<tiles, kBlock, 0, s>>>(ws.keys[cur], ws.vals[cur], ws.keys[cur ^ 1], ws.vals[cur ^ 1], n,
                                             shift, ws.hist, tiles, ws.totals);
@@ -294,23 +309,34 @@ inline int key_bits(uint32_t nkeys)
     return b;
 }
 
-// Sorts (ws.keys[0], ws.vals[0]) of n entries, keys below nkeys; returns the
-// index of the key/value buffer pair that holds the result.
-inline int radix_sort(const Workspace &ws, uint32_t n, uint32_t nkeys, hipStream_t s)
+// Digit width (8 to 10 bits) of a sort of keys below nkeys, in as few passes
+// as possible.
+inline int radix_digit_bits(uint32_t nkeys)
 {
     const int bits = key_bits(nkeys);
     const int passes = bits > 0 ? (bits + kMaxRadixBits - 1) / kMaxRadixBits : 1;
-    int dbits = (bits + passes - 1) / passes;
-    dbits = dbits < 8 ? 8 : dbits;
+    const int dbits = (bits + passes - 1) / passes;
+    return dbits < 8 ? 8 : dbits;
+}
+
+// Sorts (ws.keys[0], ws.vals[0]) of n entries, keys below nkeys; returns the
+// index of the key/value buffer pair that holds the result.  With
+// first_hist, the first pass's per-tile digit counts are already in ws.hist.
+inline int radix_sort(const Workspace &ws, uint32_t n, uint32_t nkeys, hipStream_t s, bool first_hist = false)
+{
+    const int bits = key_bits(nkeys);
+    const int passes = bits > 0 ? (bits + kMaxRadixBits - 1) / kMaxRadixBits : 1;
+    const int dbits = radix_digit_bits(nkeys);
     int cur = 0;
     for (int ps = 0; ps < passes; ++ps) {
         const int shift = ps * dbits;
+        const bool ready = first_hist && ps == 0;
         if (dbits == 8)
-            sort_pass<8>(ws, n, shift, cur, s);
+            sort_pass<8>(ws, n, shift, cur, s, ready);
         else if (dbits == 9)
-            sort_pass<9>(ws, n, shift, cur, s);
+            sort_pass<9>(ws, n, shift, cur, s, ready);
         else
-            sort_pass<10>(ws, n, shift, cur, s);
+            sort_pass<10>(ws, n, shift, cur, s, ready);
         cur ^= 1;
     }
     return cur;

@@ -198,6 +198,19 @@ class SharePass:
         L.sph_build_cells(self.grid, self.RA.struct(), self.RB.struct(), self.rperm.data_ptr(),
                           cells_struct(self.rstart, self.nc), self.ws.data_ptr(), self.ws_bytes, st)
 
+    def resort(self):
+        """Step a on arrays that are already sorted, as at every step of a run
+        (the particles arrive in the order the previous sort left them):
+        sorts LB into LA and RB into RA, then swaps the roles, so LB and RB
+        hold the result as after build()."""
+        st = stream_handle()
+        L.sph_build_cells(self.grid, self.LB.struct(), self.LA.struct(), self.lperm.data_ptr(),
+                          cells_struct(self.lstart, self.nc), self.ws.data_ptr(), self.ws_bytes, st)
+        L.sph_build_cells(self.grid, self.RB.struct(), self.RA.struct(), self.rperm.data_ptr(),
+                          cells_struct(self.rstart, self.nc), self.ws.data_ptr(), self.ws_bytes, st)
+        self.LA, self.LB = self.LB, self.LA
+        self.RA, self.RB = self.RB, self.RA
+
     def mark(self):
         L.sph_mark_boundary(self.grid, self.LB.struct(), cells_struct(self.rstart, self.nc), self.comm.data_ptr(),
                             self.bidx.data_ptr(), self.nl, self.nb.data_ptr(), self.ws.data_ptr(), self.ws_bytes,

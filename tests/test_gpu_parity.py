@@ -150,6 +150,66 @@ def test_build_cells_bit_exact(case, prec):
         assert np.array_equal(h["off"], ref.astype(np.float32).astype(np.float64))
 
 
+def _sparse(n, seed, clumps=False):
+    """n particles in the unit box with h = 0.003: a grid of 4.6 million
+    buckets, almost all empty.  Placed at random, the empty runs between
+    occupied buckets are thousands long (with 800 particles more of them
+    exceed 4096 buckets than the bucket table's list of long runs holds, so
+    its workgroup fallback runs too); in two clumps at opposite corners, one
+    run spans almost the whole grid."""
+    w = S.random_cloud(n, seed=seed, h=0.003, rho_sigma=0.01)
+    if clumps:
+        half = n // 2
+        w.x[:half] *= 0.05
+        w.x[half:] = 0.95 + 0.05 * w.x[half:]
+    return w
+
+
+SPARSE = {
+    "sparse800": lambda: _sparse(800, 60),
+    "sparse3000": lambda: _sparse(3000, 61),
+    "clumps": lambda: _sparse(1000, 62, clumps=True),
+}
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("case", list(SPARSE))
+def test_bucket_table_long_empty_runs(case, prec):
+    wl = SPARSE[case]()
+    nc = int(np.prod(wl.grid["dims"]))
+    print(f"[build_cells sparse] case={case} prec={prec} n={wl.n} buckets={nc}", flush=True)
+    sim = _sim(wl, prec)
+    sim.start.fill_(-1)   # every entry must be written
+    sim.build()
+    torch.cuda.synchronize()
+    h = sim.A.host()
+    s = cpu.State.from_workload(wl)
+    o, operm, ostart = cpu.build_cells(wl.grid, s)
+    assert np.array_equal(sim.perm.cpu().numpy().view(np.uint32), operm)
+    assert np.array_equal(h["hash"], o.hash)
+    assert np.array_equal(sim.start.cpu().numpy().view(np.uint32), ostart)
+    runs = np.diff(np.concatenate([[-1], np.unique(o.hash), [nc]])) - 1
+    print(f"  empty runs over 4096 buckets: {(runs > 4096).sum()}, longest {runs.max()}", flush=True)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_bucket_table_of_no_particles(prec):
+    from paper_2310_03596_amd import _lib as L
+    from paper_2310_03596_amd.state import Particles, cells_struct, grid_struct, ncells, stream_handle
+    wl = S.random_cloud(10, seed=63, h=0.01)
+    nc = ncells(wl.grid)
+    a, b = Particles(0, prec, False), Particles(0, prec, False)
+    start = torch.full((nc + 1,), 7, dtype=torch.int32, device="cuda")
+    gs = grid_struct(wl.grid)
+    wsb = L.sph_workspace_size(gs, 0, prec, L.SPH_FLUID_TAIT)
+    ws = torch.zeros(max(wsb, 1), dtype=torch.uint8, device="cuda")
+    rc = L.sph_build_cells(gs, a.struct(), b.struct(), None, cells_struct(start, nc), ws.data_ptr(), wsb,
+                           stream_handle())
+    assert rc == 0
+    torch.cuda.synchronize()
+    assert int(start.abs().sum()) == 0
+
+
 @pytest.mark.parametrize("prec", PRECS)
 @pytest.mark.parametrize("case", list(CASES))
 def test_force_pass_matches_oracle(case, prec):
