@@ -115,9 +115,10 @@ def time_forms(wl, plan, warmup):
     timed = {}
     for prec, steps in plan:
         sim = sims[prec]
-        # HIP events bracket the FORCE launch of every EVENT_EVERY-th timed step
-        # (an event pair costs a few microseconds of queue time, so timing every
-        # launch would slow the steps being timed)
+        # HIP events bracket the pair kernel of the FORCE call (recorded by the
+        # library around that launch alone: sph_set_pair_events) in every
+        # EVENT_EVERY-th timed step (an event pair costs a few microseconds of
+        # queue time, so timing every launch would slow the steps being timed)
         sampled = list(range(0, steps, EVENT_EVERY))
         evs = {k: (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for k in sampled}
         torch.cuda.synchronize()
@@ -487,7 +488,7 @@ def main():
                    "n_particles": wl.n, "grid": wl.grid["dims"],
                    "form": "FP32 split (bucket index + float offset, pair sums accumulated in FP64; x, E in FP64)"
                    if main_prec == 1 else "plain FP64"},
-        "roofline": {"bound": "alu", "kernel": "FORCE pass (k_pairs)",
+        "roofline": {"bound": "alu", "kernel": "FORCE pass pair kernel (k_pairs, staging excluded)",
                      "achieved": r["force_tflops"], "peak": PEAK_TFLOPS[main_prec], "unit": "TFLOP/s",
                      "frac": r["force_tflops"] / PEAK_TFLOPS[main_prec], "traffic": recorded_traffic(main_prec),
                      "avg_launch_ms": r["force_ms"], "flops_per_launch": r["flops_per_launch"],

@@ -262,6 +262,18 @@ int sph_count_pairs(const sph_params *params, const sph_grid *grid, const sph_pa
                     const sph_particles *sources, sph_cells source_cells, uint64_t *counts_dev,
                     void *stream);
 
+/* Measurement hook, not part of the method.  Given two hipEvent_t handles
+ * (created by the caller with timing enabled, still owned by the caller),
+ * every later call that runs a pair kernel (sph_interact,
+ * sph_interact_adjoint, sph_neighbor_census) records begin_event on its
+ * stream immediately before launching the pair kernel and end_event
+ * immediately after, so that the kernel alone can be timed (the staging of
+ * the source records and the wavefront plan run before it in the same
+ * call).  NULL, NULL stops the recording.  The setting is process-wide and
+ * meant for a benchmark that times one call at a time.
+ * Errors: SPH_ERR_ARG when only one of the two handles is given. */
+int sph_set_pair_events(void *begin_event, void *end_event);
+
 /* Neighbour census of one interaction pass (Section I: a particle's
  * neighbours lie in its own bucket or the 26 around it).  Takes the arguments
  * of sph_interact without the rates and runs the same staging, wavefront

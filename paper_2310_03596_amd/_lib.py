@@ -57,7 +57,8 @@ class SphAdjoint(C.Structure):
 
 
 EXPORTS = ("sph_version", "sph_last_error", "sph_workspace_size", "sph_build_cells", "sph_mark_boundary",
-           "sph_mark_boundary_noalloc", "sph_pack_boundary", "sph_interact", "sph_count_pairs", "sph_neighbor_census", "sph_integrate", "sph_interact_adjoint",
+           "sph_mark_boundary_noalloc", "sph_pack_boundary", "sph_interact", "sph_count_pairs", "sph_set_pair_events",
+           "sph_neighbor_census", "sph_integrate", "sph_interact_adjoint",
            "sph_integrate_adjoint", "sph_permute_adjoint", "sph_centroid", "sph_balance_hash",
            "sph_balance_select", "sph_swap", "sph_centroid_types", "sph_balance_hash_types",
            "sph_balance_select_types")
@@ -95,6 +96,7 @@ def load():
                                P(SphParticles), SphCells, C.c_int, P(SphRates), _vp, C.c_size_t, _vp]
     L.sph_count_pairs.argtypes = [P(SphParams), P(SphGrid), P(SphParticles), _vp, _vp, P(SphParticles),
                                   SphCells, _vp, _vp]
+    L.sph_set_pair_events.argtypes = [_vp, _vp]
     L.sph_neighbor_census.argtypes = [P(SphParams), P(SphGrid), C.c_int, P(SphParticles), _vp, _vp,
                                       P(SphParticles), SphCells, _vp, _vp, _vp, C.c_size_t, _vp]
     L.sph_integrate.argtypes = [P(SphParams), C.c_int, P(SphParticles), P(SphRates), _vp, _vp, _vp,
@@ -174,6 +176,12 @@ def sph_count_pairs(params, grid, targets, tidx_ptr, nt_ptr, sources, source_cel
     return check("sph_count_pairs", load().sph_count_pairs(C.byref(params), C.byref(grid), C.byref(targets),
                                                            tidx_ptr, nt_ptr, C.byref(sources), source_cells,
                                                            counts_ptr, stream))
+
+
+def sph_set_pair_events(begin_event, end_event):
+    """Measurement hook: hipEvent_t handles (int) recorded around every later
+    pair-kernel launch; None, None stops it."""
+    return check("sph_set_pair_events", load().sph_set_pair_events(begin_event or None, end_event or None))
 
 
 def sph_neighbor_census(params, grid, pass_, targets, tidx_ptr, nt_ptr, sources, source_cells, count_ptr, sum_ptr,

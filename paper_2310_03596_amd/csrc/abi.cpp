@@ -173,6 +173,14 @@ size_t sph_workspace_size(const sph_grid *grid, uint32_t n_max, int prec, int ma
     return carve(nullptr, n_max, stage_bytes(prec, material)).bytes;
 }
 
+int sph_set_pair_events(void *begin_event, void *end_event)
+{
+    if ((begin_event == nullptr) != (end_event == nullptr))
+        return fail(SPH_ERR_ARG, "give both events or neither");
+    set_pair_events(begin_event, end_event);
+    return SPH_OK;
+}
+
 int sph_build_cells(const sph_grid *grid, const sph_particles *in, sph_particles *out, uint32_t *perm_out,
                     sph_cells cells, void *ws, size_t ws_bytes, void *stream)
 {

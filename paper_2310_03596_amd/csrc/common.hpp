@@ -289,6 +289,7 @@ inline Stage<real> stage_view(const Workspace &w, uint32_t n, bool solid, bool a
 // ---------------------------------------------------------------- launchers
 // Each returns hipSuccess or the launch error; arguments were validated.
 
+void set_pair_events(void *begin, void *end);
 hipError_t launch_build_cells(const Grid &g, int prec, const sph_particles &in, const sph_particles &out,
                               uint32_t *perm, uint32_t *start, const Workspace &ws, hipStream_t s);
 // Largest local array sph_mark_boundary_noalloc takes (its block counts live

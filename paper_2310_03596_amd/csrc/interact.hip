@@ -33,11 +33,16 @@
 // float positions would; its pair sums accumulate in FP64 (full rate on
 // gfx950: a convert and an add per term) and are stored as a float (hi, lo)
 // pair.
+#include <atomic>
+
 #include "pair.hpp"
 
 namespace sph {
 
 namespace {
+
+// Events recorded around every pair-kernel launch when set (sph_set_pair_events).
+std::atomic<void *> g_pair_events[2] = {nullptr, nullptr};
 
 #ifndef SPH_PAIR_BLOCK
 #define SPH_PAIR_BLOCK 256
@@ -928,6 +933,12 @@ hipError_t go(const Params &P, const Grid &g, const sph_particles &tg, const uin
                 k_stage_rbar<real><<<div_up(sr.n, kBlock), kBlock, 0, s>>>(sr.n, rs, st);
         }
     }
+    hipEvent_t ev_begin = static_cast<hipEvent_t>(g_pair_events[0].load());
+    hipEvent_t ev_end = static_cast<hipEvent_t>(g_pair_events[1].load());
+    if (ev_begin && ev_end) {
+        const hipError_t e = hipEventRecord(ev_begin, s);
+        if (e != hipSuccess) return e;
+    }
     if (self)
         k_pairs<real, PASS, SOLID, true><<<blocks, kPairBlock, 0, s>>>(P, g, view<real>(tg), tidx, nt, st, sstart,
                                                                      zero_first, view<real>(r), view<real>(bar),
@@ -936,7 +947,10 @@ hipError_t go(const Params &P, const Grid &g, const sph_particles &tg, const uin
         k_pairs<real, PASS, SOLID, false><<<blocks, kPairBlock, 0, s>>>(P, g, view<real>(tg), tidx, nt, st, sstart,
                                                                       zero_first, view<real>(r), view<real>(bar),
                                                                       plan, nplan, cz);
-    return hipGetLastError();
+    const hipError_t le = hipGetLastError();
+    if (le != hipSuccess) return le;
+    if (ev_begin && ev_end) return hipEventRecord(ev_end, s);
+    return hipSuccess;
 }
 
 template <typename real>
@@ -1032,6 +1046,12 @@ hipError_t launch_interact(const Params &P, const Grid &g, int prec, int pass, c
     if (prec == SPH_FP64)
         return go_prec<double>(P, g, pass, tg, tidx, nt, sr, sstart, self, zero_first, r, ws, s);
     return go_prec<float>(P, g, pass, tg, tidx, nt, sr, sstart, self, zero_first, r, ws, s);
+}
+
+void set_pair_events(void *begin, void *end)
+{
+    g_pair_events[0].store(begin);
+    g_pair_events[1].store(end);
 }
 
 }  // namespace sph

@@ -67,8 +67,9 @@ class Sim:
         return self.diag[self.cur].data_ptr()    # [0] = next dt of the previous update
 
     def step(self, dt_ptr=None, force_events=None):
-        """One whole step.  force_events: optional (start, end) stream events
-        recorded around the FORCE pass (per-kernel timing)."""
+        """One whole step.  force_events: optional (start, end) torch CUDA
+        events (timing enabled) that the FORCE call records around its pair
+        kernel alone (sph_set_pair_events)."""
         dtp = self.dt_ptr(dt_ptr)
         self.build()
         a = self.A.struct()
@@ -79,11 +80,14 @@ class Sim:
                            self.ws.data_ptr(), self.ws_bytes, st)
             L.sph_integrate(self.params, L.SPH_STAGE_STRESS, a, r, dtp, None, None, 0, st)
         if force_events is not None:
-            force_events[0].record()
+            for ev in force_events:
+                if not ev.cuda_event:   # torch creates an event at its first record
+                    ev.record()
+            L.sph_set_pair_events(force_events[0].cuda_event, force_events[1].cuda_event)
         L.sph_interact(self.params, self.grid, L.SPH_PASS_FORCE, a, None, None, a, self.cells, 1, r,
                        self.ws.data_ptr(), self.ws_bytes, st)
         if force_events is not None:
-            force_events[1].record()
+            L.sph_set_pair_events(None, None)
         nxt = 1 - self.cur
         L.sph_integrate(self.params, L.SPH_STAGE_MOTION, a, r, dtp, self.diag[nxt].data_ptr(), self.ws.data_ptr(),
                         self.ws_bytes, st)

@@ -29,6 +29,14 @@ def test_header_declares_the_abi():
     assert set(names) == set(L.EXPORTS)
 
 
+def test_binding_wraps_every_export():
+    # sph_last_error is read by the wrappers themselves: a failed call raises
+    # SphError with its message
+    for name in L.EXPORTS:
+        if name != "sph_last_error":
+            assert callable(getattr(L, name, None)), name
+
+
 def test_library_exports_every_declared_symbol():
     lib = L.load()
     for name in declared_functions():
@@ -202,6 +210,14 @@ def test_mark_boundary_noalloc_rejects_bad_arguments():
     q = _particles(10)
     q.hash = None
     assert mark(q) == L.SPH_ERR_ARG
+
+
+def test_pair_events_need_both_handles():
+    lib = L.load()
+    assert lib.sph_set_pair_events(FAKE, None) == L.SPH_ERR_ARG
+    assert "both events" in _last()
+    assert lib.sph_set_pair_events(None, FAKE) == L.SPH_ERR_ARG
+    assert lib.sph_set_pair_events(None, None) == 0   # off: nothing is recorded
 
 
 def test_passes_over_one_array_need_one_size():
