@@ -10,7 +10,8 @@ inputs are resident in HBM before the timed region.
 
 Prints one JSON line: particle-updates/s of the FP32 split-precision form
 (value) and of the plain FP64 form, the roofline of the dominant kernel
-(the FORCE pass) from HIP events around its launches, and the FP64 CPU
+(the FORCE pass's pair kernel) from HIP events the library records around
+its launches, and the FP64 CPU
 oracle timed on a bounded sample together with the per-field error of both
 GPU forms against it.
 """
@@ -58,6 +59,8 @@ def parse():
     ap.add_argument("--only", choices=["fp32", "fp64", "both"], default="both")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward ratio leg")
     ap.add_argument("--no-share", action="store_true", help="skip the 8M + 2M share pass-set leg")
+    ap.add_argument("--adjoint-only", action="store_true",
+                    help="run only the adjoint leg and print its fields (for profiling it)")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="also run one plain device copy of this many MiB (scale for HBM counters)")
     return ap.parse_args()
@@ -202,9 +205,10 @@ def other_workloads_leg():
 
 def adjoint_leg(prec, reps=5):
     """Adjoint/forward time ratio on the 250,047-particle box: 50 fixed-dt
-    steps with checkpoints every 10 (forward), then the reverse pass
-    (recompute of every segment + reverse kernels).  Best of `reps`.  Also
-    returns the gradient (dJ/dv0, dJ/dc0) of the last round."""
+    steps with checkpoints every 10 (forward: the rollout from the initial
+    state already on the device), then the reverse pass (recompute of every
+    segment, with its bucket tables, + reverse kernels).  Best of `reps`.
+    Also returns the gradient (dJ/dv0, dJ/dc0) of the last round."""
     import torch
 
     import sph_synth as S
@@ -215,9 +219,10 @@ def adjoint_leg(prec, reps=5):
     grad = None
     for _ in range(reps + 1):      # the first round warms up
         ro = KineticEnergyRollout(wl, prec, wl.extra["steps"], wl.extra["ckpt"], wl.extra["dt"])
+        ro.prepare(wl.v, wl.params["c0"])   # host-to-device upload of the initial state
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        ro.forward(wl.v, wl.params["c0"])
+        ro.run()
         t1 = time.perf_counter()
         grad = ro.backward(1.0)
         t2 = time.perf_counter()
@@ -443,6 +448,12 @@ def main():
     import sph_synth as S
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.adjoint_only:
+        a32, g32 = adjoint_leg(1)
+        a64, g64 = adjoint_leg(0)
+        print(json.dumps({"adjoint": {"fp32_split": a32, "fp64": a64,
+                                      "fp32_gradient_error_vs_fp64": adjoint_error(g32, g64)}}), flush=True)
+        return
     wl = S.c2_column()
     out = {}
     res = {}

@@ -85,9 +85,18 @@ class KineticEnergyRollout:
         w.params = dict(self.wl.params, c0=float(c0))
         return w
 
+    def prepare(self, v0: np.ndarray, c0: float):
+        """Uploads the initial state (and its EOS) to the device: the set-up
+        that forward() does before the rollout."""
+        self.sim = Sim(self._workload(v0, c0), self.prec, self.device, fixed_dt=self.dt)
+
     def forward(self, v0: np.ndarray, c0: float) -> float:
-        sim = Sim(self._workload(v0, c0), self.prec, self.device, fixed_dt=self.dt)
-        self.sim = sim
+        self.prepare(v0, c0)
+        return self.run()
+
+    def run(self) -> float:
+        """The rollout from the prepared state, with its checkpoints; J."""
+        sim = self.sim
         self.ckpts = []
         for k in range(self.nsteps):
             if k % self.ckpt == 0:
@@ -138,8 +147,10 @@ class KineticEnergyRollout:
         sb.wait_stream(sa)   # the cotangents were initialised on sa
         st_a = stream_handle()
         npool = min(self.ckpt, self.nsteps)
-        pools = [[(Particles(n, prec, sim.solid, dev), torch.empty_like(sim.perm), torch.empty_like(sim.start),
-                   Rates(n, prec, False, dev)) for _ in range(npool)] for _ in range(2)]
+        # every saved buffer is written whole before it is read: no fill
+        pools = [[(Particles(n, prec, sim.solid, dev, zero=False), torch.empty_like(sim.perm),
+                   torch.empty_like(sim.start), Rates(n, prec, False, dev, zero=False)) for _ in range(npool)]
+                 for _ in range(2)]
         freed = [None, None]
         for idx, seg in enumerate(reversed(range(len(self.ckpts)))):
             q = idx % 2
@@ -150,15 +161,17 @@ class KineticEnergyRollout:
             sim.A.copy_from(self.ckpts[seg])
             saved = pools[q][:k1 - k0]
             for srt, perm, start, rates in saved:
-                sim.build()
-                srt.copy_from(sim.A)
-                perm.copy_(sim.perm)
-                start.copy_(sim.start)
-                a = sim.A.struct()
+                # the step's sorted state, permutation and bucket table go
+                # straight into the saved buffers; the update advances a copy
+                ps = srt.struct()
+                cs = cells_struct(start, sim.nc)
+                L.sph_build_cells(sim.grid, sim.A.struct(), ps, perm.data_ptr(), cs, sim.ws.data_ptr(),
+                                  sim.ws_bytes, st_a)
+                sim.A.copy_from(srt)
                 r = rates.struct()
-                L.sph_interact(sim.params, sim.grid, L.SPH_PASS_FORCE, a, None, None, a, sim.cells, 1, r,
+                L.sph_interact(sim.params, sim.grid, L.SPH_PASS_FORCE, ps, None, None, ps, cs, 1, r,
                                sim.ws.data_ptr(), sim.ws_bytes, st_a)
-                L.sph_integrate(sim.params, L.SPH_STAGE_MOTION, a, r, fixed, sim.diag[0].data_ptr(),
+                L.sph_integrate(sim.params, L.SPH_STAGE_MOTION, sim.A.struct(), r, fixed, sim.diag[0].data_ptr(),
                                 sim.ws.data_ptr(), sim.ws_bytes, st_a)
             ready = torch.cuda.Event()
             ready.record(sa)

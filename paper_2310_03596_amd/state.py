@@ -78,9 +78,12 @@ class _Flat:
     """Fields that live in one device allocation, so that a copy of the whole
     set (checkpoints, saved states of the reverse pass) is one copy."""
 
-    def _allocate(self, layout, device):
+    def _allocate(self, layout, device, zero=True):
+        """zero=False leaves the memory uninitialised (no fill kernel), for
+        buffers that a call overwrites completely before anything reads them."""
         self._layout = layout
-        self._buf = torch.zeros(_carved_bytes(layout), dtype=torch.uint8, device=device)
+        alloc = torch.zeros if zero else torch.empty
+        self._buf = alloc(_carved_bytes(layout), dtype=torch.uint8, device=device)
         self._bind()
 
     def _bind(self):
@@ -105,7 +108,7 @@ class Particles(_Flat):
 
     REAL = ("m", "w", "rho", "p", "c", "e")
 
-    def __init__(self, n: int, prec: int, solid: bool, device="cuda"):
+    def __init__(self, n: int, prec: int, solid: bool, device="cuda", zero: bool = True):
         real = real_dtype(prec)
         self.n, self.prec, self.solid, self.device = n, prec, solid, device
         split = prec == L.SPH_FP32_SPLIT
@@ -114,7 +117,7 @@ class Particles(_Flat):
         layout += [(f, (n,), real) for f in self.REAL]
         layout += [("E", (n,), torch.float64), ("S", (6, n) if solid else None, real),
                    ("ep", (n,) if solid else None, real)]
-        self._allocate(layout, device)
+        self._allocate(layout, device, zero)
 
     def struct(self) -> L.SphParticles:
         """The ABI struct of this array (built once: the buffers never move)."""
@@ -178,12 +181,12 @@ class Particles(_Flat):
 class Rates(_Flat):
     """Pair-sum outputs: FORCE rates and, for solids, the velocity gradient."""
 
-    def __init__(self, n: int, prec: int, gradient: bool, device="cuda"):
+    def __init__(self, n: int, prec: int, gradient: bool, device="cuda", zero: bool = True):
         real = real_dtype(prec)
         split = prec == L.SPH_FP32_SPLIT
         self._allocate([("hi", (6, n), real), ("lo", (6, n) if split else None, real),
                         ("Lhi", (9, n) if gradient else None, real),
-                        ("Llo", (9, n) if (gradient and split) else None, real)], device)
+                        ("Llo", (9, n) if (gradient and split) else None, real)], device, zero)
 
     def struct(self) -> L.SphRates:
         if self._struct is None:
