@@ -103,7 +103,7 @@ __global__ __launch_bounds__(kBlock) void k_gather(Grid g, PV<real> in, PV<real>
         const uint32_t T = gridDim.x * kBlock;
         for (uint32_t r = 0; r < m; ++r) {
             const uint3 gp = gaps[r];
-            for (uint32_t c = gp.x + k; c <= gp.y; c += T) start[c] = gp.z;
+            for (uint64_t c = (uint64_t)gp.x + k; c <= gp.y; c += T) start[c] = gp.z;   // no wrap near 2^32
         }
     }
     if (k >= in.n) return;
@@ -216,7 +216,8 @@ __global__ __launch_bounds__(kBlock) void k_cell_start(const uint32_t *__restric
     const uint32_t m = nq;
     for (uint32_t k = 0; k < m; ++k) {
         const uint3 r = q[k];
-        for (uint32_t c = r.x + threadIdx.x; c <= r.y; c += kBlock) start[c] = r.z;
+        // 64-bit index: the stride must not wrap past r.y near 2^32
+        for (uint64_t c = (uint64_t)r.x + threadIdx.x; c <= r.y; c += kBlock) start[c] = r.z;
     }
 }
 
