@@ -190,12 +190,18 @@ int sph_build_cells(const sph_grid *grid, const sph_particles *in, sph_particles
  * a surrounding bucket, else G = ncells.  Because `local` is already in hash
  * order, the stable sort by communication hash that isolates the boundary
  * particles reduces to a stable compaction: boundary_idx_out receives the
- * flagged indices in ascending order (at most boundary_cap of them) and
- * *n_boundary_dev the true count, which may exceed boundary_cap (the caller
- * checks after synchronising).  Errors: SPH_ERR_ARG, SPH_ERR_WORKSPACE. */
+ * flagged indices in ascending order, at most boundary_cap of them, and
+ * *n_boundary_dev (one uint32 on the device) the number it received,
+ * min(flagged, boundary_cap): the count that sph_pack_boundary and
+ * sph_interact read with this list, so no consumer reads past its end.
+ * *n_flagged_dev (one uint32 on the device; may be NULL) receives the number
+ * of flagged particles, above *n_boundary_dev when the list overflowed (the
+ * caller checks after synchronising, grows the list and marks again).
+ * Errors: SPH_ERR_ARG, SPH_ERR_WORKSPACE. */
 int sph_mark_boundary(const sph_grid *grid, const sph_particles *local, sph_cells remote_cells,
                       uint32_t *comm_hash_out, uint32_t *boundary_idx_out, uint32_t boundary_cap,
-                      uint32_t *n_boundary_dev, void *ws, size_t ws_bytes, void *stream);
+                      uint32_t *n_boundary_dev, uint32_t *n_flagged_dev, void *ws, size_t ws_bytes,
+                      void *stream);
 
 /* sph_mark_boundary for callers that cannot allocate device memory (code
  * under HIP graph capture, tight serving loops, harnesses that forbid
@@ -209,17 +215,19 @@ int sph_mark_boundary(const sph_grid *grid, const sph_particles *local, sph_cell
  * SPH_ERR_HIP. */
 int sph_mark_boundary_noalloc(const sph_grid *grid, const sph_particles *local, sph_cells remote_cells,
                               uint32_t *comm_hash_out, uint32_t *boundary_idx_out, uint32_t boundary_cap,
-                              uint32_t *n_boundary_dev, void *stream);
+                              uint32_t *n_boundary_dev, uint32_t *n_flagged_dev, void *stream);
 
 /* Packing for step (d): payload[k] = local[boundary_idx[k]] for
  * k < min(*n_boundary_dev, payload->n), every field present in payload
- * (payload->n is its capacity; its fields must be a subset of local's).
+ * (payload->n is its capacity; its fields must be a subset of local's).  An
+ * index at or above local->n names no particle: its row is left unwritten.
  * Errors: SPH_ERR_ARG. */
 int sph_pack_boundary(const sph_particles *local, const uint32_t *boundary_idx,
                       const uint32_t *n_boundary_dev, sph_particles *payload, void *stream);
 
 /* Steps (e) and (f).  For every target i (all of `targets` when target_idx is
- * NULL, else target_idx[k] for k < *n_targets_dev, at most targets->n), sums
+ * NULL, else target_idx[k] for k < *n_targets_dev, at most targets->n; an
+ * index at or above targets->n names no target), sums
  * the pair terms over sources j with |x_j - x_i| < 2h found through the
  * sources' bucket table.  Pairs with r = 0 (j == i in the local-local pass,
  * step e, or coincident particles) add nothing.  pass = SPH_PASS_FORCE: rates

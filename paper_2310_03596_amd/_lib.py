@@ -88,9 +88,10 @@ def load():
     L.sph_workspace_size.restype = C.c_size_t
     L.sph_build_cells.argtypes = [P(SphGrid), P(SphParticles), P(SphParticles), _vp, SphCells, _vp,
                                   C.c_size_t, _vp]
-    L.sph_mark_boundary.argtypes = [P(SphGrid), P(SphParticles), SphCells, _vp, _vp, C.c_uint32, _vp, _vp,
+    L.sph_mark_boundary.argtypes = [P(SphGrid), P(SphParticles), SphCells, _vp, _vp, C.c_uint32, _vp, _vp, _vp,
                                     C.c_size_t, _vp]
-    L.sph_mark_boundary_noalloc.argtypes = [P(SphGrid), P(SphParticles), SphCells, _vp, _vp, C.c_uint32, _vp, _vp]
+    L.sph_mark_boundary_noalloc.argtypes = [P(SphGrid), P(SphParticles), SphCells, _vp, _vp, C.c_uint32, _vp, _vp,
+                                            _vp]
     L.sph_pack_boundary.argtypes = [P(SphParticles), _vp, _vp, P(SphParticles), _vp]
     L.sph_interact.argtypes = [P(SphParams), P(SphGrid), C.c_int, P(SphParticles), _vp, _vp,
                                P(SphParticles), SphCells, C.c_int, P(SphRates), _vp, C.c_size_t, _vp]
@@ -148,16 +149,17 @@ def sph_build_cells(grid, inp, out, perm_ptr, cells, ws_ptr, ws_bytes, stream):
                                                            cells, ws_ptr, ws_bytes, stream))
 
 
-def sph_mark_boundary(grid, local, remote_cells, comm_ptr, bidx_ptr, cap, nb_ptr, ws_ptr, ws_bytes, stream):
+def sph_mark_boundary(grid, local, remote_cells, comm_ptr, bidx_ptr, cap, nb_ptr, nflag_ptr, ws_ptr, ws_bytes,
+                      stream):
     return check("sph_mark_boundary", load().sph_mark_boundary(C.byref(grid), C.byref(local), remote_cells,
-                                                               comm_ptr, bidx_ptr, cap, nb_ptr, ws_ptr,
+                                                               comm_ptr, bidx_ptr, cap, nb_ptr, nflag_ptr, ws_ptr,
                                                                ws_bytes, stream))
 
 
-def sph_mark_boundary_noalloc(grid, local, remote_cells, comm_ptr, bidx_ptr, cap, nb_ptr, stream):
+def sph_mark_boundary_noalloc(grid, local, remote_cells, comm_ptr, bidx_ptr, cap, nb_ptr, nflag_ptr, stream):
     return check("sph_mark_boundary_noalloc",
                  load().sph_mark_boundary_noalloc(C.byref(grid), C.byref(local), remote_cells, comm_ptr, bidx_ptr, cap,
-                                                  nb_ptr, stream))
+                                                  nb_ptr, nflag_ptr, stream))
 
 
 def sph_pack_boundary(local, bidx_ptr, nb_ptr, payload, stream):

@@ -205,7 +205,7 @@ int sph_build_cells(const sph_grid *grid, const sph_particles *in, sph_particles
 
 int sph_mark_boundary(const sph_grid *grid, const sph_particles *local, sph_cells remote_cells,
                       uint32_t *comm_hash_out, uint32_t *boundary_idx_out, uint32_t boundary_cap,
-                      uint32_t *n_boundary_dev, void *ws, size_t ws_bytes, void *stream)
+                      uint32_t *n_boundary_dev, uint32_t *n_flagged_dev, void *ws, size_t ws_bytes, void *stream)
 {
     Grid g;
     if (!make_grid(grid, g)) return SPH_ERR_ARG;
@@ -219,13 +219,13 @@ int sph_mark_boundary(const sph_grid *grid, const sph_particles *local, sph_cell
     Workspace w;
     if (!check_ws(ws, ws_bytes, local->n, w)) return SPH_ERR_WORKSPACE;
     return hip_status(launch_mark_boundary(g, *local, remote_cells.start, comm_hash_out, boundary_idx_out,
-                                           boundary_cap, n_boundary_dev, w, (hipStream_t)stream),
+                                           boundary_cap, n_boundary_dev, n_flagged_dev, w, (hipStream_t)stream),
                       "sph_mark_boundary");
 }
 
 int sph_mark_boundary_noalloc(const sph_grid *grid, const sph_particles *local, sph_cells remote_cells,
                               uint32_t *comm_hash_out, uint32_t *boundary_idx_out, uint32_t boundary_cap,
-                              uint32_t *n_boundary_dev, void *stream)
+                              uint32_t *n_boundary_dev, uint32_t *n_flagged_dev, void *stream)
 {
     Grid g;
     if (!make_grid(grid, g)) return SPH_ERR_ARG;
@@ -240,7 +240,8 @@ int sph_mark_boundary_noalloc(const sph_grid *grid, const sph_particles *local, 
     if (local->n > 0 && !comm_hash_out) return fail(SPH_ERR_ARG, "comm_hash_out is NULL");
     if (boundary_cap > 0 && !boundary_idx_out) return fail(SPH_ERR_ARG, "boundary_idx_out is NULL");
     return hip_status(launch_mark_boundary_noalloc(g, *local, remote_cells.start, comm_hash_out, boundary_idx_out,
-                                                   boundary_cap, n_boundary_dev, (hipStream_t)stream),
+                                                   boundary_cap, n_boundary_dev, n_flagged_dev,
+                                                   (hipStream_t)stream),
                       "sph_mark_boundary_noalloc");
 }
 

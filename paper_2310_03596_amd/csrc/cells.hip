@@ -277,11 +277,18 @@ __global__ __launch_bounds__(kBlock) void k_mark(Grid g, uint32_t n, const uint3
 
 // Single workgroup: exclusive scan of block counts, total to *nb.
 constexpr int kScanBlock = 1024;
+// nb: the entries the compaction writes (at most cap), the count the list's
+// consumers read; nflag (optional): every flagged particle, above *nb when
+// the list overflows.
 __global__ __launch_bounds__(kScanBlock) void k_scan_counts(uint32_t *__restrict__ counts, uint32_t nblocks,
-                                                            uint32_t *__restrict__ nb)
+                                                            uint32_t *__restrict__ nb, uint32_t cap,
+                                                            uint32_t *__restrict__ nflag)
 {
     const uint32_t tot = block_scan_row<kScanBlock, 8>(counts, nblocks);
-    if (threadIdx.x == 0) *nb = tot;
+    if (threadIdx.x == 0) {
+        *nb = tot < cap ? tot : cap;
+        if (nflag) *nflag = tot;
+    }
 }
 
 __global__ __launch_bounds__(kBlock) void k_compact(uint32_t n, uint32_t G, const uint32_t *__restrict__ comm,
@@ -309,7 +316,8 @@ __global__ __launch_bounds__(kBlock) void k_pack(PV<real> in, const uint32_t *__
     uint32_t k = blockIdx.x * kBlock + threadIdx.x;
     uint32_t cnt = *nb;
     if (k >= out.n || k >= cnt) return;
-    uint32_t s = bidx[k];
+    const uint32_t s = bidx[k];
+    if (s >= in.n) return;   // a listed index outside the array names no particle
     // every field is read before the first write (the payload could alias
     // the particles as far as the compiler knows, and a read issued after a
     // write would wait out the write's round trip)
@@ -394,13 +402,13 @@ hipError_t launch_build_cells(const Grid &g, int prec, const sph_particles &in, 
 }
 
 hipError_t launch_mark_boundary(const Grid &g, const sph_particles &local, const uint32_t *rstart,
-                                uint32_t *comm, uint32_t *bidx, uint32_t cap, uint32_t *nb,
+                                uint32_t *comm, uint32_t *bidx, uint32_t cap, uint32_t *nb, uint32_t *nflag,
                                 const Workspace &ws, hipStream_t s)
 {
     uint32_t n = local.n;
     uint32_t blocks = div_up(n > 0 ? n : 1, kBlock);
     k_mark<<<blocks, kBlock, 0, s>>>(g, n, local.hash, rstart, comm, ws.counts);
-    k_scan_counts<<<1, kScanBlock, 0, s>>>(ws.counts, blocks, nb);
+    k_scan_counts<<<1, kScanBlock, 0, s>>>(ws.counts, blocks, nb, cap, nflag);
     k_compact<<<blocks, kBlock, 0, s>>>(n, g.ncells, comm, ws.counts, bidx, cap);
     return hipGetLastError();
 }
@@ -437,14 +445,15 @@ hipError_t scratch_of_current_device(uint32_t **out)
 }  // namespace
 
 hipError_t launch_mark_boundary_noalloc(const Grid &g, const sph_particles &local, const uint32_t *rstart,
-                                        uint32_t *comm, uint32_t *bidx, uint32_t cap, uint32_t *nb, hipStream_t s)
+                                        uint32_t *comm, uint32_t *bidx, uint32_t cap, uint32_t *nb,
+                                        uint32_t *nflag, hipStream_t s)
 {
     uint32_t *counts = nullptr;
     hipError_t e = scratch_of_current_device(&counts);
     if (e != hipSuccess) return e;
     Workspace ws{};
     ws.counts = counts;
-    return launch_mark_boundary(g, local, rstart, comm, bidx, cap, nb, ws, s);
+    return launch_mark_boundary(g, local, rstart, comm, bidx, cap, nb, nflag, ws, s);
 }
 
 hipError_t launch_pack(int prec, const sph_particles &local, const uint32_t *bidx, const uint32_t *nb,

@@ -296,9 +296,10 @@ hipError_t launch_build_cells(const Grid &g, int prec, const sph_particles &in, 
 // in a fixed device array of kNoAllocMarkMax / kBlock + 1 words, 1 MiB).
 constexpr uint32_t kNoAllocMarkMax = 1u << 26;
 hipError_t launch_mark_boundary_noalloc(const Grid &g, const sph_particles &local, const uint32_t *rstart,
-                                        uint32_t *comm, uint32_t *bidx, uint32_t cap, uint32_t *nb, hipStream_t s);
+                                        uint32_t *comm, uint32_t *bidx, uint32_t cap, uint32_t *nb,
+                                        uint32_t *nflag, hipStream_t s);
 hipError_t launch_mark_boundary(const Grid &g, const sph_particles &local, const uint32_t *rstart,
-                                uint32_t *comm, uint32_t *bidx, uint32_t cap, uint32_t *nb,
+                                uint32_t *comm, uint32_t *bidx, uint32_t cap, uint32_t *nb, uint32_t *nflag,
                                 const Workspace &ws, hipStream_t s);
 hipError_t launch_pack(int prec, const sph_particles &local, const uint32_t *bidx, const uint32_t *nb,
                        const sph_particles &payload, hipStream_t s);

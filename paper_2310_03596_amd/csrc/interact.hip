@@ -828,8 +828,8 @@ __global__ __launch_bounds__(kBlock) void k_count(Params P, Grid g, PV<real> tg,
         nt = c < nt ? c : nt;
     }
     unsigned long long cand = 0, hits = 0;
-    if (t < nt) {
-        const uint32_t i = tidx ? tidx[t] : t;
+    const uint32_t i = t < nt ? (tidx ? tidx[t] : t) : tg.n;
+    if (i < tg.n) {   // a listed index outside the target array names no target
         const real R2 = (real)P.R2;
         const real Lf = SPLIT ? (real)g.Lf : real(0);
         const uint32_t h = tg.hash[i];

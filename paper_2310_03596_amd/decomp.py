@@ -84,7 +84,7 @@ class TwoSets:
         ws, wsb = self.ws.data_ptr(), self.ws_bytes
         for q, (X, Y) in enumerate(self.pairs()):
             L.sph_mark_boundary(self.grid, X.A.struct(), Y.cells, self.comm[q].data_ptr(), self.bidx[q].data_ptr(),
-                                X.n, self.nb[q:q + 1].data_ptr(), ws, wsb, st)
+                                X.n, self.nb[q:q + 1].data_ptr(), None, ws, wsb, st)
         for q, (X, Y) in enumerate(self.pairs()):
             a, r = X.A.struct(), X.rates.struct()
             L.sph_interact(self.params, self.grid, L.SPH_PASS_FORCE, a, None, None, a, X.cells, 1, r, ws, wsb, st)

@@ -217,8 +217,8 @@ class SharePass:
 
     def mark(self):
         L.sph_mark_boundary(self.grid, self.LB.struct(), cells_struct(self.rstart, self.nc), self.comm.data_ptr(),
-                            self.bidx.data_ptr(), self.nl, self.nb.data_ptr(), self.ws.data_ptr(), self.ws_bytes,
-                            stream_handle())
+                            self.bidx.data_ptr(), self.nl, self.nb.data_ptr(), None, self.ws.data_ptr(),
+                            self.ws_bytes, stream_handle())
 
     def pack(self):
         L.sph_pack_boundary(self.LB.struct(), self.bidx.data_ptr(), self.nb.data_ptr(), self.payload.struct(),

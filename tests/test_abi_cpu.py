@@ -197,7 +197,7 @@ def test_mark_boundary_noalloc_rejects_bad_arguments():
     cells = L.SphCells(FAKE, 64, 0)
 
     def mark(p, cl=cells, comm=FAKE, bidx=FAKE, cap=10, nb=FAKE):
-        return lib.sph_mark_boundary_noalloc(C.byref(g), C.byref(p), cl, comm, bidx, cap, nb, None)
+        return lib.sph_mark_boundary_noalloc(C.byref(g), C.byref(p), cl, comm, bidx, cap, nb, None, None)
 
     # beyond the fixed block-count array: a clear error, before anything runs
     assert mark(_particles((1 << 26) + 1)) == L.SPH_ERR_ARG

@@ -405,6 +405,10 @@ def test_share_pass_matches_oracle(layout, prec):
 
 
 def test_boundary_capacity_overflow_reports_true_count():
+    """A boundary list shorter than the flagged set: the list holds the first
+    cap indices, the count its consumers read is cap, and the flagged count
+    is the true one; packing and a local-remote pass from the short list
+    read only its entries."""
     from paper_2310_03596_amd import _lib as L
     from paper_2310_03596_amd.sim import SharePass
     from paper_2310_03596_amd.state import cells_struct, stream_handle
@@ -413,13 +417,34 @@ def test_boundary_capacity_overflow_reports_true_count():
     sp.build()
     cap = 17
     sentinel = torch.full((sp.nl,), -7, dtype=torch.int32, device="cuda")
+    nflag = torch.zeros(1, dtype=torch.int32, device="cuda")
     L.sph_mark_boundary(sp.grid, sp.LB.struct(), cells_struct(sp.rstart, sp.nc), sp.comm.data_ptr(),
-                        sentinel.data_ptr(), cap, sp.nb.data_ptr(), sp.ws.data_ptr(), sp.ws_bytes,
+                        sentinel.data_ptr(), cap, sp.nb.data_ptr(), nflag.data_ptr(), sp.ws.data_ptr(), sp.ws_bytes,
                         stream_handle())
     torch.cuda.synchronize()
-    nb = int(sp.nb.cpu()[0])
-    assert nb > cap
+    comm = sp.comm.cpu().numpy().view(np.uint32)
+    flagged = np.flatnonzero(comm != cpu.ncells(loc.grid))
+    assert int(nflag.cpu()[0]) == flagged.size > cap
+    assert int(sp.nb.cpu()[0]) == cap
     got = sentinel.cpu().numpy()
     assert np.all(got[cap:] == -7)
-    comm = sp.comm.cpu().numpy().view(np.uint32)
-    assert np.array_equal(got[:cap], np.flatnonzero(comm != cpu.ncells(loc.grid))[:cap])
+    assert np.array_equal(got[:cap], flagged[:cap])
+    # consumers of the short list: a list of exactly cap entries (the rest of
+    # the buffer poisoned with indices past the array) packs and interacts
+    # like the first cap flagged particles
+    short = torch.full((sp.nl,), -1, dtype=torch.int32, device="cuda")   # 0xFFFFFFFF: no particle
+    short[:cap] = sentinel[:cap]
+    sp.bidx.copy_(short)
+    sp.pack()
+    torch.cuda.synchronize()
+    pay = sp.payload.host()
+    hl = sp.LB.host()
+    assert np.array_equal(pay["id"][:cap], hl["id"][flagged[:cap]])
+    _, _, c_short, k_short = sp.census()
+    listed = flagged[:cap]
+    rest = np.setdiff1d(np.arange(sp.nl), listed)
+    assert not c_short[rest].any() and not k_short[rest].any()
+    sp.mark()    # the whole list (capacity: every local particle)
+    _, _, c_full, k_full = sp.census()
+    assert c_full[listed].sum() > 0
+    assert np.array_equal(c_short[listed], c_full[listed]) and np.array_equal(k_short[listed], k_full[listed])

@@ -41,10 +41,12 @@ def test_noalloc_mark_equals_workspace_mark():
         comm = torch.full((sp.nl,), -5, dtype=torch.int32, device="cuda")
         bidx = torch.full((sp.nl,), -5, dtype=torch.int32, device="cuda")
         nb = torch.full((1,), -5, dtype=torch.int32, device="cuda")
+        nflag = torch.full((1,), -5, dtype=torch.int32, device="cuda")
         L.sph_mark_boundary_noalloc(sp.grid, sp.LB.struct(), cells_struct(sp.rstart, sp.nc), comm.data_ptr(),
-                                    bidx.data_ptr(), cap, nb.data_ptr(), stream_handle())
+                                    bidx.data_ptr(), cap, nb.data_ptr(), nflag.data_ptr(), stream_handle())
         torch.cuda.synchronize()
-        assert int(nb.cpu()[0]) == nb_ref               # the true count, also past the capacity
+        assert int(nflag.cpu()[0]) == nb_ref            # the true count, also past the capacity
+        assert int(nb.cpu()[0]) == min(cap, nb_ref)     # the entries written
         assert np.array_equal(comm.cpu().numpy().view(np.uint32), comm_ref)
         got = bidx.cpu().numpy()
         k = min(cap, nb_ref)
