@@ -198,6 +198,7 @@ __device__ inline int wave_max(int v)
 // *nplan receives their number.  The staging kernel runs this as its first
 // workgroup, so the plan's latency hides behind the staging.
 constexpr int kPlanBlock = kBlock;
+constexpr int kPlanRows = 8;   // consecutive rows per thread in one chunk of the plan
 __device__ inline void wave_plan_block(const Grid &g, const uint32_t *__restrict__ start, uint2 *__restrict__ plan,
                                        uint32_t *__restrict__ nplan)
 {
@@ -205,14 +206,20 @@ __device__ inline void wave_plan_block(const Grid &g, const uint32_t *__restrict
     const uint32_t nx = (uint32_t)g.nx, nrows = (uint32_t)g.ny * (uint32_t)g.nz;
     const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
     uint32_t carry = 0;
-    for (uint32_t r0 = 0; r0 < nrows; r0 += kPlanBlock) {
-        const uint32_t r = r0 + threadIdx.x;
-        uint32_t b = 0, len = 0;
-        if (r < nrows) {
-            b = start[(size_t)r * nx];
-            len = start[(size_t)(r + 1) * nx] - b;
+    for (uint32_t r0 = 0; r0 < nrows; r0 += kPlanBlock * kPlanRows) {
+        // the thread's rows rb .. rb + kPlanRows - 1: their kPlanRows + 1
+        // boundaries are all loaded before the first is used (one memory
+        // round trip per chunk; rows past the last start and end at n)
+        const uint32_t rb = r0 + (uint32_t)threadIdx.x * kPlanRows;
+        uint32_t bnd[kPlanRows + 1];
+#pragma unroll
+        for (int k = 0; k <= kPlanRows; ++k) {
+            const uint32_t r = rb + (uint32_t)k < nrows ? rb + (uint32_t)k : nrows;
+            bnd[k] = start[(size_t)r * nx];
         }
-        const uint32_t w = (len + kWave - 1) / kWave;
+        uint32_t w = 0;
+#pragma unroll
+        for (int k = 0; k < kPlanRows; ++k) w += (bnd[k + 1] - bnd[k] + kWave - 1) / kWave;
         // exclusive scan of w over the block (wavefront scan, then wavefront totals)
         uint32_t inc = w;
 #pragma unroll
@@ -229,10 +236,14 @@ __device__ inline void wave_plan_block(const Grid &g, const uint32_t *__restrict
             tot += s;
         }
         __syncthreads();
-        const uint32_t first = carry + before + inc - w;
-        for (uint32_t k = 0; k < w; ++k) {
-            const uint32_t left = len - k * kWave;
-            plan[first + k] = make_uint2(b + k * kWave, left < (uint32_t)kWave ? left : (uint32_t)kWave);
+        uint32_t q = carry + before + inc - w;
+#pragma unroll
+        for (int k = 0; k < kPlanRows; ++k) {
+            const uint32_t b = bnd[k], len = bnd[k + 1] - bnd[k];
+            for (uint32_t m = 0; m * (uint32_t)kWave < len; ++m) {
+                const uint32_t left = len - m * (uint32_t)kWave;
+                plan[q++] = make_uint2(b + m * (uint32_t)kWave, left < (uint32_t)kWave ? left : (uint32_t)kWave);
+            }
         }
         carry += tot;
     }
