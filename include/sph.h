@@ -55,7 +55,8 @@ enum sph_status {
 enum sph_precision { SPH_FP64 = 0, SPH_FP32_SPLIT = 1 };
 enum sph_material { SPH_FLUID_TAIT = 0, SPH_SOLID_J2 = 1 };
 enum sph_pass { SPH_PASS_FORCE = 0, SPH_PASS_GRADIENT = 1 };
-enum sph_stage { SPH_STAGE_MOTION = 0, SPH_STAGE_STRESS = 1, SPH_STAGE_EOS = 2 };
+enum sph_stage { SPH_STAGE_MOTION = 0, SPH_STAGE_STRESS = 1, SPH_STAGE_EOS = 2, SPH_STAGE_INPUT_VELOCITY = 3 };
+enum sph_objective { SPH_OBJ_KINETIC_ENERGY = 0, SPH_OBJ_TAGGED_MEAN_Z = 1 };
 
 /* Particle types that the per-type balancing calls (Section III.B) accept. */
 #define SPH_MAX_TYPES 8
@@ -365,12 +366,31 @@ int sph_interact_adjoint(const sph_params *params, const sph_grid *grid, int pas
  * SPH_FP32_SPLIT) the velocity gradient it used; on entry bar->S and
  * bar->eps_p hold the cotangents of the stage's outputs, on return those of
  * its inputs, and rates_bar->Lhi receives the cotangent of L (overwritten).
+ * SPH_STAGE_INPUT_VELOCITY (the end of a reverse pass whose input is the
+ * initial velocity at a fixed specific internal energy, E = e + |v|^2 / 2
+ * with e held): p is that initial state; bar->v += bar->E v in place, with
+ * bar->E left as it is (rates, dt_dev, rates_bar, param_bar_dev and the
+ * workspace are not used).
  * Errors: SPH_ERR_ARG, SPH_ERR_WORKSPACE, SPH_ERR_UNSUPPORTED (walls,
  * gravity, the Mie-Gruneisen EOS). */
 int sph_integrate_adjoint(const sph_params *params, int stage, const sph_particles *p,
                           const sph_rates *rates, const double *dt_dev, const sph_adjoint *bar,
                           const sph_rates *rates_bar, double *param_bar_dev, void *ws,
                           size_t ws_bytes, void *stream);
+
+/* Start of a reverse pass: the cotangent of a scalar objective J of the final
+ * state p (any order), times `scale` (the cotangent of J itself; 1 for the
+ * plain gradient), written into bar.  Every non-NULL field of bar is
+ * overwritten.  SPH_OBJ_KINETIC_ENERGY: J = sum_i m_i |v_i|^2 / 2, so
+ * bar->v = scale m v, bar->m = scale |v|^2 / 2 and every other field 0.
+ * SPH_OBJ_TAGGED_MEAN_Z: J = the mean z of the ntag particles whose id is
+ * tagged (tag: tag_len bytes on the device, tag[id] != 0 for a tagged id; an
+ * id at or above tag_len is untagged), so bar->x[2] = scale / ntag on the
+ * tagged particles and every other entry and field 0.  Arithmetic in FP64,
+ * rounded once to the form's precision.  Needs p->v and p->m (kinetic
+ * energy) or p->id (tagged mean z).  Errors: SPH_ERR_ARG. */
+int sph_objective_adjoint(int objective, const sph_particles *p, const uint8_t *tag, uint32_t tag_len,
+                          uint32_t ntag, double scale, const sph_adjoint *bar, void *stream);
 
 /* Adjoint of the reorder in sph_build_cells: out[perm[k]] = in[k] for every
  * non-NULL field of the state cotangent (x, v, m, omega, E, and for solids S

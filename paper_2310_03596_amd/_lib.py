@@ -16,7 +16,8 @@ SPH_OK, SPH_ERR_ARG, SPH_ERR_WORKSPACE, SPH_ERR_HIP, SPH_ERR_UNSUPPORTED = 0, -1
 SPH_FP64, SPH_FP32_SPLIT = 0, 1
 SPH_FLUID_TAIT, SPH_SOLID_J2 = 0, 1
 SPH_PASS_FORCE, SPH_PASS_GRADIENT = 0, 1
-SPH_STAGE_MOTION, SPH_STAGE_STRESS, SPH_STAGE_EOS = 0, 1, 2
+SPH_STAGE_MOTION, SPH_STAGE_STRESS, SPH_STAGE_EOS, SPH_STAGE_INPUT_VELOCITY = 0, 1, 2, 3
+SPH_OBJ_KINETIC_ENERGY, SPH_OBJ_TAGGED_MEAN_Z = 0, 1
 SPH_EOS_LINEAR, SPH_EOS_MIE_GRUNEISEN = 0, 1
 SPH_MAX_TYPES = 8   # particle types of the per-type balancing calls
 
@@ -59,7 +60,7 @@ class SphAdjoint(C.Structure):
 EXPORTS = ("sph_version", "sph_last_error", "sph_workspace_size", "sph_build_cells", "sph_mark_boundary",
            "sph_mark_boundary_noalloc", "sph_pack_boundary", "sph_interact", "sph_count_pairs", "sph_set_pair_events",
            "sph_neighbor_census", "sph_integrate", "sph_interact_adjoint",
-           "sph_integrate_adjoint", "sph_permute_adjoint", "sph_centroid", "sph_balance_hash",
+           "sph_integrate_adjoint", "sph_objective_adjoint", "sph_permute_adjoint", "sph_centroid", "sph_balance_hash",
            "sph_balance_select", "sph_swap", "sph_centroid_types", "sph_balance_hash_types",
            "sph_balance_select_types")
 
@@ -107,6 +108,8 @@ def load():
                                        C.c_size_t, _vp]
     L.sph_integrate_adjoint.argtypes = [P(SphParams), C.c_int, P(SphParticles), P(SphRates), _vp,
                                         P(SphAdjoint), P(SphRates), _vp, _vp, C.c_size_t, _vp]
+    L.sph_objective_adjoint.argtypes = [C.c_int, P(SphParticles), _vp, C.c_uint32, C.c_uint32, C.c_double,
+                                        P(SphAdjoint), _vp]
     L.sph_permute_adjoint.argtypes = [C.c_int, C.c_uint32, _vp, P(SphAdjoint), P(SphAdjoint), _vp]
     L.sph_centroid.argtypes = [P(SphParticles), _vp, _vp, C.c_size_t, _vp]
     L.sph_balance_hash.argtypes = [P(SphParticles), _vp, _vp, C.c_uint32, _vp, _vp, _vp, C.c_size_t, _vp]
@@ -212,6 +215,11 @@ def sph_integrate_adjoint(params, stage, p, rates, dt_ptr, bar, rates_bar, pbar_
                                                                        _ref(rates), dt_ptr, C.byref(bar),
                                                                        _ref(rates_bar), pbar_ptr, ws_ptr,
                                                                        ws_bytes, stream))
+
+
+def sph_objective_adjoint(objective, p, tag_ptr, tag_len, ntag, scale, bar, stream):
+    return check("sph_objective_adjoint", load().sph_objective_adjoint(objective, C.byref(p), tag_ptr, tag_len, ntag,
+                                                                       float(scale), C.byref(bar), stream))
 
 
 def sph_permute_adjoint(prec, n, perm_ptr, inp, out, stream):

@@ -116,19 +116,18 @@ class KineticEnergyRollout:
     def backward(self, gJ: float):
         sim = self.sim
         n, prec, dev = sim.n, self.prec, self.device
-        real = real_dtype(prec)
         bar = Cotangent(n, prec, dev)
         tmp = Cotangent(n, prec, dev)
-        # dJ/d(final state): J = sum m |v|^2 / 2
+        # dJ/d(final state), seeded by the library: J = sum m |v|^2 / 2, or
+        # the mean z of the tagged particles (a byte per id marks them)
         if self.tag is None:
-            v = self.final.v.double()
-            bar.v.copy_((gJ * self.final.m.double() * v).to(real))
-            bar.m.copy_((gJ * 0.5 * (v * v).sum(0)).to(real))
+            L.sph_objective_adjoint(L.SPH_OBJ_KINETIC_ENERGY, self.final.struct(), None, 0, 0, gJ, bar.struct(),
+                                    stream_handle())
         else:
-            ids = self.final.id.to(torch.int64)
-            tag = torch.as_tensor(self.tag, device=ids.device)
-            hit = torch.isin(ids, tag)
-            bar.x[2].copy_((hit.to(torch.float64) * (gJ / float(self.tag.size))).to(real))
+            flags = torch.zeros(n, dtype=torch.uint8, device=dev)
+            flags[torch.as_tensor(self.tag, device=dev)] = 1
+            L.sph_objective_adjoint(L.SPH_OBJ_TAGGED_MEAN_Z, self.final.struct(), flags.data_ptr(), n,
+                                    int(self.tag.size), gJ, bar.struct(), stream_handle())
         c0bar = torch.zeros(1, dtype=torch.float64, device=dev)
         rbar = Rates(n, prec, False, dev)
         ws_adj_bytes = L.sph_workspace_size(sim.grid, n, prec, L.SPH_SOLID_J2)
@@ -196,9 +195,9 @@ class KineticEnergyRollout:
         sa.wait_stream(sb)
         torch.cuda.synchronize()
         # the initial state is in id order; E0 = e0 + |v0|^2 / 2 adds dJ/dE0 v0 to dJ/dv0
-        v0 = self.ckpts[0].v.double()
-        vbar = bar.v.double() + bar.E.double()[None, :] * v0
-        return vbar.T.cpu().numpy(), float(c0bar.cpu()[0])
+        L.sph_integrate_adjoint(sim.params, L.SPH_STAGE_INPUT_VELOCITY, self.ckpts[0].struct(), None, None,
+                                bar.struct(), None, None, None, 0, stream_handle())
+        return bar.v.double().T.cpu().numpy(), float(c0bar.cpu()[0])
 
 
 class SolidKineticEnergyRollout:
@@ -239,12 +238,10 @@ class SolidKineticEnergyRollout:
     def backward(self, gJ: float):
         sim = self.sim
         n, prec, dev = sim.n, self.prec, self.device
-        real = real_dtype(prec)
         bar = Cotangent(n, prec, dev, solid=True)
         tmp = Cotangent(n, prec, dev, solid=True)
-        v = self.final.v.double()
-        bar.v.copy_((gJ * self.final.m.double() * v).to(real))
-        bar.m.copy_((gJ * 0.5 * (v * v).sum(0)).to(real))
+        L.sph_objective_adjoint(L.SPH_OBJ_KINETIC_ENERGY, self.final.struct(), None, 0, 0, gJ, bar.struct(),
+                                stream_handle())
         c0bar = torch.zeros(1, dtype=torch.float64, device=dev)
         rbar = Rates(n, prec, True, dev)
         ws_bytes = L.sph_workspace_size(sim.grid, n, prec, L.SPH_SOLID_J2)
@@ -285,9 +282,9 @@ class SolidKineticEnergyRollout:
                 L.sph_permute_adjoint(prec, n, perm.data_ptr(), bar.state_struct(), tmp.state_struct(), st)
                 bar, tmp = tmp, bar
         torch.cuda.synchronize()
-        v0 = self.ckpts[0].v.double()
-        vbar = bar.v.double() + bar.E.double()[None, :] * v0
-        return vbar.T.cpu().numpy(), bar.S.double().T.cpu().numpy()
+        L.sph_integrate_adjoint(sim.params, L.SPH_STAGE_INPUT_VELOCITY, self.ckpts[0].struct(), None, None,
+                                bar.struct(), None, None, None, 0, st)
+        return bar.v.double().T.cpu().numpy(), bar.S.double().T.cpu().numpy()
 
 
 class TwoSetKineticEnergyRollout:
@@ -331,14 +328,12 @@ class TwoSetKineticEnergyRollout:
     def backward(self, gJ: float):
         ts = self.ts
         prec, dev = self.prec, self.device
-        real = real_dtype(prec)
         sides = ts.sides
         bars = [Cotangent(s.n, prec, dev) for s in sides]
         tmps = [Cotangent(s.n, prec, dev) for s in sides]
         for s, b in zip(sides, bars):
-            v = s.A.v.double()
-            b.v.copy_((gJ * s.A.m.double() * v).to(real))
-            b.m.copy_((gJ * 0.5 * (v * v).sum(0)).to(real))
+            L.sph_objective_adjoint(L.SPH_OBJ_KINETIC_ENERGY, s.A.struct(), None, 0, 0, gJ, b.struct(),
+                                    stream_handle())
         c0bar = torch.zeros(1, dtype=torch.float64, device=dev)
         rbars = [Rates(s.n, prec, False, dev) for s in sides]
         nmax = max(s.n for s in sides)
@@ -385,9 +380,9 @@ class TwoSetKineticEnergyRollout:
         # back to the caller's order: set A holds the particles with owner False
         vbar = np.empty((self.wl.n, 3))
         for q, mask in enumerate((~self.owner, self.owner)):
-            v0 = self.ckpts[0][q].v.double()
-            vb = bars[q].v.double() + bars[q].E.double()[None, :] * v0
-            vbar[mask] = vb.T.cpu().numpy()
+            L.sph_integrate_adjoint(ts.params, L.SPH_STAGE_INPUT_VELOCITY, self.ckpts[0][q].struct(), None, None,
+                                    bars[q].struct(), None, None, None, 0, st)
+            vbar[mask] = bars[q].v.double().T.cpu().numpy()
         return vbar, float(c0bar.cpu()[0])
 
 

@@ -4,6 +4,7 @@
 #include <stdarg.h>
 #include <stdio.h>
 
+#include <cmath>
 #include <string>
 
 #include "common.hpp"
@@ -463,7 +464,8 @@ int sph_integrate_adjoint(const sph_params *params, int stage, const sph_particl
     if (params->wall_mask != 0 || params->gravity[0] != 0.0 || params->gravity[1] != 0.0 ||
         params->gravity[2] != 0.0)
         return fail(SPH_ERR_UNSUPPORTED, "adjoint is provided without walls and gravity");
-    if (stage != SPH_STAGE_MOTION && stage != SPH_STAGE_EOS && stage != SPH_STAGE_STRESS)
+    if (stage != SPH_STAGE_MOTION && stage != SPH_STAGE_EOS && stage != SPH_STAGE_STRESS &&
+        stage != SPH_STAGE_INPUT_VELOCITY)
         return fail(SPH_ERR_ARG, "unknown adjoint stage %d", stage);
     if (stage == SPH_STAGE_STRESS && !solid) return fail(SPH_ERR_ARG, "the stress stage needs a solid");
     if (!p || p->prec != params->prec) return fail(SPH_ERR_ARG, "particles missing or precision mismatch");
@@ -500,6 +502,30 @@ int sph_integrate_adjoint(const sph_params *params, int stage, const sph_particl
                                                rates_bar ? *rates_bar : none, param_bar_dev, w,
                                                (hipStream_t)stream),
                       "sph_integrate_adjoint");
+}
+
+int sph_objective_adjoint(int objective, const sph_particles *p, const uint8_t *tag, uint32_t tag_len,
+                          uint32_t ntag, double scale, const sph_adjoint *bar, void *stream)
+{
+    if (objective != SPH_OBJ_KINETIC_ENERGY && objective != SPH_OBJ_TAGGED_MEAN_Z)
+        return fail(SPH_ERR_ARG, "unknown objective %d", objective);
+    if (!p) return fail(SPH_ERR_ARG, "p is NULL");
+    if (p->prec != SPH_FP64 && p->prec != SPH_FP32_SPLIT) return fail(SPH_ERR_ARG, "unknown precision %d", p->prec);
+    if (!bar) return fail(SPH_ERR_ARG, "bar is NULL");
+    if (!std::isfinite(scale)) return fail(SPH_ERR_ARG, "scale is not finite");
+    if (objective == SPH_OBJ_KINETIC_ENERGY) {
+        if (p->n > 0 && (!p->v[0] || !p->v[1] || !p->v[2] || !p->m)) return fail(SPH_ERR_ARG, "p.v or p.m is NULL");
+        if (!bar->v[0] || !bar->v[1] || !bar->v[2] || !bar->m) return fail(SPH_ERR_ARG, "bar.v or bar.m is NULL");
+    } else {
+        if (ntag == 0) return fail(SPH_ERR_ARG, "no tagged particle (ntag = 0)");
+        if (p->n > 0 && !p->id) return fail(SPH_ERR_ARG, "p.id is NULL");
+        if (tag_len > 0 && !tag) return fail(SPH_ERR_ARG, "tag is NULL");
+        if (!bar->x[2]) return fail(SPH_ERR_ARG, "bar.x[2] is NULL");
+    }
+    if (p->n == 0) return SPH_OK;
+    return hip_status(launch_objective_adjoint(p->prec, objective, *p, tag, tag_len, ntag, scale, *bar,
+                                               (hipStream_t)stream),
+                      "sph_objective_adjoint");
 }
 
 int sph_permute_adjoint(int prec, uint32_t n, const uint32_t *perm, const sph_adjoint *in, const sph_adjoint *out,

@@ -290,6 +290,60 @@ __global__ __launch_bounds__(kBlock) void k_permute(uint32_t n, const uint32_t *
     if (in.ep) out.ep[d] = ep;
 }
 
+// Seed of a reverse pass: the cotangent of the objective with respect to the
+// final state, scaled by `scale`; every non-NULL field of bar is written.
+// Kinetic energy J = sum m |v|^2 / 2: v-bar = scale m v, m-bar = scale |v|^2 / 2.
+// Tagged mean z: z-bar = scale / ntag (stag) on the particles whose id is
+// tagged.  FP64 arithmetic, rounded once to the form's precision.
+template <typename real>
+__global__ __launch_bounds__(kBlock) void k_seed(int objective, PV<real> s, const uint8_t *__restrict__ tag,
+                                                 uint32_t tag_len, double stag, double scale, AV<real> bar)
+{
+#pragma clang fp contract(off)
+    const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= s.n) return;
+    double vb[3] = {0.0, 0.0, 0.0}, mb = 0.0, zb = 0.0;
+    if (objective == SPH_OBJ_KINETIC_ENERGY) {
+        const double v[3] = {(double)s.v[0][i], (double)s.v[1][i], (double)s.v[2][i]};
+        const double sm = scale * (double)s.m[i];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) vb[d] = sm * v[d];
+        mb = scale * 0.5 * ((v[0] * v[0] + v[1] * v[1]) + v[2] * v[2]);
+    } else {
+        const uint32_t id = s.id[i];
+        zb = (id < tag_len && tag[id]) ? stag : 0.0;
+    }
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        if (bar.x[d]) bar.x[d][i] = (real)(d == 2 ? zb : 0.0);
+        if (bar.v[d]) bar.v[d][i] = (real)vb[d];
+    }
+    if (bar.m) bar.m[i] = (real)mb;
+    real *zero[] = {bar.w, bar.E, bar.rho, bar.p, bar.c, bar.e, bar.S[0], bar.S[1], bar.S[2], bar.S[3], bar.S[4],
+                    bar.S[5], bar.ep};
+#pragma unroll
+    for (int k = 0; k < 13; ++k)
+        if (zero[k]) zero[k][i] = real(0);
+}
+
+// Reverse of taking the velocities as the input at fixed specific internal
+// energy (E = e + |v|^2 / 2 with e held): v-bar += E-bar v, in place.
+template <typename real>
+__global__ __launch_bounds__(kBlock) void k_input_v_adj(PV<real> s, AV<real> bar)
+{
+    const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= s.n) return;
+    const double Eb = (double)bar.E[i];
+    double v[3], vb[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        v[d] = (double)s.v[d][i];
+        vb[d] = (double)bar.v[d][i];
+    }
+#pragma unroll
+    for (int d = 0; d < 3; ++d) bar.v[d][i] = (real)(vb[d] + Eb * v[d]);
+}
+
 template <typename real>
 hipError_t go(const Params &P, int stage, const sph_particles &p, const sph_rates &r, const double *dt,
               const sph_adjoint &bar, const sph_rates &rbar, double *pbar, const Workspace &ws, hipStream_t s)
@@ -304,6 +358,8 @@ hipError_t go(const Params &P, int stage, const sph_particles &p, const sph_rate
         if (blocks)
             k_stress_adj<real, SPLIT><<<blocks, kBlock, 0, s>>>(P, view<real>(p), view<real>(r), dt, view<real>(bar),
                                                                 view<real>(rbar));
+    } else if (stage == SPH_STAGE_INPUT_VELOCITY) {
+        if (blocks) k_input_v_adj<real><<<blocks, kBlock, 0, s>>>(view<real>(p), view<real>(bar));
     } else {
         if (blocks) k_eos_adj<real><<<blocks, kBlock, 0, s>>>(P, view<real>(p), view<real>(bar), ws.partials);
         k_sum_into<<<1, kBlock, 0, s>>>(ws.partials, blocks, pbar);
@@ -319,6 +375,21 @@ hipError_t launch_integrate_adjoint(const Params &P, int prec, int stage, const 
 {
     if (prec == SPH_FP64) return go<double>(P, stage, p, r, dt, bar, rbar, pbar, ws, s);
     return go<float>(P, stage, p, r, dt, bar, rbar, pbar, ws, s);
+}
+
+hipError_t launch_objective_adjoint(int prec, int objective, const sph_particles &p, const uint8_t *tag,
+                                    uint32_t tag_len, uint32_t ntag, double scale, const sph_adjoint &bar,
+                                    hipStream_t s)
+{
+    const uint32_t blocks = div_up(p.n, kBlock);
+    const double stag = ntag ? scale / (double)ntag : 0.0;
+    if (prec == SPH_FP64)
+        k_seed<double><<<blocks, kBlock, 0, s>>>(objective, view<double>(p), tag, tag_len, stag, scale,
+                                                 view<double>(bar));
+    else
+        k_seed<float><<<blocks, kBlock, 0, s>>>(objective, view<float>(p), tag, tag_len, stag, scale,
+                                                view<float>(bar));
+    return hipGetLastError();
 }
 
 hipError_t launch_permute_adjoint(int prec, uint32_t n, const uint32_t *perm, const sph_adjoint &in,

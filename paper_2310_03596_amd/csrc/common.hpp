@@ -342,6 +342,9 @@ hipError_t launch_balance_select_types(uint32_t n, const uint8_t *type, uint32_t
                                        uint32_t hmax, const uint32_t *npos_own, const uint32_t *npos_other,
                                        uint32_t *sel, uint32_t *k_out, uint32_t *off, const Workspace &ws,
                                        hipStream_t s);
+hipError_t launch_objective_adjoint(int prec, int objective, const sph_particles &p, const uint8_t *tag,
+                                    uint32_t tag_len, uint32_t ntag, double scale, const sph_adjoint &bar,
+                                    hipStream_t s);
 hipError_t launch_permute_adjoint(int prec, uint32_t n, const uint32_t *perm, const sph_adjoint &in,
                                   const sph_adjoint &out, hipStream_t s);
 

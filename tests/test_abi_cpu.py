@@ -317,6 +317,45 @@ def test_integrate_and_adjoint_reject_bad_arguments():
     assert "must be below 134217728" in _last()
 
 
+def test_objective_adjoint_rejects_bad_arguments():
+    lib = L.load()
+    p = _particles(10)
+    full = L.SphAdjoint()
+    for d in range(3):
+        full.x[d] = full.v[d] = FAKE
+    for f in ("m", "omega", "E", "rho", "p", "c", "e"):
+        setattr(full, f, FAKE)
+    KE, TZ = L.SPH_OBJ_KINETIC_ENERGY, L.SPH_OBJ_TAGGED_MEAN_Z
+
+    def seed(obj, q=p, tag=None, tag_len=0, ntag=0, scale=1.0, b=full):
+        return lib.sph_objective_adjoint(obj, C.byref(q), tag, tag_len, ntag, scale,
+                                         None if b is None else C.byref(b), None)
+
+    assert seed(7) == L.SPH_ERR_ARG
+    assert "unknown objective" in _last()
+    assert seed(KE, b=None) == L.SPH_ERR_ARG
+    assert seed(KE, scale=float("nan")) == L.SPH_ERR_ARG
+    assert seed(KE, b=L.SphAdjoint()) == L.SPH_ERR_ARG
+    assert "bar.v or bar.m" in _last()
+    q = _particles(10)
+    q.m = None
+    assert seed(KE, q) == L.SPH_ERR_ARG
+    assert seed(TZ, tag=FAKE, tag_len=10, ntag=0) == L.SPH_ERR_ARG
+    assert "ntag = 0" in _last()
+    assert seed(TZ, tag=None, tag_len=10, ntag=2) == L.SPH_ERR_ARG
+    q = _particles(10)
+    q.id = None
+    assert seed(TZ, q, FAKE, 10, 2) == L.SPH_ERR_ARG
+    # no particles: nothing to do
+    assert seed(KE, _particles(0, full=False)) == L.SPH_OK
+    # the input-velocity stage reads bar.v and bar.E; unknown stages are refused
+    assert lib.sph_integrate_adjoint(C.byref(_params()), L.SPH_STAGE_INPUT_VELOCITY, C.byref(p), None, None,
+                                     C.byref(L.SphAdjoint()), None, None, None, 0, None) == L.SPH_ERR_ARG
+    assert lib.sph_integrate_adjoint(C.byref(_params()), 9, C.byref(p), None, None, C.byref(full), None, None,
+                                     None, 0, None) == L.SPH_ERR_ARG
+    assert "unknown adjoint stage" in _last()
+
+
 def test_zero_particles_is_a_noop():
     lib = L.load()
     g = _grid()

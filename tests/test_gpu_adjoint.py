@@ -34,6 +34,76 @@ def small_box(n_side=6, seed=80):
     return w
 
 
+@pytest.mark.parametrize("prec", [FP64, FP32])
+def test_objective_seed_and_input_stage_match_their_definitions(prec):
+    """The two ends of a reverse pass against their definitions on a sorted
+    random state (ids out of array order, 1,728 particles: several workgroups
+    and a ragged one).  sph_objective_adjoint overwrites every cotangent
+    field: kinetic energy v-bar = s m v, m-bar = s |v|^2 / 2; tagged mean z
+    z-bar = s / ntag on the tagged ids (ids at or above the tag table's
+    length untagged); everything else 0.  Both are FP64 arithmetic rounded
+    once, equal to NumPy's evaluation in the same order.  The INPUT_VELOCITY
+    stage adds E-bar v to v-bar, within two roundings of the form's
+    precision of |v-bar| + |E-bar v| (the kernel may fuse the multiply-add);
+    E-bar is left as it was."""
+    from paper_2310_03596_amd import _lib as L
+    from paper_2310_03596_amd.adjoint import Cotangent
+    from paper_2310_03596_amd.sim import Sim
+    from paper_2310_03596_amd.state import stream_handle
+    wl = small_box(12, seed=81)
+    n = wl.n
+    print(f"[objective seed] n={n} prec={prec}", flush=True)
+    sim = Sim(wl, prec)
+    sim.build()
+    torch.cuda.synchronize()
+    h = sim.A.host()
+    assert not np.array_equal(h["id"], np.arange(n))
+    nd = np.float64 if prec == FP64 else np.float32
+    st = stream_handle()
+    s = -1.75
+    bar = Cotangent(n, prec, "cuda", solid=True)
+    def poison():
+        for t in (bar.x, bar.v, bar.m, bar.w, bar.E, bar.rho, bar.p, bar.c, bar.e, bar.S, bar.ep):
+            t.fill_(7.0)
+
+    poison()
+    L.sph_objective_adjoint(L.SPH_OBJ_KINETIC_ENERGY, sim.A.struct(), None, 0, 0, s, bar.struct(), st)
+    torch.cuda.synchronize()
+    v, m = h["v"].astype(np.float64), h["m"].astype(np.float64)
+    assert np.array_equal(bar.v.cpu().numpy().T, ((s * m)[:, None] * v).astype(nd))
+    assert np.array_equal(bar.m.cpu().numpy(), (s * 0.5 * ((v[:, 0] * v[:, 0] + v[:, 1] * v[:, 1])
+                                                            + v[:, 2] * v[:, 2])).astype(nd))
+    for t in (bar.x, bar.w, bar.E, bar.rho, bar.p, bar.c, bar.e, bar.S, bar.ep):
+        assert not t.cpu().numpy().any()
+    # tagged mean z, with a tag table shorter than the ids: ids 400 and n - 1 fall outside it
+    tag_ids = np.array([3, 17, 399, 400, n - 1])
+    flags = torch.zeros(n, dtype=torch.uint8, device="cuda")
+    flags[torch.as_tensor(tag_ids, device="cuda")] = 1
+    poison()
+    L.sph_objective_adjoint(L.SPH_OBJ_TAGGED_MEAN_Z, sim.A.struct(), flags.data_ptr(), 400, 3, s, bar.struct(), st)
+    torch.cuda.synchronize()
+    hit = np.isin(h["id"], tag_ids[:3])
+    assert hit.sum() == 3
+    assert np.array_equal(bar.x[2].cpu().numpy(), np.where(hit, s / 3, 0.0).astype(nd))
+    for t in (bar.x[:2], bar.v, bar.m, bar.w, bar.E, bar.rho, bar.p, bar.c, bar.e, bar.S, bar.ep):
+        assert not t.cpu().numpy().any()
+    # the input-velocity stage
+    g = torch.Generator(device="cpu").manual_seed(82)
+    vb0 = torch.randn((3, n), generator=g, dtype=torch.float64).to(bar.v.dtype)
+    Eb0 = torch.randn(n, generator=g, dtype=torch.float64).to(bar.E.dtype)
+    bar.v.copy_(vb0)
+    bar.E.copy_(Eb0)
+    L.sph_integrate_adjoint(sim.params, L.SPH_STAGE_INPUT_VELOCITY, sim.A.struct(), None, None, bar.struct(), None,
+                            None, None, 0, st)
+    torch.cuda.synchronize()
+    vb, Eb = vb0.double().numpy(), Eb0.double().numpy()
+    got = bar.v.double().cpu().numpy()
+    prod = Eb[None, :] * v.T
+    bound = 2 * np.finfo(nd).eps * (np.abs(vb) + np.abs(prod))
+    assert (np.abs(got - (vb + prod)) <= bound).all()
+    assert np.array_equal(bar.E.cpu().numpy(), Eb0.numpy())
+
+
 def _rollout(w, prec, nsteps, ckpt, dt):
     from paper_2310_03596_amd.adjoint import KineticEnergyRollout
     return KineticEnergyRollout(w, prec, nsteps, ckpt, dt)
