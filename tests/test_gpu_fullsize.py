@@ -139,3 +139,45 @@ def test_share_full_size(layout):
     check_census(c_ll, s_ll, tidx, hl["x"][tidx], hl["x"], hl["id"], hh, FP32, f"share {layout} local-local sample")
     tb = tidx[inB]
     check_census(c_lr, s_lr, tb, hl["x"][tb], hr["x"], hr["id"], hh, FP32, f"share {layout} local-remote sample")
+
+
+@pytest.mark.parametrize("prec", [FP32, FP64])
+def test_largest_array_the_pair_pass_takes(prec):
+    """511^3 = 133,432,831 particles, just below the 2^27 sources the pair
+    pass takes (its staged records are read at 32-bit byte offsets, here up
+    to 2^32 - 32): the bucket sort (three 8-bit passes over 7.6 M buckets),
+    its permutation, table and hashes whole against the oracle, and the
+    FORCE pass on the last 512 targets of the sorted array (whose sources
+    sit at the top of the records) and 1,536 others drawn at random."""
+    from paper_2310_03596_amd.sim import Sim
+    wl = S.jittered_lattice(511, seed=92, dx=1e-3, jitter=0.05, v_sigma=0.5, rho_sigma=0.01)
+    n = wl.n
+    assert n < 1 << 27
+    print(f"[largest] n={n} prec={prec} buckets={cpu.ncells(wl.grid)}", flush=True)
+    sim = Sim(wl, prec)
+    sim.build()
+    sim.interact()
+    torch.cuda.synchronize()
+    print("[largest] device build and FORCE pass done", flush=True)
+    s = cpu.State.from_workload(wl)
+    o, operm, ostart = cpu.build_cells(wl.grid, s)
+    del s
+    assert np.array_equal(sim.perm.cpu().numpy().view(np.uint32), operm)
+    assert np.array_equal(sim.start.cpu().numpy().view(np.uint32), ostart)
+    ohash = o.hash
+    del o, operm
+    h = sim.A.host()
+    assert np.array_equal(h["hash"], ohash)
+    del ohash
+    st = oracle_state(h, False)
+    del h
+    print("[largest] build equal to the oracle's", flush=True)
+    tidx = np.union1d(np.arange(n - 512, n), _sample(n - 512, 1536, 93)).astype(np.uint32)
+    ref = cpu.interact(wl.params, wl.grid, cpu.FORCE, st, st, ostart, True, tidx=tidx)[tidx]
+    bound = rate_bound(wl.params, wl.grid, cpu.FORCE, st, st, ostart, True, prec, tidx=tidx)[tidx]
+    idx = torch.as_tensor(tidx.astype(np.int64), device="cuda")
+    r = sim.rates
+    got = r.hi[:, idx].double()
+    if r.lo is not None:
+        got = got + r.lo[:, idx].double()
+    assert_within(got.T.cpu().numpy(), ref, bound, "largest array: rates (sample)")
