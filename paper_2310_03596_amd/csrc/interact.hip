@@ -105,6 +105,9 @@ __device__ inline unsigned long long mix64(uint32_t id)
     z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
     return z ^ (z >> 31);
 }
+#ifndef SPH_PAIR_MX
+#define SPH_PAIR_MX 1   // the FP64 fluid FORCE pass over every target filters on the matrix cores (k_pairs_mx)
+#endif
 #ifndef SPH_PAIR_WAVES_PER_EU
 #define SPH_PAIR_WAVES_PER_EU 4
 #endif
@@ -192,15 +195,16 @@ __device__ inline int wave_max(int v)
 // contiguous range of the sorted array, and a wavefront whose targets span
 // two rows walks the neighbour rows of each in turn with the other lanes
 // idle.  For a pass over every target of a sorted array, one workgroup
-// lists (first target, count) for wavefronts that each take up to 64
-// targets of a single row, rows in order (on the column workload: 13,183 row
-// walks instead of 14,243).  plan holds at most ceil(n / 64) + rows entries;
+// lists (first target, count) for wavefronts that each take up to `chunk`
+// (64, or 32 for the two-lane targets of k_pairs_mx) targets of a single
+// row, rows in order (on the column workload, chunks of 64: 13,183 row walks
+// instead of 14,243).  plan holds at most ceil(n / chunk) + rows entries;
 // *nplan receives their number.  The staging kernel runs this as its first
 // workgroup, so the plan's latency hides behind the staging.
 constexpr int kPlanBlock = kBlock;
 constexpr int kPlanRows = 8;   // consecutive rows per thread in one chunk of the plan
 __device__ inline void wave_plan_block(const Grid &g, const uint32_t *__restrict__ start, uint2 *__restrict__ plan,
-                                       uint32_t *__restrict__ nplan)
+                                       uint32_t *__restrict__ nplan, uint32_t chunk)
 {
     __shared__ uint32_t wsum[kPlanBlock / kWave];
     const uint32_t nx = (uint32_t)g.nx, nrows = (uint32_t)g.ny * (uint32_t)g.nz;
@@ -219,7 +223,7 @@ __device__ inline void wave_plan_block(const Grid &g, const uint32_t *__restrict
         }
         uint32_t w = 0;
 #pragma unroll
-        for (int k = 0; k < kPlanRows; ++k) w += (bnd[k + 1] - bnd[k] + kWave - 1) / kWave;
+        for (int k = 0; k < kPlanRows; ++k) w += (bnd[k + 1] - bnd[k] + chunk - 1) / chunk;
         // exclusive scan of w over the block (wavefront scan, then wavefront totals)
         uint32_t inc = w;
 #pragma unroll
@@ -240,9 +244,9 @@ __device__ inline void wave_plan_block(const Grid &g, const uint32_t *__restrict
 #pragma unroll
         for (int k = 0; k < kPlanRows; ++k) {
             const uint32_t b = bnd[k], len = bnd[k + 1] - bnd[k];
-            for (uint32_t m = 0; m * (uint32_t)kWave < len; ++m) {
-                const uint32_t left = len - m * (uint32_t)kWave;
-                plan[q++] = make_uint2(b + m * (uint32_t)kWave, left < (uint32_t)kWave ? left : (uint32_t)kWave);
+            for (uint32_t m = 0; m * chunk < len; ++m) {
+                const uint32_t left = len - m * chunk;
+                plan[q++] = make_uint2(b + m * chunk, left < chunk ? left : chunk);
             }
         }
         carry += tot;
@@ -253,11 +257,11 @@ __device__ inline void wave_plan_block(const Grid &g, const uint32_t *__restrict
 // Packs the pair inputs of every source particle (see Stage).
 template <typename real, bool SOLID>
 __global__ __launch_bounds__(kBlock) void k_stage(Grid g, PV<real> s, Stage<real> st, const uint32_t *pstart,
-                                                  uint2 *plan, uint32_t *nplan)
+                                                  uint2 *plan, uint32_t *nplan, uint32_t chunk)
 {
     constexpr bool SPLIT = sizeof(real) == 4;
     if (plan && blockIdx.x == 0) {
-        wave_plan_block(g, pstart, plan, nplan);
+        wave_plan_block(g, pstart, plan, nplan, chunk);
         return;
     }
     uint32_t j = (blockIdx.x - (plan ? 1u : 0u)) * kBlock + threadIdx.x;
@@ -788,6 +792,298 @@ void k_pairs(Params P, Grid g, PV<real> tg, const uint32_t *__restrict__ tidx, c
     }
 }
 
+// The FORCE pass of a fluid over every target of a sorted array, with the
+// neighbour filter on the matrix cores.  A wavefront takes up to 32 targets
+// of one bucket row (the row-aligned plan cut into chunks of 32), two lanes
+// per target: lane t and lane t + 32.  For each of the 9 neighbour rows the
+// sources of the union of its targets' buckets are tested 32 at a time: the
+// shortlist value |q|^2 - 2 q.f of every (source, target) pair of a block is
+// one 32 x 32 x 4 matrix product, two v_mfma_f32_32x32x2f32 (A: the sources'
+// (-2q, |q|^2), B: the targets' (f, 1)), in the FP32 frame of the VALU
+// filter and against the same widened bound (the product's rounding, within
+// two units of 2^-24 of the sum of the terms' magnitudes when measured, is
+// far inside that margin).  Lane (t, h) receives the values of the block's
+// sources 8m + 4h + r (m, r < 4) for target t and keeps one bit for each;
+// the hits are evaluated from these bit masks in one flat loop per lane (so
+// a lane's hits in different rows do not wait for each other), and the two
+// lanes of a target add their sums at the end.  No per-candidate LDS traffic
+// and about three vector instructions per 64 candidate tests, where the VALU
+// filter spends eight and a page read; but every target is tested against
+// the union of the wavefront's buckets (about 1.8 times its own 27), and two
+// lanes per target balance their hits less evenly than one, so it pays in
+// the FP64 form only (whose pair evaluation and staging cost more per hit).
+constexpr int kMxWaves = 4;      // wavefronts per workgroup
+constexpr int kMxTargets = 32;   // targets per wavefront
+constexpr int kMxWords = 24;     // bit-mask words a lane holds before its hits are evaluated
+typedef float mx16 __attribute__((ext_vector_type(16)));
+
+template <typename real, bool CENSUS>
+__global__ __launch_bounds__(kMxWaves * kWave)
+__attribute__((amdgpu_waves_per_eu(sizeof(real) == 4 ? SPH_PAIR_WAVES_PER_EU : 3)))
+void k_pairs_mx(Params P, Grid g, PV<real> tg, Stage<real> src, const uint32_t *__restrict__ sstart,
+                int zero_first, RV<real> R, const uint2 *__restrict__ plan, const uint32_t *__restrict__ nplan,
+                Census cz)
+{
+    using v4 = typename Vec4<real>::type;
+    constexpr bool SPLIT = sizeof(real) == 4;
+    constexpr int NOUT = CENSUS ? 1 : 6;
+    // one word of a lane's bit masks covers two blocks of one row: the first
+    // block's first source and the row's (c_j - c_i) L in y and z
+    struct alignas(16) Slot {
+        uint32_t base;
+        float dy, dz, pad;
+    };
+    __shared__ uint32_t bits[kMxWaves][kMxWords][kWave];
+    __shared__ Slot slots[kMxWaves][kMxWords];
+
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    const int tl = lane & (kMxTargets - 1), half = lane / kMxTargets;
+    const uint32_t wid = xcd_tile(blockIdx.x, gridDim.x) * kMxWaves + wave;
+    if (wid >= *nplan) return;   // whole wavefronts beyond the plan leave
+    const uint2 pd = plan[wid];
+    const bool valid = (uint32_t)tl < pd.y;
+    const uint32_t i = pd.x + (valid ? (uint32_t)tl : 0u);   // idle lanes shadow the first target
+
+    const PairK<real> K = make_pair_k<real>(P);
+    const real R2 = (real)P.R2;
+    const uint32_t h = tg.hash[i];
+    const int cx = (int)(h % (uint32_t)g.nx);
+    // one row for the whole wavefront, its targets in ascending x bucket
+    const uint32_t key = __builtin_amdgcn_readfirstlane(h / (uint32_t)g.nx);
+    const int gx0 = __builtin_amdgcn_readfirstlane(cx);
+    const int gx1 = wave_max(valid ? cx : gx0);
+    const int gy = (int)(key % (uint32_t)g.ny), gz = (int)(key / (uint32_t)g.ny);
+
+    TargetPos<real> T;
+    T.cxf = (real)cx;
+    T.Lf = SPLIT ? (real)g.Lf : real(0);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        if constexpr (SPLIT) {
+            T.o[d] = tg.off[d][i];
+            T.x[d] = 0.0;
+        } else {
+            T.x[d] = tg.x[d][i];
+            T.o[d] = real(0);
+        }
+    }
+    Part<real, false> I;
+    if constexpr (!CENSUS) load_part<real, false>(tg, i, I);
+    Acc acc[NOUT];
+#pragma unroll
+    for (int k = 0; k < NOUT; ++k) {
+        double s0 = 0.0;
+        if constexpr (!CENSUS) {
+            if (!zero_first && valid && half == 0) {
+                s0 = (double)R.hi[k][i];
+                if (SPLIT) s0 += (double)R.lo[k][i];
+            }
+        }
+        acc[k].s = s0;
+    }
+    uint32_t ncen = 0;             // census: pairs evaluated
+    unsigned long long scen = 0;   // census: sum of mix64 of their ids
+
+    // the filter frame, margin and bound of the VALU filter (k_pairs)
+    const float kFar = 1e30f;
+    float fo[3];
+    const float gx0f = (float)gx0;
+    double corner[3] = {0.0, 0.0, 0.0};
+    if constexpr (SPLIT) {
+        fo[0] = (T.cxf - gx0f) * T.Lf + T.o[0];
+        fo[1] = T.o[1];
+        fo[2] = T.o[2];
+    } else {
+        corner[0] = uniform_double(g.o[0] + (double)gx0 * g.L);
+        corner[1] = uniform_double(g.o[1] + (double)gy * g.L);
+        corner[2] = uniform_double(g.o[2] + (double)gz * g.L);
+#pragma unroll
+        for (int d = 0; d < 3; ++d) fo[d] = (float)(T.x[d] - corner[d]);
+    }
+    const float f2 = fo[0] * fo[0] + fo[1] * fo[1] + fo[2] * fo[2];
+    const float fl = sqrtf(f2) + (float)(2.0 * P.h);
+    float margin = 0x1p-16f * fl * fl;
+    if constexpr (!SPLIT) {
+        const float X = (float)(fabs(corner[0]) + fabs(corner[1]) + fabs(corner[2])) + fl;
+        margin += 0x1p-46f * X * fl;
+    }
+    const float Tl = valid ? ((float)R2 - f2) + margin : -kFar;
+    // B operands: component h, then 2 + h, of the lane's target (f, 1)
+    const float b1 = half ? fo[1] : fo[0];
+    const float b2 = half ? 1.0f : fo[2];
+
+    // Records of one hit; the next hit's are loaded while the current pair
+    // is evaluated.
+    struct Rec {
+        v4 p, a, b;
+        real qy, qz;
+        uint32_t j;
+    };
+    int nslot = 0;   // words recorded (the same in every lane)
+    int cnt = 0;     // hits recorded by this lane
+    // the lane's walk over its recorded bits: current word and what is left
+    int cs = -1, left = 0;
+    uint32_t w = 0, jlast = i;
+    float dylast = 0.0f, dzlast = 0.0f;
+    auto fetch = [&]() {
+        if (left > 0) {
+            while (w == 0) w = bits[wave][++cs][lane];   // a later word holds the next hit
+            const int p = __builtin_ctz(w);
+            w &= w - 1u;
+            --left;
+            const Slot sl = slots[wave][cs];
+            const int rr = p & 15;
+            jlast = sl.base + 32u * (uint32_t)(p >> 4) + 8u * (uint32_t)(rr >> 2) + 4u * (uint32_t)half +
+                    (uint32_t)(rr & 3);
+            dylast = sl.dy;
+            dzlast = sl.dz;
+        }
+        // past the lane's last hit the last record is read again (never evaluated)
+        Rec q;
+        q.j = jlast;
+        q.qy = SPLIT ? (real)dylast : real(0);
+        q.qz = SPLIT ? (real)dzlast : real(0);
+        const uint32_t ob = jlast * (uint32_t)sizeof(v4);
+        auto at = [&](const v4 *base, uint32_t o) { return *reinterpret_cast<const v4 *>(reinterpret_cast<const char *>(base) + o); };
+        q.p = at(src.pos, ob);
+        if constexpr (!CENSUS) {
+            const uint32_t ob2 = ob * rec_stride<real>;
+            q.a = at(src.va, ob2);
+            q.b = at(src.vb, ob2);
+        }
+        return q;
+    };
+    auto eval = [&](const Rec &cur) {
+        real d[3];
+        diff<real>(T, cur.p, cur.qy, cur.qz, d);
+        const real r2 = r2_of<real>(d);
+        if (!(r2 < R2)) {
+            // outside the support: nothing to add
+        } else if constexpr (CENSUS) {
+            ++ncen;
+            scen += mix64(cz.sid[cur.j]);
+        } else {
+            Part<real, false> J;
+            J.v[0] = cur.a.x;
+            J.v[1] = cur.a.y;
+            J.v[2] = cur.a.z;
+            J.w = cur.a.w;
+            J.rho = cur.b.x;
+            J.p = cur.b.y;
+            J.c = cur.b.z;
+            J.e = cur.b.w;
+            real o[6];
+            pair_force<real, false>(d, r2, I, J, K, o);
+#pragma unroll
+            for (int k = 0; k < 6; ++k) acc[k].add(o[k]);
+        }
+    };
+    // evaluate every recorded hit, two at a time in flight, then start over
+    auto flush = [&]() {
+        wave_lds_sync();   // the words and slots written are visible to every lane
+        const int nmax = wave_max(cnt);
+        if (nmax > 0) {
+            cs = -1;
+            left = cnt;
+            w = 0;
+            Rec A = fetch();
+            Rec B = fetch();
+            for (int s = 0; s < nmax; s += 2) {
+                if (s < cnt) eval(A);
+                A = fetch();
+                if (s + 1 < cnt) eval(B);
+                B = fetch();
+            }
+        }
+        cnt = 0;
+        nslot = 0;
+        wave_lds_sync();   // every read of the words is done before they are rewritten
+    };
+
+    uint32_t word = 0, wbase = 0;
+    bool open = false;   // a word holds one block and waits for the next
+    float wdy = 0.0f, wdz = 0.0f;
+    auto commit = [&]() {
+        bits[wave][nslot][lane] = word;
+        if (lane == 0) slots[wave][nslot] = Slot{wbase, wdy, wdz, 0.0f};
+        cnt += __popc(word);
+        ++nslot;
+        open = false;
+    };
+    const int xa = gx0 > 0 ? gx0 - 1 : 0;
+    const int xb = gx1 + 1 < g.nx ? gx1 + 1 : g.nx - 1;
+    for (int r = 0; r < 9; ++r) {
+        const int dz = r / 3 - 1, dy = r % 3 - 1;
+        const int z = gz + dz, y = gy + dy;
+        if (z < 0 || z >= g.nz || y < 0 || y >= g.ny) continue;
+        const uint32_t row = (uint32_t)g.nx * ((uint32_t)y + (uint32_t)g.ny * (uint32_t)z);
+        const uint32_t ub = sstart[row + xa], ue = sstart[row + xb + 1];
+        const float ddy = SPLIT ? (float)((real)dy * T.Lf) : 0.0f;
+        const float ddz = SPLIT ? (float)((real)dz * T.Lf) : 0.0f;
+        for (uint32_t b0 = ub; b0 < ue; b0 += 32u) {
+            // A operands: component h, then 2 + h, of source b0 + t's (-2q, |q|^2);
+            // past the row's end a far sentinel that no target takes
+            const uint32_t sj = b0 + (uint32_t)tl;
+            float a1 = 0.0f, a2 = half ? kFar : 0.0f;
+            if (sj < ue) {
+                const v4 pp = src.pos[sj];
+                float q0, q1, q2;
+                if constexpr (SPLIT) {
+                    q0 = (pp.w - gx0f) * T.Lf + pp.x;
+                    q1 = ddy + pp.y;
+                    q2 = ddz + pp.z;
+                } else {
+                    q0 = (float)(pp.x - corner[0]);
+                    q1 = (float)(pp.y - corner[1]);
+                    q2 = (float)(pp.z - corner[2]);
+                }
+                a1 = -2.0f * (half ? q1 : q0);
+                a2 = half ? q0 * q0 + q1 * q1 + q2 * q2 : -2.0f * q2;
+            }
+            mx16 c = {};
+            c = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b1, c, 0, 0, 0);
+            c = __builtin_amdgcn_mfma_f32_32x32x2f32(a2, b2, c, 0, 0, 0);
+            uint32_t m16 = 0;
+#pragma unroll
+            for (int k = 15; k >= 0; --k) m16 = m16 + m16 + (c[k] < Tl ? 1u : 0u);
+            if (!open) {
+                if (nslot == kMxWords) flush();
+                word = m16;
+                wbase = b0;
+                wdy = ddy;
+                wdz = ddz;
+                open = true;
+            } else {
+                word |= m16 << 16;
+                commit();
+            }
+        }
+        if (open) commit();
+    }
+    flush();
+
+    // the two lanes of a target add their sums; lane t writes
+    if constexpr (CENSUS) {
+        ncen += __shfl_xor(ncen, kMxTargets, kWave);
+        scen += __shfl_xor(scen, kMxTargets, kWave);
+        if (valid && half == 0) {
+            cz.count[i] = ncen;
+            cz.sum[i] = scen;
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < 6; ++k) acc[k].s += __shfl_xor(acc[k].s, kMxTargets, kWave);
+        if (valid && half == 0) {
+#pragma unroll
+            for (int k = 0; k < 6; ++k) {
+                const real hv = (real)acc[k].s;
+                R.hi[k][i] = hv;
+                if (SPLIT) R.lo[k][i] = (real)(acc[k].s - (double)hv);
+            }
+        }
+    }
+}
+
 // Adjoint pass: the sources' rate cotangents in the two spare records
 // (zeros when the sources' rates have no cotangent: rb.hi[0] == NULL).
 template <typename real>
@@ -921,20 +1217,29 @@ hipError_t go(const Params &P, const Grid &g, const sph_particles &tg, const uin
     // (Measured: the FP32 column's FORCE pass 5 % faster; the solid
     // workloads' steps 4-7 % slower with it, so their passes keep 64
     // consecutive targets per wavefront.)
+    // The FP64 form's fluid FORCE pass (and its census) over every target
+    // takes the matrix-core filter (k_pairs_mx, two lanes per target: chunks
+    // of 32).  Measured on the column: FP64 605 us against 651 with the VALU
+    // filter; FP32 361 against 353, so the FP32 form keeps the VALU filter.
+    constexpr bool MX_PASS = !SOLID && (PASS == SPH_PASS_FORCE || PASS == kPassCensus) && sizeof(real) == 8 &&
+                             SPH_PAIR_MX;
+    const bool mx = MX_PASS && !census_of_gradient && self && !tidx;
+    const uint32_t chunk = mx ? (uint32_t)kMxTargets : (uint32_t)kWave;
     const uint64_t nrows = (uint64_t)g.ny * (uint64_t)g.nz;
-    const uint64_t pmax = div_up(tg.n, kWave) + nrows;
+    const uint64_t pmax = div_up(tg.n, chunk) + nrows;
     // (the workspace's key buffers hold 4 bytes for each of the sources->n
     // particles it was sized for)
     if (!SOLID && PASS != SPH_PASS_GRADIENT && PASS != kPassGradAdjoint && !census_of_gradient && self && !tidx &&
         pmax * sizeof(uint2) <= 4ull * sr.n) {
         plan = reinterpret_cast<uint2 *>(ws.keys[0]);
         nplan = ws.keys[1];
-        blocks = div_up(pmax, kWaves);
+        blocks = div_up(pmax, mx ? kMxWaves : kWaves);
     }
+    const bool use_mx = mx && plan;
     if (sr.n > 0) {
         // one more workgroup (the first) builds the wavefront plan
         k_stage<real, SOLID><<<div_up(sr.n, kBlock) + (plan ? 1 : 0), kBlock, 0, s>>>(g, view<real>(sr), st, sstart,
-                                                                                    plan, nplan);
+                                                                                    plan, nplan, chunk);
         if constexpr (ADJ) {
             const sph_rates none{};
             const RV<real> rs = view<real>(rsrc ? *rsrc : none);
@@ -949,6 +1254,16 @@ hipError_t go(const Params &P, const Grid &g, const sph_particles &tg, const uin
     if (ev_begin && ev_end) {
         const hipError_t e = hipEventRecord(ev_begin, s);
         if (e != hipSuccess) return e;
+    }
+    if constexpr (MX_PASS) {
+        if (use_mx) {
+            k_pairs_mx<real, PASS == kPassCensus><<<blocks, kMxWaves * kWave, 0, s>>>(
+                P, g, view<real>(tg), st, sstart, zero_first, view<real>(r), plan, nplan, cz);
+            const hipError_t le = hipGetLastError();
+            if (le != hipSuccess) return le;
+            if (ev_begin && ev_end) return hipEventRecord(ev_end, s);
+            return hipSuccess;
+        }
     }
     if (self)
         k_pairs<real, PASS, SOLID, true><<<blocks, kPairBlock, 0, s>>>(P, g, view<real>(tg), tidx, nt, st, sstart,
