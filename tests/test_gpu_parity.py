@@ -230,6 +230,31 @@ def test_force_pass_matches_oracle(case, prec):
 
 
 @pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("case", ["cloud2049", "dense"])
+def test_force_pass_continues_its_sums(case, prec):
+    """zero_first = 0 on a pass over every target (the FP64 form's
+    matrix-filter kernel, the FP32 form's VALU filter): the second pass adds
+    its terms to the sums the first left, so the rates are twice the
+    oracle's, within twice the one-pass bound."""
+    from paper_2310_03596_amd import _lib as L
+    from paper_2310_03596_amd.state import stream_handle
+    wl = CASES[case]()
+    print(f"[force continue] case={case} prec={prec} n={wl.n}", flush=True)
+    sim = _sim(wl, prec)
+    sim.build()
+    sim.interact()
+    a = sim.A.struct()
+    L.sph_interact(sim.params, sim.grid, L.SPH_PASS_FORCE, a, None, None, a, sim.cells, 0, sim.rates.struct(),
+                   sim.ws.data_ptr(), sim.ws_bytes, stream_handle())
+    torch.cuda.synchronize()
+    st = oracle_state(sim.A.host(), False)
+    start = cpu.cell_start(st.hash, cpu.ncells(wl.grid))
+    ref = cpu.interact(wl.params, wl.grid, cpu.FORCE, st, st, start, True)
+    bound = rate_bound(wl.params, wl.grid, cpu.FORCE, st, st, start, True, prec)
+    assert_within(sim.rates.force().T.cpu().numpy(), 2.0 * ref, 2.0 * bound, f"{case} rates after two passes")
+
+
+@pytest.mark.parametrize("prec", PRECS)
 def test_force_pass_conserves(prec):
     wl = S.jittered_lattice(14, seed=56, jitter=0.3, rho_sigma=0.02, v_sigma=1.0)
     sim = _sim(wl, prec)
