@@ -812,14 +812,23 @@ void k_pairs(Params P, Grid g, PV<real> tg, const uint32_t *__restrict__ tidx, c
 // the union of the wavefront's buckets (about 1.8 times its own 27), and two
 // lanes per target balance their hits less evenly than one, so it pays in
 // the FP64 form only (whose pair evaluation and staging cost more per hit).
-constexpr int kMxWaves = 4;      // wavefronts per workgroup
+// Measured on the FP64 column (FORCE launch, median of 60): 4 wavefronts
+// per workgroup 0.570 ms, 2 0.569, 8 0.665; 3 wavefronts per SIMD as set,
+// 4 spills ten registers and takes 0.646.
+#ifndef SPH_PAIR_MX_WAVES
+#define SPH_PAIR_MX_WAVES 4
+#endif
+#ifndef SPH_PAIR_MX_EU_F64
+#define SPH_PAIR_MX_EU_F64 3
+#endif
+constexpr int kMxWaves = SPH_PAIR_MX_WAVES;   // wavefronts per workgroup
 constexpr int kMxTargets = 32;   // targets per wavefront
 constexpr int kMxWords = 24;     // bit-mask words a lane holds before its hits are evaluated
 typedef float mx16 __attribute__((ext_vector_type(16)));
 
 template <typename real, bool CENSUS>
 __global__ __launch_bounds__(kMxWaves * kWave)
-__attribute__((amdgpu_waves_per_eu(sizeof(real) == 4 ? SPH_PAIR_WAVES_PER_EU : 3)))
+__attribute__((amdgpu_waves_per_eu(sizeof(real) == 4 ? SPH_PAIR_WAVES_PER_EU : SPH_PAIR_MX_EU_F64)))
 void k_pairs_mx(Params P, Grid g, PV<real> tg, Stage<real> src, const uint32_t *__restrict__ sstart,
                 int zero_first, RV<real> R, const uint2 *__restrict__ plan, const uint32_t *__restrict__ nplan,
                 Census cz)
