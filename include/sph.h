@@ -236,7 +236,9 @@ int sph_pack_boundary(const sph_particles *local, const uint32_t *boundary_idx,
  * (solids: Cauchy stress -p I + S); SPH_PASS_GRADIENT: velocity gradient L.
  * zero_first = 1 overwrites the rate entries of the targets, 0 adds to them
  * (the local-remote pass, step f, continues the sums of step e from hi + lo).
- * Summation over j runs in ascending source index.  Both arrays must be
+ * Summation over j runs in ascending source index (the FP64 fluid FORCE pass
+ * over every target: two sums, each over every other run of four sources of
+ * a row in ascending index, then added).  Both arrays must be
  * hash-sorted on `grid`.  The workspace receives a packed copy of the
  * sources' pair inputs (sized by sph_workspace_size for sources->n).
  * Errors: SPH_ERR_ARG (precision or material mismatch, missing field,

@@ -27,6 +27,12 @@
 // pair with r = 0 (the target itself, or a coincident particle) adds
 // nothing: its terms all carry F(0) = 0.
 //
+// The FP64 form's fluid FORCE pass over every target (and its census) runs
+// k_pairs_mx instead: the same frame, bound, staging and pair body, with the
+// candidate tests of 32 sources x 32 targets done as one matrix product on
+// the matrix cores and two lanes per target, each summing every other run of
+// four sources in ascending index; the two sums are then added.
+//
 // In the FP32-split form the position difference is rebuilt from bucket
 // indices and float offsets, d = (c_j - c_i) L + (off_j - off_i), which is
 // exactly odd under i <-> j and never cancels the way a difference of large
