@@ -23,6 +23,21 @@ __device__ inline uint32_t xcd_tile(uint32_t b, uint32_t n)
     const uint32_t q = n / kXcds, r = n % kXcds;
     return x * q + (x < r ? x : r) + k;
 }
+
+// The same mapping when only the first `active` tiles of a larger grid have
+// work (a grid sized for an upper bound that the device fills in): each XCD
+// takes an equal share of the active tiles, one contiguous run, and the
+// workgroups past their XCD's share get no tile (false).  With xcd_tile the
+// idle tiles would all fall on the last XCDs and leave the others a larger
+// share of the work.
+__device__ inline bool xcd_tile_active(uint32_t b, uint32_t active, uint32_t &tile)
+{
+    const uint32_t x = b % kXcds, k = b / kXcds;
+    const uint32_t q = active / kXcds, r = active % kXcds;
+    if (k >= q + (x < r ? 1u : 0u)) return false;
+    tile = x * q + (x < r ? x : r) + k;
+    return true;
+}
 #ifndef SPH_SORT_ITEMS
 #define SPH_SORT_ITEMS 8
 #endif

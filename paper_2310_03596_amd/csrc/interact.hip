@@ -201,16 +201,15 @@ __device__ inline int wave_max(int v)
 // contiguous range of the sorted array, and a wavefront whose targets span
 // two rows walks the neighbour rows of each in turn with the other lanes
 // idle.  For a pass over every target of a sorted array, one workgroup
-// lists (first target, count) for wavefronts that each take up to `chunk`
-// (64, or 32 for the two-lane targets of k_pairs_mx) targets of a single
-// row, rows in order (on the column workload, chunks of 64: 13,183 row walks
-// instead of 14,243).  plan holds at most ceil(n / chunk) + rows entries;
+// lists (first target, count) for wavefronts that each take up to 64
+// targets of a single row, rows in order (on the column workload: 13,183 row
+// walks instead of 14,243).  plan holds at most ceil(n / 64) + rows entries;
 // *nplan receives their number.  The staging kernel runs this as its first
 // workgroup, so the plan's latency hides behind the staging.
 constexpr int kPlanBlock = kBlock;
 constexpr int kPlanRows = 8;   // consecutive rows per thread in one chunk of the plan
 __device__ inline void wave_plan_block(const Grid &g, const uint32_t *__restrict__ start, uint2 *__restrict__ plan,
-                                       uint32_t *__restrict__ nplan, uint32_t chunk)
+                                       uint32_t *__restrict__ nplan)
 {
     __shared__ uint32_t wsum[kPlanBlock / kWave];
     const uint32_t nx = (uint32_t)g.nx, nrows = (uint32_t)g.ny * (uint32_t)g.nz;
@@ -229,7 +228,7 @@ __device__ inline void wave_plan_block(const Grid &g, const uint32_t *__restrict
         }
         uint32_t w = 0;
 #pragma unroll
-        for (int k = 0; k < kPlanRows; ++k) w += (bnd[k + 1] - bnd[k] + chunk - 1) / chunk;
+        for (int k = 0; k < kPlanRows; ++k) w += (bnd[k + 1] - bnd[k] + kWave - 1) / kWave;
         // exclusive scan of w over the block (wavefront scan, then wavefront totals)
         uint32_t inc = w;
 #pragma unroll
@@ -250,9 +249,9 @@ __device__ inline void wave_plan_block(const Grid &g, const uint32_t *__restrict
 #pragma unroll
         for (int k = 0; k < kPlanRows; ++k) {
             const uint32_t b = bnd[k], len = bnd[k + 1] - bnd[k];
-            for (uint32_t m = 0; m * chunk < len; ++m) {
-                const uint32_t left = len - m * chunk;
-                plan[q++] = make_uint2(b + m * chunk, left < chunk ? left : chunk);
+            for (uint32_t m = 0; m * (uint32_t)kWave < len; ++m) {
+                const uint32_t left = len - m * (uint32_t)kWave;
+                plan[q++] = make_uint2(b + m * (uint32_t)kWave, left < (uint32_t)kWave ? left : (uint32_t)kWave);
             }
         }
         carry += tot;
@@ -263,11 +262,11 @@ __device__ inline void wave_plan_block(const Grid &g, const uint32_t *__restrict
 // Packs the pair inputs of every source particle (see Stage).
 template <typename real, bool SOLID>
 __global__ __launch_bounds__(kBlock) void k_stage(Grid g, PV<real> s, Stage<real> st, const uint32_t *pstart,
-                                                  uint2 *plan, uint32_t *nplan, uint32_t chunk)
+                                                  uint2 *plan, uint32_t *nplan)
 {
     constexpr bool SPLIT = sizeof(real) == 4;
     if (plan && blockIdx.x == 0) {
-        wave_plan_block(g, pstart, plan, nplan, chunk);
+        wave_plan_block(g, pstart, plan, nplan);
         return;
     }
     uint32_t j = (blockIdx.x - (plan ? 1u : 0u)) * kBlock + threadIdx.x;
@@ -380,24 +379,30 @@ void k_pairs(Params P, Grid g, PV<real> tg, const uint32_t *__restrict__ tidx, c
     __shared__ Win win[kWaves][kMaxWin];
 
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
-    const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);   // neighbouring tiles share sources
+    uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);   // neighbouring tiles share sources
     bool valid;
     uint32_t i;
     if (plan) {
-        // row-aligned wavefronts (k_wave_plan): whole wavefronts beyond the
-        // plan leave
+        // row-aligned wavefronts (k_wave_plan), the plan's tiles shared evenly
+        // by the XCDs (the grid is sized for the plan's bound); whole
+        // wavefronts beyond the plan leave
+        const uint32_t np = *nplan;
+        if (!xcd_tile_active(blockIdx.x, (np + kWaves - 1) / kWaves, tile)) return;
         const uint32_t wid = tile * kWaves + wave;
-        if (wid >= *nplan) return;
+        if (wid >= np) return;
         const uint2 d = plan[wid];
         valid = (uint32_t)lane < d.y;
         i = valid ? d.x + (uint32_t)lane : 0u;
     } else {
-        const uint32_t t = tile * kPairBlock + tid;
         uint32_t nt = tg.n;
         if (tidx) {
+            // a target list's count is on the device and the grid is sized for
+            // the whole array: the list's tiles shared evenly by the XCDs
             uint32_t c = *ntdev;
             nt = c < nt ? c : nt;
+            if (!xcd_tile_active(blockIdx.x, (nt + kPairBlock - 1) / kPairBlock, tile)) return;
         }
+        const uint32_t t = tile * kPairBlock + tid;
         // whole wavefronts beyond the targets leave; partial ones keep idle lanes
         if (tile * kPairBlock + wave * kWave >= nt) return;
         valid = t < nt;
@@ -800,7 +805,7 @@ void k_pairs(Params P, Grid g, PV<real> tg, const uint32_t *__restrict__ tidx, c
 
 // The FORCE pass of a fluid over every target of a sorted array, with the
 // neighbour filter on the matrix cores.  A wavefront takes up to 32 targets
-// of one bucket row (the row-aligned plan cut into chunks of 32), two lanes
+// of one bucket row (one half of an entry of the row-aligned plan), two lanes
 // per target: lane t and lane t + 32.  For each of the 9 neighbour rows the
 // sources of the union of its targets' buckets are tested 32 at a time: the
 // shortlist value |q|^2 - 2 q.f of every (source, target) pair of a block is
@@ -853,9 +858,20 @@ void k_pairs_mx(Params P, Grid g, PV<real> tg, Stage<real> src, const uint32_t *
 
     const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
     const int tl = lane & (kMxTargets - 1), half = lane / kMxTargets;
-    const uint32_t wid = xcd_tile(blockIdx.x, gridDim.x) * kMxWaves + wave;
-    if (wid >= *nplan) return;   // whole wavefronts beyond the plan leave
-    const uint2 pd = plan[wid];
+    // wavefront w takes half w % 2 of the plan's entry w / 2 (up to 64
+    // targets of one row); wavefronts beyond the plan, or on the empty second
+    // half of a short entry, leave whole
+    // (the plan's tiles shared evenly by the XCDs: the grid is sized for the
+    // plan's bound)
+    const uint32_t np = *nplan;
+    uint32_t tile;
+    if (!xcd_tile_active(blockIdx.x, (2u * np + kMxWaves - 1) / kMxWaves, tile)) return;
+    const uint32_t wid = tile * kMxWaves + wave;
+    if (wid / 2u >= np) return;
+    const uint2 pe = plan[wid / 2u];
+    const uint32_t off = (wid & 1u) * (uint32_t)kMxTargets;
+    if (pe.y <= off) return;
+    const uint2 pd = make_uint2(pe.x + off, pe.y - off < (uint32_t)kMxTargets ? pe.y - off : (uint32_t)kMxTargets);
     const bool valid = (uint32_t)tl < pd.y;
     const uint32_t i = pd.x + (valid ? (uint32_t)tl : 0u);   // idle lanes shadow the first target
 
@@ -1233,28 +1249,27 @@ hipError_t go(const Params &P, const Grid &g, const sph_particles &tg, const uin
     // workloads' steps 4-7 % slower with it, so their passes keep 64
     // consecutive targets per wavefront.)
     // The FP64 form's fluid FORCE pass (and its census) over every target
-    // takes the matrix-core filter (k_pairs_mx, two lanes per target: chunks
-    // of 32).  Measured on the column: FP64 605 us against 651 with the VALU
+    // takes the matrix-core filter (k_pairs_mx: two lanes per target, two
+    // wavefronts per plan entry).  Measured on the column: FP64 605 us against 651 with the VALU
     // filter; FP32 361 against 353, so the FP32 form keeps the VALU filter.
     constexpr bool MX_PASS = !SOLID && (PASS == SPH_PASS_FORCE || PASS == kPassCensus) && sizeof(real) == 8 &&
                              SPH_PAIR_MX;
     const bool mx = MX_PASS && !census_of_gradient && self && !tidx;
-    const uint32_t chunk = mx ? (uint32_t)kMxTargets : (uint32_t)kWave;
     const uint64_t nrows = (uint64_t)g.ny * (uint64_t)g.nz;
-    const uint64_t pmax = div_up(tg.n, chunk) + nrows;
+    const uint64_t pmax = div_up(tg.n, kWave) + nrows;
     // (the workspace's key buffers hold 4 bytes for each of the sources->n
     // particles it was sized for)
     if (!SOLID && PASS != SPH_PASS_GRADIENT && PASS != kPassGradAdjoint && !census_of_gradient && self && !tidx &&
         pmax * sizeof(uint2) <= 4ull * sr.n) {
         plan = reinterpret_cast<uint2 *>(ws.keys[0]);
         nplan = ws.keys[1];
-        blocks = div_up(pmax, mx ? kMxWaves : kWaves);
+        blocks = mx ? div_up(2 * pmax, kMxWaves) : div_up(pmax, kWaves);   // k_pairs_mx: two wavefronts per entry
     }
     const bool use_mx = mx && plan;
     if (sr.n > 0) {
         // one more workgroup (the first) builds the wavefront plan
         k_stage<real, SOLID><<<div_up(sr.n, kBlock) + (plan ? 1 : 0), kBlock, 0, s>>>(g, view<real>(sr), st, sstart,
-                                                                                    plan, nplan, chunk);
+                                                                                    plan, nplan);
         if constexpr (ADJ) {
             const sph_rates none{};
             const RV<real> rs = view<real>(rsrc ? *rsrc : none);
