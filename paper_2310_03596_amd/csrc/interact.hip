@@ -1242,12 +1242,12 @@ hipError_t go(const Params &P, const Grid &g, const sph_particles &tg, const uin
     uint32_t blocks = div_up(tg.n, kPairBlock);
     uint2 *plan = nullptr;
     uint32_t *nplan = nullptr;
-    // A fluid pass over every target of a sorted array (targets = sources,
-    // whose bucket table is at hand) takes row-aligned wavefronts; the plan
-    // lives in the sort's key buffers, free during a pass, when it fits there.
-    // (Measured: the FP32 column's FORCE pass 5 % faster; the solid
-    // workloads' steps 4-7 % slower with it, so their passes keep 64
-    // consecutive targets per wavefront.)
+    // A pass over every target of a sorted array (targets = sources, whose
+    // bucket table is at hand) takes row-aligned wavefronts; the plan lives in
+    // the sort's key buffers, free during a pass, when it fits there.
+    // (Measured: the FP32 column's FORCE pass 5 % faster; with the plan's
+    // tiles shared evenly by the XCDs, the solid steps too: cylinder 4.87 ->
+    // 4.70 ms FP32, 8.68 -> 7.93 FP64; impact 8.46 -> 8.33, 14.73 -> 14.30.)
     // The FP64 form's fluid FORCE pass (and its census) over every target
     // takes the matrix-core filter (k_pairs_mx: two lanes per target, two
     // wavefronts per plan entry).  Measured on the column: FP64 605 us against 651 with the VALU
@@ -1259,8 +1259,7 @@ hipError_t go(const Params &P, const Grid &g, const sph_particles &tg, const uin
     const uint64_t pmax = div_up(tg.n, kWave) + nrows;
     // (the workspace's key buffers hold 4 bytes for each of the sources->n
     // particles it was sized for)
-    if (!SOLID && PASS != SPH_PASS_GRADIENT && PASS != kPassGradAdjoint && !census_of_gradient && self && !tidx &&
-        pmax * sizeof(uint2) <= 4ull * sr.n) {
+    if (self && !tidx && pmax * sizeof(uint2) <= 4ull * sr.n) {
         plan = reinterpret_cast<uint2 *>(ws.keys[0]);
         nplan = ws.keys[1];
         blocks = mx ? div_up(2 * pmax, kMxWaves) : div_up(pmax, kWaves);   // k_pairs_mx: two wavefronts per entry
