@@ -114,6 +114,16 @@ __device__ inline unsigned long long mix64(uint32_t id)
 #ifndef SPH_PAIR_MX
 #define SPH_PAIR_MX 1   // the FP64 fluid FORCE pass over every target filters on the matrix cores (k_pairs_mx)
 #endif
+// Wavefronts per SIMD of the solid FORCE pass: at 4 (FP32) and 3 (FP64) its
+// registers spilled (4 and 33); measured on the cylinder and the impact
+// (steps, ms): FP32 4.69 -> 4.53 and 8.30 -> 8.07 at 3, FP64 7.90 -> 7.46
+// and 14.27 -> 13.63 at 2.
+#ifndef SPH_PAIR_EU_SOLID_F32
+#define SPH_PAIR_EU_SOLID_F32 3
+#endif
+#ifndef SPH_PAIR_EU_SOLID_F64
+#define SPH_PAIR_EU_SOLID_F64 2
+#endif
 #ifndef SPH_PAIR_WAVES_PER_EU
 #define SPH_PAIR_WAVES_PER_EU 4
 #endif
@@ -125,8 +135,11 @@ __device__ inline unsigned long long mix64(uint32_t id)
 template <typename real, bool SOLID, int PASS>
 struct PairOccupancy {
     static constexpr bool ADJ = PASS == kPassAdjoint || PASS == kPassGradAdjoint;
-    static constexpr int fp32 = ADJ ? ((SOLID && PASS == kPassAdjoint) ? 2 : 3) : (SOLID ? 4 : SPH_PAIR_WAVES_PER_EU);
-    static constexpr int fp64 = ADJ ? 2 : 3;   // measured: FP64 passes run faster at 3 than at 4 (no spills)
+    static constexpr int fp32 = ADJ ? ((SOLID && PASS == kPassAdjoint) ? 2 : 3)
+                                    : (SOLID && PASS == SPH_PASS_FORCE ? SPH_PAIR_EU_SOLID_F32
+                                                                       : (SOLID ? 4 : SPH_PAIR_WAVES_PER_EU));
+    // measured: the FP64 fluid passes run faster at 3 than at 4 (no spills)
+    static constexpr int fp64 = ADJ ? 2 : (SOLID && PASS == SPH_PASS_FORCE ? SPH_PAIR_EU_SOLID_F64 : 3);
     static constexpr int value = sizeof(real) == 4 ? fp32 : fp64;
 };
 
