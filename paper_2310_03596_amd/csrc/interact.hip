@@ -118,6 +118,13 @@ __device__ inline unsigned long long mix64(uint32_t id)
 // registers spilled (4 and 33); measured on the cylinder and the impact
 // (steps, ms): FP32 4.69 -> 4.53 and 8.30 -> 8.07 at 3, FP64 7.90 -> 7.46
 // and 14.27 -> 13.63 at 2.
+// The FP64 solid FORCE reverse needs about 380 registers: at two wavefronts
+// per SIMD it spilled 244 to scratch, at one it keeps them (256 plus 120
+// accumulation registers); backward pass of a 64,000-particle block 12.6 ->
+// 8.6 ms.
+#ifndef SPH_PAIR_EU_SOLID_ADJ_F64
+#define SPH_PAIR_EU_SOLID_ADJ_F64 1
+#endif
 #ifndef SPH_PAIR_EU_SOLID_F32
 #define SPH_PAIR_EU_SOLID_F32 3
 #endif
@@ -139,7 +146,8 @@ struct PairOccupancy {
                                     : (SOLID && PASS == SPH_PASS_FORCE ? SPH_PAIR_EU_SOLID_F32
                                                                        : (SOLID ? 4 : SPH_PAIR_WAVES_PER_EU));
     // measured: the FP64 fluid passes run faster at 3 than at 4 (no spills)
-    static constexpr int fp64 = ADJ ? 2 : (SOLID && PASS == SPH_PASS_FORCE ? SPH_PAIR_EU_SOLID_F64 : 3);
+    static constexpr int fp64 = ADJ ? ((SOLID && PASS == kPassAdjoint) ? SPH_PAIR_EU_SOLID_ADJ_F64 : 2)
+                                    : (SOLID && PASS == SPH_PASS_FORCE ? SPH_PAIR_EU_SOLID_F64 : 3);
     static constexpr int value = sizeof(real) == 4 ? fp32 : fp64;
 };
 
